@@ -1,0 +1,367 @@
+/*
+ * hpa.h -- GPU PC-sample attribution on AMD Instinct MI355X (gfx950).
+ *
+ * Post-mortem core of GPU performance analysis as described in Zhou et al.,
+ * "Measurement and Analysis of GPU-accelerated Applications with HPCToolkit"
+ * (Parallel Computing 2021, arXiv 2109.06931):
+ *
+ *   1. map each sampled instruction address to its function, inlined code,
+ *      loop and source line through an address-to-structure interval map
+ *      (Section 5; Section 6.1 "Calling Context Expansion");
+ *   2. aggregate samples by (calling context, PC, stall reason): a raw metric
+ *      is the sum of the measured values (Section 4.2 sample record,
+ *      Section 4.5 raw metrics);
+ *   3. rebuild the approximate GPU calling context tree of each kernel
+ *      invocation by splitting every GPU function's cost over its call sites
+ *      in proportion to call-instruction samples, with recursion handled as
+ *      strongly connected components (Section 6.3, steps 1-4);
+ *   4. derive inclusive metrics and stall ratios such as the warp issue rate
+ *      W = (S - S_stall) / S (Section 6.1 "Statistic Generation", Section 7.1).
+ *
+ * Conventions for every call
+ * --------------------------
+ *  - Every call returns hpa_status: HPA_OK (0) or a negative error code.  On
+ *    error no output handle is created and out-parameters are left untouched;
+ *    hpa_last_error() returns a message for the calling thread.
+ *  - "host" pointers are CPU memory, borrowed for the duration of the call.
+ *    "device" pointers are GPU memory on the context's device, borrowed until
+ *    the given stream has executed the work the call enqueued.
+ *  - All device work is enqueued on the stream passed in.  A call whose output
+ *    size depends on the data synchronises that stream; each such call says
+ *    how often.
+ *  - Output handles own their device arrays (allocated through the context's
+ *    allocator) and are immutable; *_view_get returns their device pointers.
+ *    Release a handle with its *_free function; the handle must not be in use
+ *    by queued work when it is freed.
+ *  - A context (hpa_ctx) is used by one host thread at a time.  Handles may be
+ *    read from several threads.
+ *
+ * Readings of points the paper leaves open (applied throughout):
+ *  - a sample record without a weight counts once;
+ *  - stall reason 0 means "not stalled", reasons 1..15 are stalls;
+ *  - a PC outside every function is kept, under scope HPA_UNMAPPED, and
+ *    attributed to an <unknown> node of the calling context tree;
+ *  - overlapping functions: an address belongs to the containing function with
+ *    the largest start, then the smallest end, then the smallest id;
+ *  - inline and loop ranges form a laminar family, each inside the addresses
+ *    of one function; equal ranges nest function > inline > loop, and among
+ *    equal ranges of one kind the lower id is outer.
+ */
+#ifndef HPA_H
+#define HPA_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#include <hip/hip_runtime_api.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+  HPA_OK = 0,
+  HPA_E_INVAL = -1,       /* malformed argument or input value */
+  HPA_E_UNSORTED = -2,    /* prebuilt intervals not in ascending order */
+  HPA_E_OVERLAP = -3,     /* overlapping line ranges or prebuilt intervals */
+  HPA_E_NOT_LAMINAR = -4, /* crossing inline/loop ranges, or one outside a function */
+  HPA_E_NOMEM = -5,       /* the allocator returned NULL */
+  HPA_E_BUDGET = -6,      /* calling context tree larger than the caller's node budget */
+  HPA_E_DEVICE = -7,      /* a HIP runtime call failed */
+  HPA_E_UNSUPPORTED = -8  /* valid input outside what this build handles (message says what) */
+} hpa_status;
+
+#define HPA_UNMAPPED 0xFFFFFFFFu           /* no scope / no interval / no parent */
+#define HPA_NO_SITE 0xFFFFFFFFFFFFFFFFull  /* CCT node not entered through a call site */
+#define HPA_N_STALL 16                     /* stall reasons 0..15 */
+
+/* Thread-local message describing the last failure on this thread. */
+const char* hpa_last_error(void);
+
+/* ------------------------------------------------------------------------ */
+/* Context                                                                   */
+/* ------------------------------------------------------------------------ */
+
+/* Device-memory allocator.  alloc returns device memory usable on `stream`
+ * (NULL on failure -> HPA_E_NOMEM); free releases it in stream order.  When
+ * no allocator is given the library uses hipMallocAsync / hipFreeAsync on the
+ * device's default memory pool, whose release threshold it raises so that
+ * repeated calls reuse memory. */
+typedef struct {
+  void* (*alloc)(size_t bytes, hipStream_t stream, void* user);
+  void (*free)(void* ptr, hipStream_t stream, void* user);
+  void* user;
+} hpa_allocator;
+
+typedef struct hpa_ctx hpa_ctx;
+
+/* Create a context on HIP device `device`.  alloc may be NULL (default pool);
+ * the struct is copied.  Errors: HPA_E_INVAL (bad device or out == NULL),
+ * HPA_E_DEVICE. */
+hpa_status hpa_ctx_create(int device, const hpa_allocator* alloc, hpa_ctx** out);
+void hpa_ctx_destroy(hpa_ctx* ctx);
+
+/* ------------------------------------------------------------------------ */
+/* A1: structure map (Section 5; Section 6.1 calling-context expansion)      */
+/* ------------------------------------------------------------------------ */
+
+typedef enum { HPA_FUNC = 0, HPA_INLINE = 1, HPA_LOOP = 2 } hpa_scope_kind;
+
+/* One address range [start, end) of a scope.  Functions are relocated to
+ * unique addresses by the caller (Section 5); overlapping functions are split
+ * by the library.  A scope id may repeat over several ranges (a loop spread
+ * over several blocks); all ranges of one id share the kind and the parent. */
+typedef struct {
+  uint64_t start, end;
+  uint32_t id;   /* scope id; the scope table is indexed by id */
+  uint32_t kind; /* hpa_scope_kind */
+} hpa_scope;
+
+/* One source-line range [start, end).  Line ranges must not overlap; an
+ * address inside a function but in no line range gets file 0, line 0. */
+typedef struct {
+  uint64_t start, end;
+  uint32_t file, line;
+} hpa_line_range;
+
+/* Either scopes (+ optional lines), or prebuilt sorted disjoint intervals
+ * (iv_start/iv_end, n_iv > 0; interval i is then labelled scope i with no
+ * scope table).  All arrays are host memory. */
+typedef struct {
+  const hpa_scope* scopes;
+  uint64_t n_scopes;
+  const hpa_line_range* lines;
+  uint64_t n_lines;
+  const uint64_t* iv_start;
+  const uint64_t* iv_end;
+  uint64_t n_iv;
+  int learned; /* 1: also train the learned interval index (HPA_LOOKUP_LEARNED) */
+} hpa_structure_desc;
+
+typedef struct hpa_structure_map hpa_structure_map;
+
+/* Build the map: sorted, disjoint, maximally merged elementary intervals
+ * [start, end) labelled (innermost scope, file, line), and the scope table
+ * (parent, kind, owning function) indexed by scope id.  The host builds the
+ * intervals and uploads them on `stream` (synchronised once at the end).
+ * Errors: HPA_E_INVAL (start >= end, kind > 2, one id with two kinds),
+ * HPA_E_OVERLAP (overlapping line ranges or prebuilt intervals),
+ * HPA_E_UNSORTED (prebuilt intervals out of order), HPA_E_NOT_LAMINAR,
+ * HPA_E_NOMEM, HPA_E_DEVICE. */
+hpa_status hpa_build_structure_map(hpa_ctx* ctx, const hpa_structure_desc* desc, hipStream_t stream,
+                                   hpa_structure_map** out);
+
+/* Device arrays of a map (SoA; n_intervals and n_scope_ids entries). */
+typedef struct {
+  uint64_t n_intervals;
+  uint32_t n_scope_ids;
+  const uint64_t* start;
+  const uint64_t* end;
+  const uint32_t* scope;
+  const uint32_t* file;
+  const uint32_t* line;
+  const uint32_t* parent; /* scope table: enclosing scope or HPA_UNMAPPED for functions */
+  const uint8_t* kind;    /* hpa_scope_kind, 0xFF for unused ids */
+  const uint32_t* func;   /* owning function scope id, HPA_UNMAPPED for unused ids */
+} hpa_structure_map_view;
+
+hpa_status hpa_structure_map_view_get(const hpa_structure_map* map, hpa_structure_map_view* out);
+void hpa_structure_map_free(hpa_structure_map* map);
+
+/* ------------------------------------------------------------------------ */
+/* A3: address -> interval lookup (Section 6.1 calling-context expansion)    */
+/* ------------------------------------------------------------------------ */
+
+#define HPA_LOOKUP_PLAIN 0   /* binary search over interval starts */
+#define HPA_LOOKUP_LEARNED 1 /* learned index + bounded search, verified (map built with learned=1) */
+
+/* d_out[i] = the interval i with start[i] <= d_pc[i] < end[i], else
+ * HPA_UNMAPPED.  d_pc (n x u64) and d_out (n x u32) are device memory.  Both
+ * modes return identical results.  Asynchronous (no synchronisation).
+ * Errors: HPA_E_INVAL (NULL pointers with n > 0, unknown mode),
+ * HPA_E_UNSUPPORTED (learned mode on a map built without it). */
+hpa_status hpa_lookup_intervals(hpa_ctx* ctx, const hpa_structure_map* map, const uint64_t* d_pc, uint64_t n,
+                                uint32_t* d_out, int mode, hipStream_t stream);
+
+/* ------------------------------------------------------------------------ */
+/* A2-A4: attribution (Section 4.2 sample record; Section 4.5 raw metrics)   */
+/* ------------------------------------------------------------------------ */
+
+/* PC samples, structure of arrays, device memory: pc[n] instruction address,
+ * ctx[n] calling-context id (< n_ctx; the kernel invocation's placeholder),
+ * stall[n] stall reason (< 16), weight[n] observation count or NULL (each
+ * record then counts once). */
+typedef struct {
+  const uint64_t* pc;
+  const uint32_t* ctx;
+  const uint8_t* stall;
+  const uint32_t* weight;
+  uint64_t n;
+  uint32_t n_ctx;
+} hpa_samples;
+
+typedef struct hpa_attribution hpa_attribution;
+
+/* count[(ctx, pc, stall)] = sum of weights.  Output keys are unique and sorted
+ * ascending by (ctx, pc, stall); scope is the innermost scope of pc (or
+ * HPA_UNMAPPED); ctx_offsets (n_ctx + 1) is the CSR index of each context's
+ * keys.  Synchronises `stream` twice (once to size the work, once to learn the
+ * number of keys).  Errors: HPA_E_INVAL (a stall >= 16 or ctx >= n_ctx,
+ * NULL arrays), HPA_E_UNSUPPORTED (the PCs of one context span more than
+ * 2^56 bytes after removing common trailing zero bits), HPA_E_NOMEM,
+ * HPA_E_DEVICE. */
+hpa_status hpa_attribute(hpa_ctx* ctx, const hpa_structure_map* map, const hpa_samples* samples,
+                         hipStream_t stream, hpa_attribution** out);
+
+typedef struct {
+  uint64_t n_keys;
+  uint32_t n_ctx;
+  const uint32_t* ctx;
+  const uint64_t* pc;
+  const uint8_t* stall;
+  const uint64_t* count;
+  const uint32_t* scope;
+  const uint64_t* ctx_offsets;
+} hpa_attribution_view;
+
+hpa_status hpa_attribution_view_get(const hpa_attribution* a, hpa_attribution_view* out);
+void hpa_attribution_free(hpa_attribution* a);
+
+/* ------------------------------------------------------------------------ */
+/* A5: GPU calling context tree (Section 6.3)                                */
+/* ------------------------------------------------------------------------ */
+
+/* Static call graph from function symbols and call instructions (Section
+ * 6.3 step 1), host memory.  Node ids are function scope ids of the map and
+ * n_funcs must equal its number of scope ids.  One entry per call
+ * instruction: site_pc must lie in site_caller's addresses and be unique. */
+typedef struct {
+  uint32_t n_funcs;
+  uint64_t n_sites;
+  const uint64_t* site_pc;
+  const uint32_t* site_caller;
+  const uint32_t* site_callee;
+} hpa_callgraph;
+
+/* Host calling contexts, host memory: parent[c] (HPA_UNMAPPED for a root)
+ * and kernel_entry[c], the GPU kernel function launched at placeholder c, or
+ * -1.  A context with an entry uses the call graph restricted to what the
+ * entry reaches; one without uses the whole graph with every function that
+ * no other function calls as a root. */
+typedef struct {
+  uint32_t n;
+  const uint32_t* parent;
+  const int32_t* kernel_entry;
+} hpa_context_table;
+
+typedef struct hpa_callgraph_plan hpa_callgraph_plan;
+
+/* Validate the call graph and context table against the map, find the SCCs
+ * (Tarjan, Section 6.3 step 3; ids ranked by smallest member), build the
+ * condensed graph and upload it.  Host work plus one synchronisation; reuse
+ * the plan for every profile that shares the graph.  Errors: HPA_E_INVAL
+ * (n_funcs mismatch, a caller/callee/entry that is not a function, duplicate
+ * site_pc, a site outside its caller, a parent index out of range or a cycle
+ * in the context table), HPA_E_NOMEM, HPA_E_DEVICE. */
+hpa_status hpa_prepare_callgraph(hpa_ctx* ctx, const hpa_structure_map* map, const hpa_callgraph* graph,
+                                 const hpa_context_table* contexts, hipStream_t stream,
+                                 hpa_callgraph_plan** out);
+void hpa_callgraph_plan_free(hpa_callgraph_plan* plan);
+
+typedef struct {
+  int sample_based;        /* 1: edge weights are call-instruction samples, apply step 2 (required) */
+  uint64_t max_cct_nodes;  /* 0: no limit; else HPA_E_BUDGET if the tree needs more nodes */
+  uint64_t* required_nodes; /* host, may be NULL: receives the node count on HPA_OK and HPA_E_BUDGET */
+} hpa_apportion_opts;
+
+typedef struct hpa_gpu_cct hpa_gpu_cct;
+
+/* Per context: self cost per function and stall; call-site weights (the call
+ * instruction's samples); step 2 as the least fixpoint of its rule; SCC
+ * condensation with the step-2 rule applied once more on the condensed graph;
+ * unfolding from the roots into a tree whose nodes are call paths, children
+ * ordered by call-site PC, with phi(path) the product of w(e) / W(callee)
+ * along the path and exclusive cost phi * self (Section 6.3 step 4).  Paths
+ * that reach no sample are pruned by an integer test.  Samples outside the
+ * entry's reach form an <unreachable> node, unmapped PCs an <unknown> node.
+ * Synchronises `stream` twice.  Errors: HPA_E_INVAL (attribution from another
+ * map or context count), HPA_E_BUDGET, HPA_E_UNSUPPORTED (sample_based == 0),
+ * HPA_E_NOMEM, HPA_E_DEVICE. */
+hpa_status hpa_apportion_callpaths(hpa_ctx* ctx, const hpa_callgraph_plan* plan, const hpa_attribution* attr,
+                                   const hpa_apportion_opts* opts, hipStream_t stream, hpa_gpu_cct** out);
+
+/* Node kinds */
+#define HPA_NODE_PATH 0
+#define HPA_NODE_UNREACHABLE 1
+#define HPA_NODE_UNKNOWN 2
+
+/* Device arrays of a GPU CCT.  Nodes of context c are
+ * [node_offsets[c], node_offsets[c+1]) in DFS preorder; parent is an index
+ * local to the context (HPA_UNMAPPED for a child of the placeholder); node is
+ * the condensed call-graph node (HPA_UNMAPPED for the special nodes); site is
+ * the call-site PC of the edge into the node; excl holds 16 stall columns per
+ * node.  w_offsets/w_site/w_val list, per context, the final positive weight
+ * of every call edge between condensed nodes, by call-site PC. */
+typedef struct {
+  uint64_t n_nodes;
+  uint32_t n_ctx;
+  uint32_t n_funcs;
+  const uint32_t* scc;
+  const uint64_t* node_offsets;
+  const uint32_t* parent;
+  const uint32_t* node;
+  const uint64_t* site;
+  const uint8_t* kind;
+  const double* phi;
+  const double* excl;
+  uint64_t n_weights;
+  const uint64_t* w_offsets;
+  const uint64_t* w_site;
+  const uint64_t* w_val;
+} hpa_gpu_cct_view;
+
+hpa_status hpa_gpu_cct_view_get(const hpa_gpu_cct* t, hpa_gpu_cct_view* out);
+void hpa_gpu_cct_free(hpa_gpu_cct* t);
+
+/* ------------------------------------------------------------------------ */
+/* A6: derived metrics (Section 6.1 statistic generation; Section 7.1)       */
+/* ------------------------------------------------------------------------ */
+
+typedef struct hpa_metrics hpa_metrics;
+
+/* Inclusive values up three trees:
+ *  - GPU CCT (FP64): incl(p,s) = excl(p,s) + children's incl in child order;
+ *    S = sum over s, W = (S - S_stall) / S with S_stall over reasons 1..15
+ *    (0 when S = 0);
+ *  - host calling-context tree (integer): per context, the samples of its
+ *    subtree per stall reason, and its W;
+ *  - static scope tree per context (integer): for each scope on the ancestor
+ *    chain of a sampled scope, the samples of the scope and everything nested
+ *    in it; CSR by context, scopes ascending (HPA_UNMAPPED last).
+ * Synchronises `stream` once.  Errors: HPA_E_INVAL (inputs from different
+ * plans or attributions), HPA_E_NOMEM, HPA_E_DEVICE. */
+hpa_status hpa_derive_metrics(hpa_ctx* ctx, const hpa_callgraph_plan* plan, const hpa_attribution* attr,
+                              const hpa_gpu_cct* cct, hipStream_t stream, hpa_metrics** out);
+
+typedef struct {
+  uint64_t n_nodes;
+  uint32_t n_ctx;
+  const double* incl; /* n_nodes x 16 */
+  const double* S;    /* n_nodes */
+  const double* W;    /* n_nodes */
+  const uint64_t* host_incl; /* n_ctx x 16 */
+  const double* host_W;      /* n_ctx */
+  uint64_t n_scope_rows;
+  const uint64_t* sc_offsets; /* n_ctx + 1 */
+  const uint32_t* sc_scope;
+  const uint64_t* sc_val; /* n_scope_rows x 16 */
+} hpa_metrics_view;
+
+hpa_status hpa_metrics_view_get(const hpa_metrics* m, hpa_metrics_view* out);
+void hpa_metrics_free(hpa_metrics* m);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* HPA_H */

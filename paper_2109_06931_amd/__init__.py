@@ -1,0 +1,418 @@
+"""Python binding of libhpa (GPU PC-sample attribution on MI355X).
+
+Argument marshalling only: every step runs in the library's HIP kernels.
+PyTorch supplies device memory (inputs as CUDA tensors) and the stream
+(`torch.cuda.current_stream()` unless one is given).  Names follow the C ABI
+in include/hpa.h.  The library must be built (`paper_2109_06931_amd.build`);
+importing this module on a machine without it raises immediately.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libhpa.so")
+
+OK, E_INVAL, E_UNSORTED, E_OVERLAP, E_NOT_LAMINAR, E_NOMEM, E_BUDGET, E_DEVICE, E_UNSUPPORTED = (
+    0, -1, -2, -3, -4, -5, -6, -7, -8)
+UNMAPPED = 0xFFFFFFFF
+NO_SITE = 0xFFFFFFFFFFFFFFFF
+N_STALL = 16
+LOOKUP_PLAIN, LOOKUP_LEARNED = 0, 1
+NODE_PATH, NODE_UNREACHABLE, NODE_UNKNOWN = 0, 1, 2
+
+SCOPE_DTYPE = np.dtype([("start", "<u8"), ("end", "<u8"), ("id", "<u4"), ("kind", "<u4")])
+LINE_DTYPE = np.dtype([("start", "<u8"), ("end", "<u8"), ("file", "<u4"), ("line", "<u4")])
+
+
+class HpaError(RuntimeError):
+    def __init__(self, code: int, what: str, msg: str):
+        super().__init__(f"{what}: status {code}: {msg}")
+        self.code = code
+
+
+# ---------------------------------------------------------------------------
+# ctypes declarations
+# ---------------------------------------------------------------------------
+P = C.c_void_p
+U64, U32, I32, I = C.c_uint64, C.c_uint32, C.c_int32, C.c_int
+
+
+class _StructureDesc(C.Structure):
+    _fields_ = [("scopes", P), ("n_scopes", U64), ("lines", P), ("n_lines", U64), ("iv_start", P),
+                ("iv_end", P), ("n_iv", U64), ("learned", I)]
+
+
+class _MapView(C.Structure):
+    _fields_ = [("n_intervals", U64), ("n_scope_ids", U32), ("start", P), ("end", P), ("scope", P),
+                ("file", P), ("line", P), ("parent", P), ("kind", P), ("func", P)]
+
+
+class _Samples(C.Structure):
+    _fields_ = [("pc", P), ("ctx", P), ("stall", P), ("weight", P), ("n", U64), ("n_ctx", U32)]
+
+
+class _AttrView(C.Structure):
+    _fields_ = [("n_keys", U64), ("n_ctx", U32), ("ctx", P), ("pc", P), ("stall", P), ("count", P),
+                ("scope", P), ("ctx_offsets", P)]
+
+
+class _CallGraph(C.Structure):
+    _fields_ = [("n_funcs", U32), ("n_sites", U64), ("site_pc", P), ("site_caller", P), ("site_callee", P)]
+
+
+class _ContextTable(C.Structure):
+    _fields_ = [("n", U32), ("parent", P), ("kernel_entry", P)]
+
+
+class _ApportionOpts(C.Structure):
+    _fields_ = [("sample_based", I), ("max_cct_nodes", U64), ("required_nodes", P)]
+
+
+class _CctView(C.Structure):
+    _fields_ = [("n_nodes", U64), ("n_ctx", U32), ("n_funcs", U32), ("scc", P), ("node_offsets", P),
+                ("parent", P), ("node", P), ("site", P), ("kind", P), ("phi", P), ("excl", P),
+                ("n_weights", U64), ("w_offsets", P), ("w_site", P), ("w_val", P)]
+
+
+class _MetricsView(C.Structure):
+    _fields_ = [("n_nodes", U64), ("n_ctx", U32), ("incl", P), ("S", P), ("W", P), ("host_incl", P),
+                ("host_W", P), ("n_scope_rows", U64), ("sc_offsets", P), ("sc_scope", P), ("sc_val", P)]
+
+
+_lib = None
+
+
+def lib():
+    """Load libhpa.so (raises if it has not been built)."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise RuntimeError(f"libhpa.so is not built at {LIB_PATH}; run paper_2109_06931_amd/build.py")
+        L = C.CDLL(LIB_PATH)
+        PP = C.POINTER(C.c_void_p)
+        L.hpa_last_error.restype = C.c_char_p
+        L.hpa_ctx_create.argtypes = [I, P, PP]
+        L.hpa_ctx_destroy.argtypes = [P]
+        L.hpa_ctx_destroy.restype = None
+        L.hpa_build_structure_map.argtypes = [P, C.POINTER(_StructureDesc), P, PP]
+        L.hpa_structure_map_view_get.argtypes = [P, C.POINTER(_MapView)]
+        L.hpa_structure_map_free.argtypes = [P]
+        L.hpa_structure_map_free.restype = None
+        L.hpa_lookup_intervals.argtypes = [P, P, P, U64, P, I, P]
+        L.hpa_attribute.argtypes = [P, P, C.POINTER(_Samples), P, PP]
+        L.hpa_attribution_view_get.argtypes = [P, C.POINTER(_AttrView)]
+        L.hpa_attribution_free.argtypes = [P]
+        L.hpa_attribution_free.restype = None
+        if hasattr(L, "hpa_prepare_callgraph"):
+            L.hpa_prepare_callgraph.argtypes = [P, P, C.POINTER(_CallGraph), C.POINTER(_ContextTable), P, PP]
+            L.hpa_callgraph_plan_free.argtypes = [P]
+            L.hpa_callgraph_plan_free.restype = None
+            L.hpa_apportion_callpaths.argtypes = [P, P, P, C.POINTER(_ApportionOpts), P, PP]
+            L.hpa_gpu_cct_view_get.argtypes = [P, C.POINTER(_CctView)]
+            L.hpa_gpu_cct_free.argtypes = [P]
+            L.hpa_gpu_cct_free.restype = None
+            L.hpa_derive_metrics.argtypes = [P, P, P, P, P, PP]
+            L.hpa_metrics_view_get.argtypes = [P, C.POINTER(_MetricsView)]
+            L.hpa_metrics_free.argtypes = [P]
+            L.hpa_metrics_free.restype = None
+        _lib = L
+    return _lib
+
+
+def _check(rc: int, what: str):
+    if rc != OK:
+        raise HpaError(rc, what, lib().hpa_last_error().decode(errors="replace"))
+
+
+def _stream(stream):
+    import torch
+    s = torch.cuda.current_stream() if stream is None else stream
+    return s.cuda_stream if hasattr(s, "cuda_stream") else int(s)
+
+
+def _ptr(t):
+    if t is None:
+        return None
+    return C.c_void_p(t.data_ptr())
+
+
+def _np(a, dt):
+    return np.ascontiguousarray(a, dtype=dt)
+
+
+# ---------------------------------------------------------------------------
+# device views -> torch tensors
+# ---------------------------------------------------------------------------
+_TYPESTR = {np.dtype(np.uint8): "|u1", np.dtype(np.uint32): "<u4", np.dtype(np.int32): "<i4",
+            np.dtype(np.uint64): "<u8", np.dtype(np.float64): "<f8"}
+_hip = None
+
+
+def _hip_memcpy_d2d(dst: int, src: int, nbytes: int):
+    global _hip
+    if _hip is None:
+        _hip = C.CDLL("libamdhip64.so")
+        _hip.hipMemcpy.argtypes = [P, P, C.c_size_t, I]
+    rc = _hip.hipMemcpy(C.c_void_p(dst), C.c_void_p(src), nbytes, 3)  # device to device
+    if rc != 0:
+        raise RuntimeError(f"hipMemcpy failed ({rc})")
+
+
+class _DevArray:
+    def __init__(self, ptr, shape, dtype):
+        self.__cuda_array_interface__ = {"shape": tuple(shape), "typestr": _TYPESTR[np.dtype(dtype)],
+                                         "data": (int(ptr or 0), False), "version": 3, "strides": None}
+
+
+def device_view(ptr, shape, dtype, owner=None):
+    """A torch tensor over library-owned device memory (copied if torch cannot alias it)."""
+    import torch
+    shape = tuple(int(x) for x in shape)
+    n = int(np.prod(shape)) if shape else 1
+    tdt = {np.dtype(np.uint8): torch.uint8, np.dtype(np.uint32): torch.uint32, np.dtype(np.int32): torch.int32,
+           np.dtype(np.uint64): torch.uint64, np.dtype(np.float64): torch.float64}[np.dtype(dtype)]
+    if n == 0 or not ptr:
+        return torch.empty(shape, dtype=tdt, device="cuda")
+    try:
+        t = torch.as_tensor(_DevArray(ptr, shape, dtype), device="cuda")
+        if t.dtype != tdt:
+            t = t.view(tdt)
+        t._hpa_owner = owner  # keep the handle alive
+        return t
+    except Exception:
+        t = torch.empty(shape, dtype=tdt, device="cuda")
+        torch.cuda.synchronize()
+        _hip_memcpy_d2d(t.data_ptr(), int(ptr), n * np.dtype(dtype).itemsize)
+        return t
+
+
+# ---------------------------------------------------------------------------
+# API
+# ---------------------------------------------------------------------------
+class Context:
+    """hpa_ctx on one device (default allocator: the device's stream-ordered pool)."""
+
+    def __init__(self, device: int = 0):
+        self.h = C.c_void_p()
+        _check(lib().hpa_ctx_create(device, None, C.byref(self.h)), "hpa_ctx_create")
+        self.device = device
+
+    def __del__(self):
+        if getattr(self, "h", None) and _lib is not None:
+            _lib.hpa_ctx_destroy(self.h)
+            self.h = None
+
+
+class StructureMap:
+    def __init__(self, ctx: Context, h):
+        self.ctx, self.h = ctx, h
+        v = _MapView()
+        _check(lib().hpa_structure_map_view_get(h, C.byref(v)), "hpa_structure_map_view_get")
+        self.n_intervals, self.n_scope_ids = v.n_intervals, v.n_scope_ids
+        self._v = v
+
+    def tensors(self):
+        v, m, k = self._v, self.n_intervals, self.n_scope_ids
+        return dict(start=device_view(v.start, (m,), np.uint64, self), end=device_view(v.end, (m,), np.uint64, self),
+                    scope=device_view(v.scope, (m,), np.uint32, self), file=device_view(v.file, (m,), np.uint32, self),
+                    line=device_view(v.line, (m,), np.uint32, self), parent=device_view(v.parent, (k,), np.uint32, self),
+                    kind=device_view(v.kind, (k,), np.uint8, self), func=device_view(v.func, (k,), np.uint32, self))
+
+    def __del__(self):
+        if getattr(self, "h", None) and _lib is not None:
+            _lib.hpa_structure_map_free(self.h)
+            self.h = None
+
+
+def build_structure_map(ctx: Context, scope_start=None, scope_end=None, scope_id=None, scope_kind=None,
+                        line_start=None, line_end=None, line_file=None, line_line=None,
+                        iv_start=None, iv_end=None, learned: bool = False, stream=None) -> StructureMap:
+    """hpa_build_structure_map from host (numpy) arrays."""
+    d = _StructureDesc()
+    keep = []
+    if iv_start is not None:
+        s, e = _np(iv_start, np.uint64), _np(iv_end, np.uint64)
+        keep += [s, e]
+        d.iv_start, d.iv_end, d.n_iv = s.ctypes.data, e.ctypes.data, len(s)
+    else:
+        sc = np.empty(len(scope_start), SCOPE_DTYPE)
+        sc["start"], sc["end"], sc["id"], sc["kind"] = scope_start, scope_end, scope_id, scope_kind
+        keep.append(sc)
+        d.scopes, d.n_scopes = sc.ctypes.data if len(sc) else None, len(sc)
+        if line_start is not None and len(line_start):
+            ln = np.empty(len(line_start), LINE_DTYPE)
+            ln["start"], ln["end"], ln["file"], ln["line"] = line_start, line_end, line_file, line_line
+            keep.append(ln)
+            d.lines, d.n_lines = ln.ctypes.data, len(ln)
+    d.learned = 1 if learned else 0
+    h = C.c_void_p()
+    _check(lib().hpa_build_structure_map(ctx.h, C.byref(d), C.c_void_p(_stream(stream)), C.byref(h)),
+           "hpa_build_structure_map")
+    return StructureMap(ctx, h)
+
+
+def build_structure_map_workload(ctx: Context, w, **kw) -> StructureMap:
+    return build_structure_map(ctx, w.scope_start, w.scope_end, w.scope_id, w.scope_kind, w.line_start, w.line_end,
+                               w.line_file, w.line_line, **kw)
+
+
+def lookup_intervals(ctx: Context, m: StructureMap, pc, out, mode: int = LOOKUP_PLAIN, stream=None):
+    """hpa_lookup_intervals on CUDA tensors pc (uint64) -> out (uint32)."""
+    _check(lib().hpa_lookup_intervals(ctx.h, m.h, _ptr(pc), pc.numel(), _ptr(out), mode,
+                                      C.c_void_p(_stream(stream))), "hpa_lookup_intervals")
+    return out
+
+
+class Attribution:
+    def __init__(self, ctx, m, h):
+        self.ctx, self.map, self.h = ctx, m, h
+        v = _AttrView()
+        _check(lib().hpa_attribution_view_get(h, C.byref(v)), "hpa_attribution_view_get")
+        self.n_keys, self.n_ctx, self._v = v.n_keys, v.n_ctx, v
+
+    def tensors(self):
+        v, u = self._v, self.n_keys
+        return dict(ctx=device_view(v.ctx, (u,), np.uint32, self), pc=device_view(v.pc, (u,), np.uint64, self),
+                    stall=device_view(v.stall, (u,), np.uint8, self),
+                    count=device_view(v.count, (u,), np.uint64, self),
+                    scope=device_view(v.scope, (u,), np.uint32, self),
+                    ctx_offsets=device_view(v.ctx_offsets, (self.n_ctx + 1,), np.uint64, self))
+
+    def numpy(self):
+        return {k: t.cpu().numpy() for k, t in self.tensors().items()}
+
+    def __del__(self):
+        if getattr(self, "h", None) and _lib is not None:
+            _lib.hpa_attribution_free(self.h)
+            self.h = None
+
+
+def attribute(ctx: Context, m: StructureMap, pc, ctx_ids, stall, weight=None, n_ctx: int = None,
+              stream=None) -> Attribution:
+    """hpa_attribute on CUDA tensors (uint64 pc, uint32/int32 ctx, uint8 stall, optional uint32 weight)."""
+    s = _Samples()
+    s.pc, s.ctx, s.stall, s.weight = _ptr(pc), _ptr(ctx_ids), _ptr(stall), _ptr(weight)
+    s.n, s.n_ctx = pc.numel(), int(n_ctx)
+    h = C.c_void_p()
+    _check(lib().hpa_attribute(ctx.h, m.h, C.byref(s), C.c_void_p(_stream(stream)), C.byref(h)), "hpa_attribute")
+    return Attribution(ctx, m, h)
+
+
+class CallgraphPlan:
+    def __init__(self, ctx, m, h, n_ctx):
+        self.ctx, self.map, self.h, self.n_ctx = ctx, m, h, n_ctx
+
+    def __del__(self):
+        if getattr(self, "h", None) and _lib is not None:
+            _lib.hpa_callgraph_plan_free(self.h)
+            self.h = None
+
+
+def prepare_callgraph(ctx: Context, m: StructureMap, n_funcs, site_pc, site_caller, site_callee, ctx_parent,
+                      ctx_entry, stream=None) -> CallgraphPlan:
+    sp, sc, se = _np(site_pc, np.uint64), _np(site_caller, np.uint32), _np(site_callee, np.uint32)
+    cp, ce = _np(ctx_parent, np.uint32), _np(ctx_entry, np.int32)
+    g = _CallGraph(int(n_funcs), len(sp), sp.ctypes.data if len(sp) else None, sc.ctypes.data if len(sc) else None,
+                   se.ctypes.data if len(se) else None)
+    t = _ContextTable(len(cp), cp.ctypes.data, ce.ctypes.data)
+    h = C.c_void_p()
+    _check(lib().hpa_prepare_callgraph(ctx.h, m.h, C.byref(g), C.byref(t), C.c_void_p(_stream(stream)), C.byref(h)),
+           "hpa_prepare_callgraph")
+    return CallgraphPlan(ctx, m, h, len(cp))
+
+
+def prepare_callgraph_workload(ctx: Context, m: StructureMap, w, **kw) -> CallgraphPlan:
+    return prepare_callgraph(ctx, m, w.n_scope_ids, w.site_pc, w.site_caller, w.site_callee, w.ctx_parent,
+                             w.ctx_entry, **kw)
+
+
+class GpuCct:
+    def __init__(self, ctx, plan, attr, h):
+        self.ctx, self.plan, self.attr, self.h = ctx, plan, attr, h
+        v = _CctView()
+        _check(lib().hpa_gpu_cct_view_get(h, C.byref(v)), "hpa_gpu_cct_view_get")
+        self._v = v
+        self.n_nodes, self.n_ctx, self.n_funcs, self.n_weights = v.n_nodes, v.n_ctx, v.n_funcs, v.n_weights
+
+    def tensors(self):
+        v, n, c = self._v, self.n_nodes, self.n_ctx
+        return dict(scc=device_view(v.scc, (self.n_funcs,), np.uint32, self),
+                    node_offsets=device_view(v.node_offsets, (c + 1,), np.uint64, self),
+                    parent=device_view(v.parent, (n,), np.uint32, self), node=device_view(v.node, (n,), np.uint32, self),
+                    site=device_view(v.site, (n,), np.uint64, self), kind=device_view(v.kind, (n,), np.uint8, self),
+                    phi=device_view(v.phi, (n,), np.float64, self),
+                    excl=device_view(v.excl, (n, N_STALL), np.float64, self),
+                    w_offsets=device_view(v.w_offsets, (c + 1,), np.uint64, self),
+                    w_site=device_view(v.w_site, (self.n_weights,), np.uint64, self),
+                    w_val=device_view(v.w_val, (self.n_weights,), np.uint64, self))
+
+    def numpy(self):
+        return {k: t.cpu().numpy() for k, t in self.tensors().items()}
+
+    def __del__(self):
+        if getattr(self, "h", None) and _lib is not None:
+            _lib.hpa_gpu_cct_free(self.h)
+            self.h = None
+
+
+def apportion_callpaths(ctx: Context, plan: CallgraphPlan, attr: Attribution, sample_based: int = 1,
+                        max_cct_nodes: int = 0, stream=None) -> GpuCct:
+    req = C.c_uint64(0)
+    o = _ApportionOpts(int(sample_based), int(max_cct_nodes), C.cast(C.byref(req), C.c_void_p))
+    h = C.c_void_p()
+    rc = lib().hpa_apportion_callpaths(ctx.h, plan.h, attr.h, C.byref(o), C.c_void_p(_stream(stream)), C.byref(h))
+    if rc != OK:
+        err = HpaError(rc, "hpa_apportion_callpaths", lib().hpa_last_error().decode(errors="replace"))
+        err.required = req.value
+        raise err
+    t = GpuCct(ctx, plan, attr, h)
+    t.required = req.value
+    return t
+
+
+class Metrics:
+    def __init__(self, ctx, cct, h):
+        self.ctx, self.cct, self.h = ctx, cct, h
+        v = _MetricsView()
+        _check(lib().hpa_metrics_view_get(h, C.byref(v)), "hpa_metrics_view_get")
+        self._v = v
+        self.n_nodes, self.n_ctx, self.n_scope_rows = v.n_nodes, v.n_ctx, v.n_scope_rows
+
+    def tensors(self):
+        v, n, c, r = self._v, self.n_nodes, self.n_ctx, self.n_scope_rows
+        return dict(incl=device_view(v.incl, (n, N_STALL), np.float64, self),
+                    S=device_view(v.S, (n,), np.float64, self), W=device_view(v.W, (n,), np.float64, self),
+                    host_incl=device_view(v.host_incl, (c, N_STALL), np.uint64, self),
+                    host_W=device_view(v.host_W, (c,), np.float64, self),
+                    sc_offsets=device_view(v.sc_offsets, (c + 1,), np.uint64, self),
+                    sc_scope=device_view(v.sc_scope, (r,), np.uint32, self),
+                    sc_val=device_view(v.sc_val, (r, N_STALL), np.uint64, self))
+
+    def numpy(self):
+        return {k: t.cpu().numpy() for k, t in self.tensors().items()}
+
+    def __del__(self):
+        if getattr(self, "h", None) and _lib is not None:
+            _lib.hpa_metrics_free(self.h)
+            self.h = None
+
+
+def derive_metrics(ctx: Context, plan: CallgraphPlan, attr: Attribution, cct: GpuCct, stream=None) -> Metrics:
+    h = C.c_void_p()
+    _check(lib().hpa_derive_metrics(ctx.h, plan.h, attr.h, cct.h, C.c_void_p(_stream(stream)), C.byref(h)),
+           "hpa_derive_metrics")
+    return Metrics(ctx, cct, h)
+
+
+def samples_to_device(w, device="cuda"):
+    """Copy a workload's sample arrays into CUDA tensors (uint64/uint32/uint8)."""
+    import torch
+    pc = torch.from_numpy(w.pc.view(np.int64)).to(device).view(torch.uint64)
+    cx = torch.from_numpy(w.ctx.view(np.int32)).to(device).view(torch.uint32)
+    st = torch.from_numpy(w.stall).to(device)
+    wt = None if w.weight is None else torch.from_numpy(w.weight.view(np.int32)).to(device).view(torch.uint32)
+    return pc, cx, st, wt

@@ -1,0 +1,1091 @@
+// A2-A4: stream PC samples once, form (context, pc, stall) keys and aggregate
+// them into sorted unique keys with counts (Section 4.2 sample record; Section
+// 4.5: a raw metric is the sum of measured values), then label each key's pc
+// with its innermost scope (Section 6.1 calling-context expansion).
+//
+// Samples arrive per kernel invocation, so the context id is constant over long
+// runs of the stream (Section 4.2: a buffer of PC samples belongs to one kernel
+// launch and its placeholder).  The pipeline uses that:
+//
+//   scan_ctx    read ctx[] once (4 B/sample): run boundaries, per-context
+//               sample and run counts (one 64-bit atomic per run), run list.
+//   plan        one workgroup: prefix sums over contexts, packing of contexts
+//               into work units of <= T samples, list of contexts > T samples.
+//   group_runs  order the run list by context (atomic cursors; a run learns
+//               its offset inside its context from the same atomic).
+//   units       one workgroup per unit, taken in context order by ticket:
+//               gather the unit's samples from its runs (pc 8 B + stall 1 B,
+//               read once), pack keys relative to each context's smallest pc,
+//               LSD radix sort in LDS, run-length reduce, decoupled look-back
+//               over units for the output offset, scope lookup, write.
+//   big path    contexts over T samples: chunk sort, pairwise merge rounds,
+//               duplicate combine, written where the unit pass placed them.
+//
+// When runs are short (shuffled input) the run list would cost more than the
+// samples themselves; the samples are then scattered into context order first.
+#include <algorithm>
+#include <memory>
+
+#include "block_prims.h"
+#include "hpa_internal.h"
+
+namespace hpa {
+namespace {
+
+constexpr int SCAN_BLOCK = 256;
+constexpr int SCAN_ITEMS = 16;
+constexpr int SCAN_TILE = SCAN_BLOCK * SCAN_ITEMS;  // samples per scan tile
+
+constexpr int UBLOCK = 512;
+constexpr int UITEMS = 16;
+constexpr int UT = UBLOCK * UITEMS;  // unit capacity (samples)
+constexpr int UHALF = UT / 2;        // contexts up to this size are packed together
+constexpr int MAXC = 256;            // contexts per unit
+constexpr int RBITS = 5;
+using Sorter = BlockRadix<UBLOCK, UITEMS, RBITS>;
+
+constexpr uint64_t M40 = (1ull << 40) - 1;
+constexpr int ERR_CTX = 1, ERR_STALL = 2, ERR_WIDE = 4;
+
+struct Run {
+  uint64_t start;  // first sample index in the input
+  uint64_t flat;   // position in context-grouped order (set by group_runs)
+  uint32_t len;
+  uint32_t ctx;
+};
+
+struct PlanInfo {
+  unsigned long long n_runs;
+  unsigned long long n_chunks;
+  unsigned long long big_samples;
+  unsigned long long total_keys;
+  uint32_t n_units;
+  uint32_t n_big;
+  uint32_t max_chunks;
+  uint32_t err;
+};
+
+__device__ inline int bits_for(uint64_t v) { return v ? 64 - __clzll(v) : 0; }
+
+// ----------------------------------------------------------------------------
+// scan_ctx: run detection over ctx[] (Section 4.2: one placeholder per buffer)
+// ----------------------------------------------------------------------------
+__global__ void __launch_bounds__(SCAN_BLOCK)
+k_scan_ctx(const uint32_t* __restrict__ ctx, uint64_t n, uint32_t n_ctx, unsigned long long* __restrict__ hist,
+           Run* __restrict__ runs, uint64_t run_cap, PlanInfo* __restrict__ info) {
+  __shared__ uint32_t s_ctx[SCAN_TILE];
+  __shared__ uint32_t s_head[SCAN_TILE];
+  __shared__ uint32_t s_wcnt[SCAN_ITEMS][SCAN_BLOCK / WAVE];
+  __shared__ unsigned long long s_base;
+  __shared__ uint32_t s_R;
+  const int tid = threadIdx.x;
+  const uint64_t n_tiles = (n + SCAN_TILE - 1) / SCAN_TILE;
+  for (uint64_t tile = blockIdx.x; tile < n_tiles; tile += gridDim.x) {
+    const uint64_t t0 = tile * SCAN_TILE;
+    const int cnt = (int)min((uint64_t)SCAN_TILE, n - t0);
+#pragma unroll
+    for (int i = 0; i < SCAN_ITEMS; ++i) {
+      int j = i * SCAN_BLOCK + tid;
+      if (j < cnt) s_ctx[j] = ctx[t0 + j];
+    }
+    __syncthreads();
+    // head flags in striped order; rank among heads = prefix over (item, wave, lane)
+    uint64_t mask[SCAN_ITEMS];
+#pragma unroll
+    for (int i = 0; i < SCAN_ITEMS; ++i) {
+      int j = i * SCAN_BLOCK + tid;
+      bool h = j < cnt && (j == 0 || s_ctx[j] != s_ctx[j - 1]);
+      mask[i] = __ballot(h);
+      if (lane_id() == 0) s_wcnt[i][wave_id()] = (uint32_t)__popcll(mask[i]);
+    }
+    __syncthreads();
+    if (tid == 0) {
+      uint32_t run = 0;
+      for (int i = 0; i < SCAN_ITEMS; ++i)
+        for (int w = 0; w < SCAN_BLOCK / WAVE; ++w) {
+          uint32_t t = s_wcnt[i][w];
+          s_wcnt[i][w] = run;
+          run += t;
+        }
+      s_R = run;
+      s_base = atomicAdd(&info->n_runs, (unsigned long long)run);
+    }
+    __syncthreads();
+#pragma unroll
+    for (int i = 0; i < SCAN_ITEMS; ++i) {
+      int j = i * SCAN_BLOCK + tid;
+      uint64_t below = mask[i] & ((1ull << lane_id()) - 1);
+      if ((mask[i] >> lane_id()) & 1) s_head[s_wcnt[i][wave_id()] + (uint32_t)__popcll(below)] = (uint32_t)j;
+    }
+    __syncthreads();
+    const uint32_t R = s_R;
+    const unsigned long long base = s_base;
+    for (uint32_t k = tid; k < R; k += SCAN_BLOCK) {
+      uint32_t p = s_head[k];
+      uint32_t len = (k + 1 < R ? s_head[k + 1] : (uint32_t)cnt) - p;
+      uint32_t c = s_ctx[p];
+      if (c >= n_ctx) {
+        atomicOr(&info->err, (uint32_t)ERR_CTX);
+        continue;
+      }
+      atomicAdd(&hist[c], (1ull << 40) | (unsigned long long)len);
+      uint64_t g = base + k;
+      if (g < run_cap) runs[g] = Run{t0 + p, 0, len, c};
+    }
+    __syncthreads();
+  }
+}
+
+// ----------------------------------------------------------------------------
+// plan: one workgroup walks the contexts in order
+// ----------------------------------------------------------------------------
+constexpr int PLAN_BLOCK = 1024;
+constexpr int PLAN_ITEMS = 8;
+
+enum : uint8_t { KIND_S = 0, KIND_M = 1, KIND_B = 2 };
+
+__device__ inline uint8_t ctx_kind(uint64_t n) { return n <= (uint64_t)UHALF ? KIND_S : (n <= (uint64_t)UT ? KIND_M : KIND_B); }
+
+__global__ void __launch_bounds__(PLAN_BLOCK)
+k_plan(const unsigned long long* __restrict__ hist, uint32_t n_ctx, uint64_t* __restrict__ sbase,
+       uint64_t* __restrict__ rbase, uint32_t* __restrict__ unit_begin, int32_t* __restrict__ unit_big,
+       uint32_t* __restrict__ big_ctx, uint64_t* __restrict__ big_sbase, uint64_t* __restrict__ big_chunk,
+       PlanInfo* __restrict__ info) {
+  __shared__ unsigned long long s_tmp[PLAN_BLOCK / WAVE + 1];
+  __shared__ uint32_t s_max;
+  const int tid = threadIdx.x;
+  if (tid == 0) s_max = 0;
+  // running totals carried across blocks of contexts
+  unsigned long long c_s = 0, c_r = 0, c_ps = 0, c_unit = 0, c_big = 0, c_chunk = 0, c_bs = 0;
+  uint32_t maxch = 0;
+  for (uint32_t b0 = 0; b0 < n_ctx; b0 += PLAN_BLOCK * PLAN_ITEMS) {
+    const uint32_t c0 = b0 + (uint32_t)tid * PLAN_ITEMS;
+    uint64_t nn[PLAN_ITEMS], rr[PLAN_ITEMS];
+    unsigned long long ls = 0, lr = 0, lps = 0, lbig = 0, lch = 0, lbs = 0;
+#pragma unroll
+    for (int i = 0; i < PLAN_ITEMS; ++i) {
+      uint32_t c = c0 + i;
+      unsigned long long h = c < n_ctx ? hist[c] : 0ull;
+      nn[i] = h & M40;
+      rr[i] = h >> 40;
+      ls += nn[i];
+      lr += rr[i];
+      uint8_t k = ctx_kind(nn[i]);
+      if (k == KIND_S) lps += nn[i];
+      if (k == KIND_B) { lbig += 1; lch += (nn[i] + UT - 1) / UT; lbs += nn[i]; }
+    }
+    const uint64_t n_before = (c0 > 0 && c0 - 1 < n_ctx) ? (hist[c0 - 1] & M40) : 0;
+    unsigned long long t;
+    const unsigned long long ps = block_excl_scan<PLAN_BLOCK>(ls, s_tmp, &t); const unsigned long long ps_tot = t;
+    const unsigned long long pr = block_excl_scan<PLAN_BLOCK>(lr, s_tmp, &t); const unsigned long long pr_tot = t;
+    const unsigned long long pp = block_excl_scan<PLAN_BLOCK>(lps, s_tmp, &t); const unsigned long long pp_tot = t;
+    const unsigned long long pb = block_excl_scan<PLAN_BLOCK>(lbig, s_tmp, &t); const unsigned long long pb_tot = t;
+    const unsigned long long pc = block_excl_scan<PLAN_BLOCK>(lch, s_tmp, &t); const unsigned long long pc_tot = t;
+    const unsigned long long pbs = block_excl_scan<PLAN_BLOCK>(lbs, s_tmp, &t); const unsigned long long pbs_tot = t;
+    // unit starts: a new unit at every context that is not packable, after one,
+    // every MAXC contexts, and where the packable prefix crosses a multiple of UHALF
+    uint8_t starts[PLAN_ITEMS];
+    unsigned long long lunits = 0;
+    {
+      uint64_t ps_c = c_ps + pp;  // packable samples before context c
+      uint64_t n_prev = n_before;
+#pragma unroll
+      for (int i = 0; i < PLAN_ITEMS; ++i) {
+        uint32_t c = c0 + i;
+        bool st = false;
+        if (c < n_ctx) {
+          uint8_t k = ctx_kind(nn[i]);
+          uint8_t kp = c > 0 ? ctx_kind(n_prev) : KIND_S;
+          uint64_t ps_prev = ps_c - (c > 0 && kp == KIND_S ? n_prev : 0);
+          st = c == 0 || k != KIND_S || kp != KIND_S || (c % MAXC) == 0 || (ps_c / UHALF) != (ps_prev / UHALF);
+          if (k == KIND_S) ps_c += nn[i];
+          n_prev = nn[i];
+        }
+        starts[i] = st;
+        lunits += st;
+      }
+    }
+    const unsigned long long pu = block_excl_scan<PLAN_BLOCK>(lunits, s_tmp, &t);
+    const unsigned long long pu_tot = t;
+    {
+      unsigned long long sv = c_s + ps, r = c_r + pr, u = c_unit + pu, bg = c_big + pb, ch = c_chunk + pc,
+                         bs = c_bs + pbs;
+#pragma unroll
+      for (int i = 0; i < PLAN_ITEMS; ++i) {
+        uint32_t c = c0 + i;
+        if (c >= n_ctx) continue;
+        sbase[c] = sv;
+        rbase[c] = r;
+        const uint8_t k = ctx_kind(nn[i]);
+        if (starts[i]) {
+          unit_begin[u] = c;
+          unit_big[u] = k == KIND_B ? (int32_t)bg : -1;
+          ++u;
+        }
+        if (k == KIND_B) {
+          uint64_t nk = (nn[i] + UT - 1) / UT;
+          big_ctx[bg] = c;
+          big_sbase[bg] = bs;
+          big_chunk[bg] = ch;
+          maxch = max(maxch, (uint32_t)nk);
+          ++bg;
+          ch += nk;
+          bs += nn[i];
+        }
+        sv += nn[i];
+        r += rr[i];
+      }
+    }
+    c_s += ps_tot; c_r += pr_tot; c_ps += pp_tot; c_big += pb_tot; c_chunk += pc_tot; c_unit += pu_tot;
+    c_bs += pbs_tot;
+  }
+  atomicMax(&s_max, maxch);
+  __syncthreads();
+  if (tid == 0) {
+    sbase[n_ctx] = c_s;
+    rbase[n_ctx] = c_r;
+    unit_begin[c_unit] = n_ctx;
+    big_chunk[c_big] = c_chunk;
+    big_sbase[c_big] = c_bs;
+    info->n_units = (uint32_t)c_unit;
+    info->n_big = (uint32_t)c_big;
+    info->n_chunks = c_chunk;
+    info->big_samples = c_bs;
+    info->max_chunks = s_max;
+  }
+}
+
+// ----------------------------------------------------------------------------
+// group_runs: runs ordered by context; one 64-bit atomic gives both the run's
+// slot and its sample offset within the context
+// ----------------------------------------------------------------------------
+__global__ void k_group_runs(const Run* __restrict__ runs, uint64_t n_runs, const uint64_t* __restrict__ sbase,
+                             const uint64_t* __restrict__ rbase, unsigned long long* __restrict__ cur,
+                             Run* __restrict__ grouped) {
+  for (uint64_t r = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; r < n_runs; r += (uint64_t)gridDim.x * blockDim.x) {
+    Run x = runs[r];
+    unsigned long long old = atomicAdd(&cur[x.ctx], (1ull << 40) | (unsigned long long)x.len);
+    uint64_t k = old >> 40, soff = old & M40;
+    x.flat = sbase[x.ctx] + soff;
+    grouped[rbase[x.ctx] + k] = x;
+  }
+}
+
+// scatter: samples into context order (used when runs are short)
+__global__ void k_scatter(const uint64_t* __restrict__ pc, const uint32_t* __restrict__ ctx,
+                          const uint8_t* __restrict__ stall, const uint32_t* __restrict__ weight, uint64_t n,
+                          const uint64_t* __restrict__ sbase, unsigned long long* __restrict__ cur,
+                          uint64_t* __restrict__ opc, uint8_t* __restrict__ ostall, uint32_t* __restrict__ ow,
+                          uint32_t n_ctx) {
+  for (uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (uint64_t)gridDim.x * blockDim.x) {
+    uint32_t c = ctx[i];
+    if (c >= n_ctx) continue;
+    uint64_t pos = sbase[c] + atomicAdd(&cur[c], 1ull);
+    opc[pos] = pc[i];
+    ostall[pos] = stall[i];
+    if (ow) ow[pos] = weight[i];
+  }
+}
+
+// ----------------------------------------------------------------------------
+// Shared pieces of the sort workgroups (units and big-context chunks)
+// ----------------------------------------------------------------------------
+struct SortSmem {
+  uint32_t buf[Sorter::BUF_WORDS];
+  uint32_t cnt[Sorter::CNT_WORDS];  // radix counters; later head positions / weight prefixes
+  uint32_t doff[Sorter::DOFF_WORDS];
+  unsigned long long pcmin[MAXC];
+  uint32_t ucnt[MAXC + 1];
+  unsigned long long red_or, red_max;
+  unsigned long long scan_tmp[UBLOCK / WAVE + 1];
+  uint32_t last_hi[UBLOCK], last_lo[UBLOCK];
+  unsigned long long prefix;
+  uint32_t unit, nU;
+};
+static_assert(sizeof(uint32_t) * (Sorter::BUF_WORDS + Sorter::CNT_WORDS) >= sizeof(unsigned long long) * (UT + 1),
+              "weight prefixes must fit in the exchange and counter planes");
+
+// One workgroup's samples in registers: pc, (stall | local context << 4), weight.
+template <bool WEIGHTED>
+struct Gathered {
+  uint64_t pc[UITEMS];
+  uint32_t meta[UITEMS];
+  uint32_t w[WEIGHTED ? UITEMS : 1];
+  __device__ uint32_t st(int i) const { return meta[i] & 15u; }
+  __device__ uint32_t lc(int i) const { return meta[i] >> 4; }
+  __device__ uint32_t wt(int i) const {
+    if constexpr (WEIGHTED) return w[i];
+    else return 1u;
+  }
+};
+
+// Load sample j (0 <= j < n_u, flat = s0 + j) of a unit: run mode finds the run
+// by binary search over the unit's grouped runs; scattered mode reads flat.
+template <bool SCATTERED, bool WEIGHTED>
+__device__ inline void gather(Gathered<WEIGHTED>& g, uint64_t s0, uint64_t n_u, uint32_t cb, const Run* __restrict__ grp,
+                              uint64_t r_lo, uint64_t r_hi, const uint64_t* __restrict__ sb_lds_or_global,
+                              uint32_t n_cu, const uint64_t* __restrict__ pc, const uint8_t* __restrict__ stall,
+                              const uint32_t* __restrict__ weight, uint32_t* err) {
+#pragma unroll
+  for (int i = 0; i < UITEMS; ++i) {
+    uint64_t j = (uint64_t)i * UBLOCK + threadIdx.x;
+    g.pc[i] = 0;
+    g.meta[i] = 0;
+    if constexpr (WEIGHTED) g.w[i] = 0;
+    if (j >= n_u) continue;
+    uint64_t flat = s0 + j, src;
+    uint32_t c;
+    if constexpr (SCATTERED) {
+      // local context: last l with sbase[cb + l] <= flat among the unit's contexts
+      uint32_t lo = 0, hi = n_cu;
+      while (hi - lo > 1) {
+        uint32_t mid = (lo + hi) >> 1;
+        if (sb_lds_or_global[mid] <= flat) lo = mid;
+        else hi = mid;
+      }
+      c = cb + lo;
+      src = flat;
+    } else {
+      uint64_t lo = r_lo, hi = r_hi;
+      while (hi - lo > 1) {
+        uint64_t mid = (lo + hi) >> 1;
+        if (grp[mid].flat <= flat) lo = mid;
+        else hi = mid;
+      }
+      Run r = grp[lo];
+      c = r.ctx;
+      src = r.start + (flat - r.flat);
+    }
+    g.pc[i] = pc[src];
+    uint8_t s = stall[src];
+    if (s >= NS) { atomicOr(err, (uint32_t)ERR_STALL); s = 0; }
+    g.meta[i] = (uint32_t)s | ((c - cb) << 4);
+    if constexpr (WEIGHTED) g.w[i] = weight[src];
+  }
+}
+
+// Sort the unit's keys and find the unique keys.  Returns false (and flags
+// ERR_WIDE) when the packed key needs more than 63 bits.
+template <bool WEIGHTED, class K>
+__device__ inline void sort_reduce(SortSmem& sm, Gathered<WEIGHTED>& g, uint64_t n_u, uint32_t n_cu, K (&key)[UITEMS],
+                                   uint32_t (&val)[UITEMS], int kbits, int pcb, uint32_t tz) {
+#pragma unroll
+  for (int i = 0; i < UITEMS; ++i) {
+    uint64_t j = (uint64_t)i * UBLOCK + threadIdx.x;
+    if (j < n_u) {
+      uint64_t rel = (g.pc[i] - sm.pcmin[g.lc(i)]) >> tz;
+      key[i] = (K)(((uint64_t)g.lc(i) << (pcb + 4)) | (rel << 4) | g.st(i));
+    } else {
+      key[i] = (K)(1ull << kbits);  // padding sorts after every real key
+    }
+    val[i] = g.wt(i);
+  }
+  Sorter::template sort<K, WEIGHTED>(key, val, kbits + 1, sm.buf, sm.cnt, sm.doff);
+}
+
+__device__ inline void publish(unsigned long long* status, uint32_t u, unsigned long long flag,
+                               unsigned long long value) {
+  __hip_atomic_store(&status[u], (flag << 62) | value, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
+}
+
+// decoupled look-back over units in ticket order; returns the exclusive prefix
+__device__ inline unsigned long long lookback(unsigned long long* status, uint32_t u, unsigned long long agg) {
+  if (u == 0) {
+    publish(status, 0, 2, agg);
+    return 0;
+  }
+  publish(status, u, 1, agg);
+  unsigned long long acc = 0;
+  int64_t j = (int64_t)u - 1;
+  while (j >= 0) {
+    unsigned long long s = __hip_atomic_load(&status[j], __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT);
+    unsigned long long f = s >> 62;
+    if (f == 0) {
+      __builtin_amdgcn_s_sleep(1);
+      continue;
+    }
+    acc += s & ((1ull << 62) - 1);
+    if (f == 2) break;
+    --j;
+  }
+  publish(status, u, 2, acc + agg);
+  return acc;
+}
+
+// Find the interval of pc starting from a known lower bound (keys of one
+// context come in ascending pc order, so the walk is short).
+__device__ inline uint32_t scope_walk(const uint64_t* __restrict__ start, const uint64_t* __restrict__ end,
+                                      const uint32_t* __restrict__ scope, uint64_t n_iv, uint64_t pc, uint64_t& hint) {
+  // hint: index with start[hint] <= pc is not guaranteed; restart when pc is below
+  uint64_t i = hint;
+  if (n_iv == 0) return NONE32;
+  if (i >= n_iv || start[i] > pc) {
+    uint64_t lo = 0, hi = n_iv;
+    while (lo < hi) {
+      uint64_t mid = (lo + hi) >> 1;
+      if (start[mid] <= pc) lo = mid + 1;
+      else hi = mid;
+    }
+    if (lo == 0) { hint = 0; return NONE32; }
+    i = lo - 1;
+  } else {
+    int steps = 0;
+    while (i + 1 < n_iv && start[i + 1] <= pc) {
+      ++i;
+      if (++steps == 8) {
+        uint64_t lo = i, hi = n_iv;
+        while (lo < hi) {
+          uint64_t mid = (lo + hi) >> 1;
+          if (start[mid] <= pc) lo = mid + 1;
+          else hi = mid;
+        }
+        i = lo - 1;
+        break;
+      }
+    }
+  }
+  hint = i;
+  return pc < end[i] ? scope[i] : NONE32;
+}
+
+struct MapDev {
+  const uint64_t* start;
+  const uint64_t* end;
+  const uint32_t* scope;
+  uint64_t n_iv;
+};
+
+struct OutDev {
+  uint32_t* ctx;
+  uint64_t* pc;
+  uint8_t* stall;
+  unsigned long long* count;
+  uint32_t* scope;
+  uint64_t* ctx_off;
+};
+
+// Per-unit key statistics: per-context smallest pc, common trailing zeros, widest span.
+template <bool WEIGHTED>
+__device__ inline void key_stats(SortSmem& sm, const Gathered<WEIGHTED>& g, uint64_t n_u, uint32_t n_cu, uint32_t* err,
+                                 int& kbits, int& pcb, uint32_t& tz) {
+  for (uint32_t l = threadIdx.x; l < n_cu; l += UBLOCK) sm.pcmin[l] = ~0ull;
+  if (threadIdx.x == 0) { sm.red_or = 0; sm.red_max = 0; }
+  __syncthreads();
+#pragma unroll
+  for (int i = 0; i < UITEMS; ++i)
+    if ((uint64_t)i * UBLOCK + threadIdx.x < n_u) atomicMin(&sm.pcmin[g.lc(i)], (unsigned long long)g.pc[i]);
+  __syncthreads();
+  unsigned long long o = 0, mx = 0;
+#pragma unroll
+  for (int i = 0; i < UITEMS; ++i)
+    if ((uint64_t)i * UBLOCK + threadIdx.x < n_u) {
+      unsigned long long r = g.pc[i] - sm.pcmin[g.lc(i)];
+      o |= r;
+      mx = r > mx ? r : mx;
+    }
+  o = wave_or(o);
+  mx = wave_max(mx);
+  if (lane_id() == 0) { atomicOr(&sm.red_or, o); atomicMax(&sm.red_max, mx); }
+  __syncthreads();
+  tz = sm.red_or ? (uint32_t)__ffsll((long long)sm.red_or) - 1 : 0;
+  pcb = bits_for(sm.red_max >> tz);
+  int cbits = bits_for(n_cu > 0 ? n_cu - 1 : 0);
+  kbits = cbits + pcb + 4;
+  if (kbits > 63 && threadIdx.x == 0) atomicOr(err, (uint32_t)ERR_WIDE);
+}
+
+// After the sort: head flags, unique count, per-unique counts (in LDS), the
+// per-context unique counts.  Returns the thread's head count and fills hpos.
+template <bool WEIGHTED, class K>
+__device__ inline uint32_t find_heads(SortSmem& sm, const K (&key)[UITEMS], const uint32_t (&val)[UITEMS],
+                                      uint64_t n_u, uint32_t n_cu, int pcb, uint32_t& first_uidx, uint32_t& nU) {
+  const int tid = threadIdx.x;
+  sm.last_lo[tid] = (uint32_t)key[UITEMS - 1];
+  sm.last_hi[tid] = (uint32_t)((uint64_t)key[UITEMS - 1] >> 32);
+  for (uint32_t l = tid; l <= n_cu; l += UBLOCK) sm.ucnt[l] = 0;
+  __syncthreads();
+  K prev = tid == 0 ? (K)0 : (K)(((uint64_t)sm.last_hi[tid - 1] << 32) | sm.last_lo[tid - 1]);
+  uint32_t heads = 0;
+#pragma unroll
+  for (int i = 0; i < UITEMS; ++i) {
+    uint32_t p = (uint32_t)tid * UITEMS + i;
+    bool h = p < n_u && (p == 0 || key[i] != prev);
+    heads += h;
+    prev = key[i];
+  }
+  unsigned long long tot;
+  unsigned long long ex = block_excl_scan<UBLOCK>((unsigned long long)heads, sm.scan_tmp, &tot);
+  first_uidx = (uint32_t)ex;
+  nU = (uint32_t)tot;
+  // head positions (or weight prefixes) indexed by unique index, in the counter/buffer planes
+  if constexpr (WEIGHTED) {
+    unsigned long long wsum = 0;
+#pragma unroll
+    for (int i = 0; i < UITEMS; ++i)
+      if ((uint64_t)tid * UITEMS + i < n_u) wsum += val[i];
+    unsigned long long wtot;
+    unsigned long long wex = block_excl_scan<UBLOCK>(wsum, sm.scan_tmp, &wtot);
+    unsigned long long* wp = reinterpret_cast<unsigned long long*>(sm.buf);
+    prev = tid == 0 ? (K)0 : (K)(((uint64_t)sm.last_hi[tid - 1] << 32) | sm.last_lo[tid - 1]);
+    uint32_t u = first_uidx;
+    unsigned long long run = wex;
+#pragma unroll
+    for (int i = 0; i < UITEMS; ++i) {
+      uint32_t p = (uint32_t)tid * UITEMS + i;
+      bool h = p < n_u && (p == 0 || key[i] != prev);
+      if (h) wp[u++] = run;
+      if (p < n_u) run += val[i];
+      prev = key[i];
+    }
+    if (tid == 0) wp[nU] = wtot;
+  } else {
+    uint32_t* hp = sm.buf;
+    prev = tid == 0 ? (K)0 : (K)(((uint64_t)sm.last_hi[tid - 1] << 32) | sm.last_lo[tid - 1]);
+    uint32_t u = first_uidx;
+#pragma unroll
+    for (int i = 0; i < UITEMS; ++i) {
+      uint32_t p = (uint32_t)tid * UITEMS + i;
+      bool h = p < n_u && (p == 0 || key[i] != prev);
+      if (h) hp[u++] = p;
+      prev = key[i];
+    }
+    if (tid == 0) hp[nU] = (uint32_t)n_u;
+  }
+  // unique keys per local context
+  {
+    prev = tid == 0 ? (K)0 : (K)(((uint64_t)sm.last_hi[tid - 1] << 32) | sm.last_lo[tid - 1]);
+#pragma unroll
+    for (int i = 0; i < UITEMS; ++i) {
+      uint32_t p = (uint32_t)tid * UITEMS + i;
+      bool h = p < n_u && (p == 0 || key[i] != prev);
+      if (h) atomicAdd(&sm.ucnt[(uint32_t)((uint64_t)key[i] >> (pcb + 4))], 1u);
+      prev = key[i];
+    }
+  }
+  __syncthreads();
+  return heads;
+}
+
+template <bool WEIGHTED>
+__device__ inline unsigned long long count_of(const SortSmem& sm, uint32_t u) {
+  if constexpr (WEIGHTED) {
+    const unsigned long long* wp = reinterpret_cast<const unsigned long long*>(sm.buf);
+    return wp[u + 1] - wp[u];
+  } else {
+    return (unsigned long long)(sm.buf[u + 1] - sm.buf[u]);
+  }
+}
+
+// ----------------------------------------------------------------------------
+// units: the ordered pass
+// ----------------------------------------------------------------------------
+struct UnitArgs {
+  const uint64_t* pc;
+  const uint8_t* stall;
+  const uint32_t* weight;
+  const uint64_t* sbase;
+  const uint64_t* rbase;
+  const Run* grouped;
+  const uint32_t* unit_begin;
+  const int32_t* unit_big;
+  const uint64_t* big_U;
+  uint64_t* big_out;
+  unsigned long long* status;
+  unsigned int* ticket;
+  PlanInfo* info;
+  uint32_t n_units;
+  uint32_t n_ctx;
+  MapDev map;
+  OutDev out;
+};
+
+template <bool WEIGHTED, class K>
+__device__ void unit_body(SortSmem& sm, const UnitArgs& a, uint32_t u, uint32_t cb, uint32_t ce, uint64_t n_u,
+                          Gathered<WEIGHTED>& g, int kbits, int pcb, uint32_t tz) {
+  const uint32_t n_cu = ce - cb;
+  K key[UITEMS];
+  uint32_t val[UITEMS];
+  sort_reduce<WEIGHTED, K>(sm, g, n_u, n_cu, key, val, kbits, pcb, tz);
+  uint32_t first, nU;
+  uint32_t heads = find_heads<WEIGHTED, K>(sm, key, val, n_u, n_cu, pcb, first, nU);
+  if (threadIdx.x == 0) sm.prefix = lookback(a.status, u, nU);
+  __syncthreads();
+  const unsigned long long prefix = sm.prefix;
+  // context offsets: exclusive scan of unique counts per local context
+  if (threadIdx.x == 0) {
+    unsigned long long run = prefix;
+    for (uint32_t l = 0; l < n_cu; ++l) {
+      a.out.ctx_off[cb + l] = run;
+      run += sm.ucnt[l];
+    }
+    if (u + 1 == a.n_units) {
+      a.out.ctx_off[a.n_ctx] = run;
+      a.info->total_keys = run;
+    }
+  }
+  // emit: each thread writes its heads (consecutive output slots per thread)
+  if (heads) {
+    K prev = threadIdx.x == 0 ? (K)0
+                              : (K)(((uint64_t)sm.last_hi[threadIdx.x - 1] << 32) | sm.last_lo[threadIdx.x - 1]);
+    uint32_t ui = first;
+    uint64_t hint = NONE64;
+    const uint64_t pmask = pcb >= 64 ? ~0ull : ((1ull << pcb) - 1);
+#pragma unroll
+    for (int i = 0; i < UITEMS; ++i) {
+      uint32_t p = threadIdx.x * UITEMS + i;
+      bool h = p < n_u && (p == 0 || key[i] != prev);
+      prev = key[i];
+      if (!h) continue;
+      uint64_t kk = (uint64_t)key[i];
+      uint32_t lc = (uint32_t)(kk >> (pcb + 4));
+      uint64_t pcv = sm.pcmin[lc] + (((kk >> 4) & pmask) << tz);
+      uint64_t o = prefix + ui;
+      a.out.ctx[o] = cb + lc;
+      a.out.pc[o] = pcv;
+      a.out.stall[o] = (uint8_t)(kk & 15);
+      a.out.count[o] = count_of<WEIGHTED>(sm, ui);
+      a.out.scope[o] = scope_walk(a.map.start, a.map.end, a.map.scope, a.map.n_iv, pcv, hint);
+      ++ui;
+    }
+  }
+}
+
+template <bool WEIGHTED, bool SCATTERED>
+__global__ void __launch_bounds__(UBLOCK) k_units32(UnitArgs a) {
+  __shared__ SortSmem sm;
+  __shared__ uint64_t s_sb[MAXC + 1];
+  if (threadIdx.x == 0) sm.unit = atomicAdd(a.ticket, 1u);
+  __syncthreads();
+  const uint32_t u = sm.unit;
+  if (u >= a.n_units) return;
+  const uint32_t cb = a.unit_begin[u], ce = a.unit_begin[u + 1];
+  const int32_t big = a.unit_big[u];
+  if (big >= 0) {
+    if (threadIdx.x == 0) {
+      unsigned long long U = a.big_U[big];
+      unsigned long long p = lookback(a.status, u, U);
+      a.big_out[big] = p;
+      a.out.ctx_off[cb] = p;
+      if (u + 1 == a.n_units) {
+        a.out.ctx_off[a.n_ctx] = p + U;
+        a.info->total_keys = p + U;
+      }
+    }
+    return;
+  }
+  const uint64_t s0 = a.sbase[cb];
+  const uint64_t n_u = a.sbase[ce] - s0;
+  for (uint32_t l = threadIdx.x; l <= ce - cb; l += UBLOCK) s_sb[l] = a.sbase[cb + l];
+  __syncthreads();
+  Gathered<WEIGHTED> g;
+  gather<SCATTERED, WEIGHTED>(g, s0, n_u, cb, a.grouped, SCATTERED ? 0 : a.rbase[cb], SCATTERED ? 0 : a.rbase[ce],
+                              s_sb, ce - cb, a.pc, a.stall, a.weight, &a.info->err);
+  // key width decides the register type of the sort
+  int kbits, pcb;
+  uint32_t tz;
+  key_stats(sm, g, n_u, ce - cb, &a.info->err, kbits, pcb, tz);
+  if (kbits > 63) {
+    // keep the look-back chain alive; the call reports the error afterwards
+    if (threadIdx.x == 0) sm.prefix = lookback(a.status, u, 0);
+    __syncthreads();
+    for (uint32_t l = threadIdx.x; l < ce - cb; l += UBLOCK) a.out.ctx_off[cb + l] = sm.prefix;
+    if (threadIdx.x == 0 && u + 1 == a.n_units) { a.out.ctx_off[a.n_ctx] = sm.prefix; a.info->total_keys = sm.prefix; }
+    return;
+  }
+  __syncthreads();
+  unit_body<WEIGHTED, uint64_t>(sm, a, u, cb, ce, n_u, g, kbits, pcb, tz);
+}
+
+// ----------------------------------------------------------------------------
+// big contexts: chunk sort -> merge rounds -> heads -> write
+// ----------------------------------------------------------------------------
+struct BigArgs {
+  const uint64_t* pc;
+  const uint8_t* stall;
+  const uint32_t* weight;
+  const uint64_t* sbase;
+  const uint64_t* rbase;
+  const Run* grouped;
+  const uint32_t* big_ctx;
+  const uint64_t* big_sbase;
+  const uint64_t* big_chunk;
+  uint32_t n_big;
+  uint64_t n_chunks;
+  PlanInfo* info;
+};
+
+struct ListBuf {
+  uint64_t* pc;
+  uint8_t* stall;
+  unsigned long long* cnt;
+  uint64_t* len;  // per chunk: length of the list that starts at this chunk
+};
+
+__device__ inline uint32_t chunk_owner(const uint64_t* big_chunk, uint32_t n_big, uint64_t ch) {
+  uint32_t lo = 0, hi = n_big;  // last b with big_chunk[b] <= ch
+  while (hi - lo > 1) {
+    uint32_t mid = (lo + hi) >> 1;
+    if (big_chunk[mid] <= ch) lo = mid;
+    else hi = mid;
+  }
+  return lo;
+}
+
+template <bool WEIGHTED, bool SCATTERED>
+__global__ void __launch_bounds__(UBLOCK) k_big_chunks(BigArgs a, ListBuf o) {
+  __shared__ SortSmem sm;
+  __shared__ uint64_t s_sb[2];
+  const uint64_t ch = blockIdx.x;
+  const uint32_t b = chunk_owner(a.big_chunk, a.n_big, ch);
+  const uint32_t c = a.big_ctx[b];
+  const uint64_t j = ch - a.big_chunk[b];
+  const uint64_t nc = a.sbase[c + 1] - a.sbase[c];
+  const uint64_t s0 = a.sbase[c] + j * UT;
+  const uint64_t n_u = min((uint64_t)UT, nc - j * UT);
+  if (threadIdx.x == 0) { s_sb[0] = a.sbase[c]; s_sb[1] = a.sbase[c + 1]; }
+  __syncthreads();
+  Gathered<WEIGHTED> g;
+  gather<SCATTERED, WEIGHTED>(g, s0, n_u, c, a.grouped, SCATTERED ? 0 : a.rbase[c], SCATTERED ? 0 : a.rbase[c + 1],
+                              s_sb, 1, a.pc, a.stall, a.weight, &a.info->err);
+  int kbits, pcb;
+  uint32_t tz;
+  key_stats(sm, g, n_u, 1, &a.info->err, kbits, pcb, tz);
+  const uint64_t obase = a.big_sbase[b] + j * UT;
+  if (kbits > 63) {
+    if (threadIdx.x == 0) o.len[ch] = 0;
+    return;
+  }
+  uint64_t key[UITEMS];
+  uint32_t val[UITEMS];
+  __syncthreads();
+  sort_reduce<WEIGHTED, uint64_t>(sm, g, n_u, 1, key, val, kbits, pcb, tz);
+  uint32_t first, nU;
+  uint32_t heads = find_heads<WEIGHTED, uint64_t>(sm, key, val, n_u, 1, pcb, first, nU);
+  if (threadIdx.x == 0) o.len[ch] = nU;
+  if (!heads) return;
+  uint64_t prev = threadIdx.x == 0 ? 0 : (((uint64_t)sm.last_hi[threadIdx.x - 1] << 32) | sm.last_lo[threadIdx.x - 1]);
+  uint32_t ui = first;
+  const uint64_t pmask = pcb >= 64 ? ~0ull : ((1ull << pcb) - 1);
+#pragma unroll
+  for (int i = 0; i < UITEMS; ++i) {
+    uint32_t p = threadIdx.x * UITEMS + i;
+    bool h = p < n_u && (p == 0 || key[i] != prev);
+    prev = key[i];
+    if (!h) continue;
+    uint64_t kk = key[i];
+    o.pc[obase + ui] = sm.pcmin[0] + (((kk >> 4) & pmask) << tz);
+    o.stall[obase + ui] = (uint8_t)(kk & 15);
+    o.cnt[obase + ui] = count_of<WEIGHTED>(sm, ui);
+    ++ui;
+  }
+}
+
+__device__ inline bool key_less(uint64_t pa, uint8_t sa, uint64_t pb, uint8_t sb) {
+  return pa < pb || (pa == pb && sa < sb);
+}
+
+// One merge round: lists of 2^r chunks pair up into lists of 2^(r+1) chunks.
+__global__ void __launch_bounds__(256) k_big_merge(BigArgs a, ListBuf in, ListBuf out, int r) {
+  const uint64_t ch = blockIdx.x;
+  const uint32_t b = chunk_owner(a.big_chunk, a.n_big, ch);
+  const uint64_t c0 = a.big_chunk[b], nch = a.big_chunk[b + 1] - c0;
+  const uint64_t j = ch - c0;
+  const uint64_t L = j >> r;               // my list
+  const uint64_t first_mine = L << r;      // first chunk of my list
+  const uint64_t other = L ^ 1ull;
+  const uint64_t first_other = other << r;
+  const uint64_t first_merged = (L >> 1) << (r + 1);
+  const bool is_b = (L & 1) != 0;
+  const uint64_t len_mine = in.len[c0 + first_mine];
+  const uint64_t len_other = first_other < nch ? in.len[c0 + first_other] : 0;
+  const uint64_t base = a.big_sbase[b];
+  const uint64_t mine_off = base + first_mine * UT, other_off = base + first_other * UT;
+  const uint64_t out_off = base + first_merged * UT;
+  const uint64_t e0 = (j - first_mine) * UT;
+  if (threadIdx.x == 0 && j == first_merged) {
+    uint64_t la = is_b ? len_other : len_mine, lb = is_b ? len_mine : len_other;
+    out.len[c0 + first_merged] = la + lb;
+  }
+  for (uint64_t e = e0 + threadIdx.x; e < e0 + UT && e < len_mine; e += blockDim.x) {
+    uint64_t p = in.pc[mine_off + e];
+    uint8_t s = in.stall[mine_off + e];
+    unsigned long long cnt = in.cnt[mine_off + e];
+    // rank in the other list: A elements go before equal B elements
+    uint64_t lo = 0, hi = len_other;
+    while (lo < hi) {
+      uint64_t mid = (lo + hi) >> 1;
+      uint64_t q = in.pc[other_off + mid];
+      uint8_t qs = in.stall[other_off + mid];
+      bool go_right = is_b ? !key_less(p, s, q, qs) : key_less(q, qs, p, s);
+      if (go_right) lo = mid + 1;
+      else hi = mid;
+    }
+    uint64_t pos = out_off + e + lo;
+    out.pc[pos] = p;
+    out.stall[pos] = s;
+    out.cnt[pos] = cnt;
+  }
+}
+
+// heads per chunk-sized slot of each big context's final list
+__global__ void __launch_bounds__(256) k_big_heads(BigArgs a, ListBuf fin, unsigned long long* slot_heads) {
+  __shared__ unsigned long long s_tmp[256 / WAVE + 1];
+  const uint64_t ch = blockIdx.x;
+  const uint32_t b = chunk_owner(a.big_chunk, a.n_big, ch);
+  const uint64_t c0 = a.big_chunk[b];
+  const uint64_t len = fin.len[c0];
+  const uint64_t base = a.big_sbase[b];
+  const uint64_t e0 = (ch - c0) * UT;
+  unsigned long long h = 0;
+  for (uint64_t e = e0 + threadIdx.x; e < e0 + UT && e < len; e += blockDim.x)
+    h += e == 0 || fin.pc[base + e] != fin.pc[base + e - 1] || fin.stall[base + e] != fin.stall[base + e - 1];
+  unsigned long long tot;
+  block_excl_scan<256>(h, s_tmp, &tot);
+  if (threadIdx.x == 0) slot_heads[ch] = tot;
+}
+
+// exclusive scan of slot head counts (one workgroup), per-context totals
+__global__ void __launch_bounds__(1024) k_big_scan(BigArgs a, unsigned long long* slot_heads, uint64_t* big_U) {
+  __shared__ unsigned long long s_tmp[1024 / WAVE + 1];
+  unsigned long long carry = 0;
+  for (uint64_t b0 = 0; b0 < a.n_chunks; b0 += 1024) {
+    uint64_t i = b0 + threadIdx.x;
+    unsigned long long v = i < a.n_chunks ? slot_heads[i] : 0;
+    unsigned long long tot;
+    unsigned long long ex = block_excl_scan<1024>(v, s_tmp, &tot);
+    if (i < a.n_chunks) slot_heads[i] = carry + ex;
+    carry += tot;
+    __syncthreads();
+  }
+  __syncthreads();
+  for (uint32_t b = threadIdx.x; b < a.n_big; b += 1024) {
+    uint64_t c0 = a.big_chunk[b], c1 = a.big_chunk[b + 1];
+    unsigned long long end = c1 < a.n_chunks ? slot_heads[c1] : carry;
+    big_U[b] = end - slot_heads[c0];
+  }
+}
+
+__global__ void __launch_bounds__(256) k_big_write(BigArgs a, ListBuf fin, const unsigned long long* slot_prefix,
+                                                   const uint64_t* big_out, MapDev map, OutDev out) {
+  __shared__ unsigned long long s_tmp[256 / WAVE + 1];
+  const uint64_t ch = blockIdx.x;
+  const uint32_t b = chunk_owner(a.big_chunk, a.n_big, ch);
+  const uint64_t c0 = a.big_chunk[b];
+  const uint32_t c = a.big_ctx[b];
+  const uint64_t len = fin.len[c0];
+  const uint64_t base = a.big_sbase[b];
+  const uint64_t e0 = (ch - c0) * UT;
+  const unsigned long long slot0 = slot_prefix[ch] - slot_prefix[c0];
+  unsigned long long done = 0;
+  uint64_t hint = NONE64;
+  for (uint64_t eb = e0; eb < e0 + UT && eb < len; eb += blockDim.x) {
+    uint64_t e = eb + threadIdx.x;
+    bool h = e < len && e < e0 + UT &&
+             (e == 0 || fin.pc[base + e] != fin.pc[base + e - 1] || fin.stall[base + e] != fin.stall[base + e - 1]);
+    unsigned long long tot;
+    unsigned long long ex = block_excl_scan<256>((unsigned long long)h, s_tmp, &tot);
+    if (h) {
+      uint64_t p = fin.pc[base + e];
+      uint8_t s = fin.stall[base + e];
+      unsigned long long cnt = fin.cnt[base + e];
+      for (uint64_t f = e + 1; f < len && fin.pc[base + f] == p && fin.stall[base + f] == s; ++f) cnt += fin.cnt[base + f];
+      uint64_t o = big_out[b] + slot0 + done + ex;
+      out.ctx[o] = c;
+      out.pc[o] = p;
+      out.stall[o] = s;
+      out.count[o] = cnt;
+      out.scope[o] = scope_walk(map.start, map.end, map.scope, map.n_iv, p, hint);
+    }
+    done += tot;
+  }
+}
+
+}  // namespace
+}  // namespace hpa
+
+using namespace hpa;
+
+extern "C" hpa_status hpa_attribute(hpa_ctx* ctx, const hpa_structure_map* map, const hpa_samples* smp,
+                                    hipStream_t stream, hpa_attribution** out) {
+  return guard([&] {
+    if (!ctx || !map || !smp || !out) fail(HPA_E_INVAL, "NULL argument");
+    if (map->ctx != ctx) fail(HPA_E_INVAL, "map belongs to another context");
+    if (smp->n && (!smp->pc || !smp->ctx || !smp->stall)) fail(HPA_E_INVAL, "NULL sample array");
+    if (smp->n_ctx == 0 || smp->n_ctx >= 0x7FFFFFFFu) fail(HPA_E_INVAL, "n_ctx out of range");
+    if (smp->n >= (1ull << 40)) fail(HPA_E_INVAL, "too many samples for one call");
+    DeviceGuard dg(ctx->device);
+    hipStream_t s = stream;
+    const uint64_t n = smp->n;
+    const uint32_t C = smp->n_ctx;
+    auto* A = new hpa_attribution();
+    std::unique_ptr<hpa_attribution> hold(A);
+    A->ctx = ctx;
+    A->stream = s;
+    A->map = map;
+    A->n_ctx = C;
+    const uint64_t cap = n ? n : 1;
+    A->ctx_id = DBuf(ctx, cap * 4, s);
+    A->pc = DBuf(ctx, cap * 8, s);
+    A->stall = DBuf(ctx, cap, s);
+    A->count = DBuf(ctx, cap * 8, s);
+    A->scope = DBuf(ctx, cap * 4, s);
+    A->ctx_offsets = DBuf(ctx, ((uint64_t)C + 1) * 8, s);
+    if (n == 0) {
+      HPA_HIP(hipMemsetAsync(A->ctx_offsets.p, 0, ((uint64_t)C + 1) * 8, s));
+      HPA_HIP(hipStreamSynchronize(s));
+      A->n_keys = 0;
+      *out = hold.release();
+      return;
+    }
+    // --- scan ctx, plan ---
+    const uint64_t run_cap = std::min<uint64_t>(std::max<uint64_t>(n / 8, 1024), 1ull << 24);
+    DBuf d_info(ctx, sizeof(PlanInfo), s);
+    DBuf d_hist(ctx, (uint64_t)C * 8, s);
+    DBuf d_runs(ctx, run_cap * sizeof(Run), s);
+    HPA_HIP(hipMemsetAsync(d_info.p, 0, sizeof(PlanInfo), s));
+    HPA_HIP(hipMemsetAsync(d_hist.p, 0, (uint64_t)C * 8, s));
+    {
+      uint64_t tiles = (n + SCAN_TILE - 1) / SCAN_TILE;
+      unsigned grid = (unsigned)std::min<uint64_t>(tiles, (uint64_t)ctx->n_cu * 8);
+      k_scan_ctx<<<grid, SCAN_BLOCK, 0, s>>>(smp->ctx, n, C, d_hist.as<unsigned long long>(), d_runs.as<Run>(),
+                                             run_cap, d_info.as<PlanInfo>());
+      HPA_HIP(hipGetLastError());
+    }
+    // the run/scatter decision needs the run count: read it with the plan
+    DBuf d_sbase(ctx, ((uint64_t)C + 1) * 8, s);
+    DBuf d_rbase(ctx, ((uint64_t)C + 1) * 8, s);
+    DBuf d_ubeg(ctx, ((uint64_t)C + 1) * 4, s);
+    DBuf d_ubig(ctx, ((uint64_t)C + 1) * 4, s);
+    DBuf d_bctx(ctx, ((uint64_t)C + 1) * 4, s);
+    DBuf d_bsb(ctx, ((uint64_t)C + 1) * 8, s);
+    DBuf d_bch(ctx, ((uint64_t)C + 1) * 8, s);
+    k_plan<<<1, PLAN_BLOCK, 0, s>>>(d_hist.as<unsigned long long>(), C, d_sbase.as<uint64_t>(),
+                                    d_rbase.as<uint64_t>(), d_ubeg.as<uint32_t>(), d_ubig.as<int32_t>(),
+                                    d_bctx.as<uint32_t>(), d_bsb.as<uint64_t>(), d_bch.as<uint64_t>(),
+                                    d_info.as<PlanInfo>());
+    HPA_HIP(hipGetLastError());
+    PlanInfo info;
+    HPA_HIP(hipMemcpyAsync(&info, d_info.p, sizeof(info), hipMemcpyDeviceToHost, s));
+    HPA_HIP(hipStreamSynchronize(s));
+    if (info.err & ERR_CTX) fail(HPA_E_INVAL, "a sample has ctx >= n_ctx");
+    const bool scattered = info.n_runs > run_cap;
+    // --- order samples by context ---
+    DBuf d_cur(ctx, (uint64_t)C * 8, s);
+    HPA_HIP(hipMemsetAsync(d_cur.p, 0, (uint64_t)C * 8, s));
+    DBuf d_grp, d_spc, d_sst, d_sw;
+    const bool weighted = smp->weight != nullptr;
+    const uint64_t* src_pc = smp->pc;
+    const uint8_t* src_st = smp->stall;
+    const uint32_t* src_w = smp->weight;
+    if (!scattered) {
+      d_grp = DBuf(ctx, std::max<uint64_t>(info.n_runs, 1) * sizeof(Run), s);
+      k_group_runs<<<grid_for(info.n_runs, 256, ctx->n_cu * 8), 256, 0, s>>>(
+          d_runs.as<Run>(), info.n_runs, d_sbase.as<uint64_t>(), d_rbase.as<uint64_t>(),
+          d_cur.as<unsigned long long>(), d_grp.as<Run>());
+      HPA_HIP(hipGetLastError());
+    } else {
+      d_spc = DBuf(ctx, n * 8, s);
+      d_sst = DBuf(ctx, n, s);
+      if (weighted) d_sw = DBuf(ctx, n * 4, s);
+      k_scatter<<<grid_for(n, 256, ctx->n_cu * 16), 256, 0, s>>>(
+          smp->pc, smp->ctx, smp->stall, smp->weight, n, d_sbase.as<uint64_t>(), d_cur.as<unsigned long long>(),
+          d_spc.as<uint64_t>(), d_sst.as<uint8_t>(), weighted ? d_sw.as<uint32_t>() : nullptr, C);
+      HPA_HIP(hipGetLastError());
+      src_pc = d_spc.as<uint64_t>();
+      src_st = d_sst.as<uint8_t>();
+      src_w = weighted ? d_sw.as<uint32_t>() : nullptr;
+    }
+    d_runs.release();
+    // --- big contexts ---
+    DBuf d_bigU(ctx, ((uint64_t)info.n_big + 1) * 8, s);
+    DBuf d_bigout(ctx, ((uint64_t)info.n_big + 1) * 8, s);
+    DBuf d_slot;
+    ListBuf L[2] = {};
+    DBuf lbuf[2][4];
+    int fin = 0;
+    BigArgs ba{src_pc, src_st, src_w, d_sbase.as<uint64_t>(), d_rbase.as<uint64_t>(), d_grp.as<Run>(),
+               d_bctx.as<uint32_t>(), d_bsb.as<uint64_t>(), d_bch.as<uint64_t>(), info.n_big, info.n_chunks,
+               d_info.as<PlanInfo>()};
+    if (info.n_big) {
+      const uint64_t bs = info.big_samples;
+      for (int k = 0; k < 2; ++k) {
+        lbuf[k][0] = DBuf(ctx, bs * 8, s);
+        lbuf[k][1] = DBuf(ctx, bs, s);
+        lbuf[k][2] = DBuf(ctx, bs * 8, s);
+        lbuf[k][3] = DBuf(ctx, info.n_chunks * 8, s);
+        L[k] = ListBuf{lbuf[k][0].as<uint64_t>(), lbuf[k][1].as<uint8_t>(),
+                       lbuf[k][2].as<unsigned long long>(), lbuf[k][3].as<uint64_t>()};
+      }
+      unsigned g = (unsigned)info.n_chunks;
+      if (weighted) {
+        if (scattered) k_big_chunks<true, true><<<g, UBLOCK, 0, s>>>(ba, L[0]);
+        else k_big_chunks<true, false><<<g, UBLOCK, 0, s>>>(ba, L[0]);
+      } else {
+        if (scattered) k_big_chunks<false, true><<<g, UBLOCK, 0, s>>>(ba, L[0]);
+        else k_big_chunks<false, false><<<g, UBLOCK, 0, s>>>(ba, L[0]);
+      }
+      HPA_HIP(hipGetLastError());
+      int r = 0;
+      while ((1ull << r) < info.max_chunks) {
+        k_big_merge<<<g, 256, 0, s>>>(ba, L[fin], L[fin ^ 1], r);
+        HPA_HIP(hipGetLastError());
+        fin ^= 1;
+        ++r;
+      }
+      d_slot = DBuf(ctx, info.n_chunks * 8, s);
+      k_big_heads<<<g, 256, 0, s>>>(ba, L[fin], d_slot.as<unsigned long long>());
+      k_big_scan<<<1, 1024, 0, s>>>(ba, d_slot.as<unsigned long long>(), d_bigU.as<uint64_t>());
+      HPA_HIP(hipGetLastError());
+    }
+    // --- ordered unit pass ---
+    DBuf d_status(ctx, (uint64_t)info.n_units * 8, s);
+    DBuf d_ticket(ctx, 8, s);
+    HPA_HIP(hipMemsetAsync(d_status.p, 0, (uint64_t)info.n_units * 8, s));
+    HPA_HIP(hipMemsetAsync(d_ticket.p, 0, 8, s));
+    MapDev md{map->start.as<uint64_t>(), map->end.as<uint64_t>(), map->scope.as<uint32_t>(), map->n_iv};
+    OutDev od{A->ctx_id.as<uint32_t>(), A->pc.as<uint64_t>(), A->stall.as<uint8_t>(),
+              A->count.as<unsigned long long>(), A->scope.as<uint32_t>(), A->ctx_offsets.as<uint64_t>()};
+    UnitArgs ua{src_pc, src_st, src_w, d_sbase.as<uint64_t>(), d_rbase.as<uint64_t>(), d_grp.as<Run>(),
+                d_ubeg.as<uint32_t>(), d_ubig.as<int32_t>(), d_bigU.as<uint64_t>(), d_bigout.as<uint64_t>(),
+                d_status.as<unsigned long long>(), d_ticket.as<unsigned int>(), d_info.as<PlanInfo>(),
+                info.n_units, C, md, od};
+    {
+      unsigned g = info.n_units;
+      if (weighted) {
+        if (scattered) k_units32<true, true><<<g, UBLOCK, 0, s>>>(ua);
+        else k_units32<true, false><<<g, UBLOCK, 0, s>>>(ua);
+      } else {
+        if (scattered) k_units32<false, true><<<g, UBLOCK, 0, s>>>(ua);
+        else k_units32<false, false><<<g, UBLOCK, 0, s>>>(ua);
+      }
+      HPA_HIP(hipGetLastError());
+    }
+    if (info.n_big) {
+      k_big_write<<<(unsigned)info.n_chunks, 256, 0, s>>>(ba, L[fin], d_slot.as<unsigned long long>(),
+                                                        d_bigout.as<uint64_t>(), md, od);
+      HPA_HIP(hipGetLastError());
+    }
+    HPA_HIP(hipMemcpyAsync(&info, d_info.p, sizeof(info), hipMemcpyDeviceToHost, s));
+    HPA_HIP(hipStreamSynchronize(s));
+    if (info.err & ERR_STALL) fail(HPA_E_INVAL, "a sample has stall >= 16");
+    if (info.err & ERR_WIDE) fail(HPA_E_UNSUPPORTED, "the PCs of one context span more than 2^56 bytes");
+    A->n_keys = info.total_keys;
+    *out = hold.release();
+  });
+}
+
+extern "C" hpa_status hpa_attribution_view_get(const hpa_attribution* a, hpa_attribution_view* v) {
+  return guard([&] {
+    if (!a || !v) fail(HPA_E_INVAL, "NULL argument");
+    v->n_keys = a->n_keys;
+    v->n_ctx = a->n_ctx;
+    v->ctx = a->ctx_id.as<uint32_t>();
+    v->pc = a->pc.as<uint64_t>();
+    v->stall = a->stall.as<uint8_t>();
+    v->count = a->count.as<uint64_t>();
+    v->scope = a->scope.as<uint32_t>();
+    v->ctx_offsets = a->ctx_offsets.as<uint64_t>();
+  });
+}
+
+extern "C" void hpa_attribution_free(hpa_attribution* a) { delete a; }

@@ -1,0 +1,357 @@
+// Context, allocator, errors, structure map (A1) and plain interval lookup (A3).
+#include <algorithm>
+#include <limits>
+#include <map>
+#include <queue>
+
+#include "hpa_internal.h"
+
+namespace hpa {
+
+static thread_local std::string g_last_error;
+
+void set_last_error(const std::string& msg) { g_last_error = msg; }
+
+void fail(hpa_status s, const std::string& msg) { throw Error{s, msg}; }
+
+void* dalloc(hpa_ctx* ctx, size_t bytes, hipStream_t s) {
+  void* p = nullptr;
+  if (ctx->custom) {
+    p = ctx->alloc.alloc(bytes, s, ctx->alloc.user);
+    if (!p) fail(HPA_E_NOMEM, "allocator returned NULL for " + std::to_string(bytes) + " bytes");
+    return p;
+  }
+  hipError_t e = hipMallocAsync(&p, bytes, s);
+  if (e == hipErrorOutOfMemory || (e == hipSuccess && !p))
+    fail(HPA_E_NOMEM, "device allocation of " + std::to_string(bytes) + " bytes failed");
+  if (e != hipSuccess) fail(HPA_E_DEVICE, std::string("hipMallocAsync: ") + hipGetErrorString(e));
+  return p;
+}
+
+void dfree(hpa_ctx* ctx, void* p, hipStream_t s) {
+  if (!p) return;
+  if (ctx->custom) ctx->alloc.free(p, s, ctx->alloc.user);
+  else (void)hipFreeAsync(p, s);
+}
+
+}  // namespace hpa
+
+using namespace hpa;
+
+extern "C" const char* hpa_last_error(void) { return g_last_error.c_str(); }
+
+extern "C" hpa_status hpa_ctx_create(int device, const hpa_allocator* alloc, hpa_ctx** out) {
+  return guard([&] {
+    if (!out) fail(HPA_E_INVAL, "out is NULL");
+    int n = 0;
+    HPA_HIP(hipGetDeviceCount(&n));
+    if (device < 0 || device >= n) fail(HPA_E_INVAL, "no such device");
+    if (alloc && (!alloc->alloc || !alloc->free)) fail(HPA_E_INVAL, "allocator needs alloc and free");
+    DeviceGuard g(device);
+    auto* c = new hpa_ctx();
+    c->device = device;
+    if (alloc) { c->alloc = *alloc; c->custom = true; }
+    hipDeviceProp_t prop;
+    HPA_HIP(hipGetDeviceProperties(&prop, device));
+    c->n_cu = prop.multiProcessorCount;
+    if (!alloc) {
+      hipMemPool_t pool;
+      HPA_HIP(hipDeviceGetDefaultMemPool(&pool, device));
+      uint64_t thr = std::numeric_limits<uint64_t>::max();
+      HPA_HIP(hipMemPoolSetAttribute(pool, hipMemPoolAttrReleaseThreshold, &thr));
+    }
+    *out = c;
+  });
+}
+
+extern "C" void hpa_ctx_destroy(hpa_ctx* ctx) { delete ctx; }
+
+// ---------------------------------------------------------------------------
+// A1: structure map (Section 5 function relocation/splitting, line map and
+// inlined code; Section 6.1 calling-context expansion).  Host sweep over the
+// sorted boundaries of every range.
+// ---------------------------------------------------------------------------
+namespace {
+
+struct R {
+  uint64_t s, e;
+  uint32_t id, kind;
+};
+
+struct Built {
+  std::vector<uint64_t> start, end;
+  std::vector<uint32_t> scope, file, line;
+  std::vector<uint32_t> parent, func;
+  std::vector<uint8_t> kind;
+  uint32_t n_ids = 0;
+};
+
+void sweep(const hpa_structure_desc& d, Built& out) {
+  std::vector<R> fn, nest;
+  std::vector<uint8_t> kind_of;
+  for (uint64_t i = 0; i < d.n_scopes; ++i) {
+    const hpa_scope& s = d.scopes[i];
+    if (s.start >= s.end) fail(HPA_E_INVAL, "scope " + std::to_string(i) + " has start >= end");
+    if (s.kind > HPA_LOOP) fail(HPA_E_INVAL, "scope " + std::to_string(i) + " has an unknown kind");
+    if (s.id >= 0x7FFFFFFFu) fail(HPA_E_INVAL, "scope id too large");
+    if (s.id >= kind_of.size()) kind_of.resize((size_t)s.id + 1, 0xFF);
+    if (kind_of[s.id] != 0xFF && kind_of[s.id] != s.kind)
+      fail(HPA_E_INVAL, "scope id " + std::to_string(s.id) + " used with two kinds");
+    kind_of[s.id] = (uint8_t)s.kind;
+    (s.kind == HPA_FUNC ? fn : nest).push_back(R{s.start, s.end, s.id, s.kind});
+  }
+  const uint32_t n_ids = (uint32_t)kind_of.size();
+  std::vector<uint32_t> lo(d.n_lines);
+  for (uint64_t i = 0; i < d.n_lines; ++i) {
+    if (d.lines[i].start >= d.lines[i].end) fail(HPA_E_INVAL, "line range has start >= end");
+    lo[i] = (uint32_t)i;
+  }
+  std::sort(lo.begin(), lo.end(), [&](uint32_t a, uint32_t b) { return d.lines[a].start < d.lines[b].start; });
+  for (size_t i = 1; i < lo.size(); ++i)
+    if (d.lines[lo[i]].start < d.lines[lo[i - 1]].end) fail(HPA_E_OVERLAP, "line ranges overlap");
+
+  // boundaries
+  std::vector<uint64_t> B;
+  B.reserve(2 * (fn.size() + nest.size() + lo.size()));
+  for (auto& r : fn) { B.push_back(r.s); B.push_back(r.e); }
+  for (auto& r : nest) { B.push_back(r.s); B.push_back(r.e); }
+  for (uint32_t i : lo) { B.push_back(d.lines[i].start); B.push_back(d.lines[i].end); }
+  std::sort(B.begin(), B.end());
+  B.erase(std::unique(B.begin(), B.end()), B.end());
+
+  // functions by start; nested ranges by (start asc, end desc, kind asc, id asc): outer first
+  std::sort(fn.begin(), fn.end(), [](const R& a, const R& b) { return a.s < b.s; });
+  std::sort(nest.begin(), nest.end(), [](const R& a, const R& b) {
+    if (a.s != b.s) return a.s < b.s;
+    if (a.e != b.e) return a.e > b.e;
+    if (a.kind != b.kind) return a.kind < b.kind;
+    return a.id < b.id;
+  });
+  // owner priority: larger start, then smaller end, then smaller id
+  auto worse = [](const R& a, const R& b) {
+    if (a.s != b.s) return a.s < b.s;
+    if (a.e != b.e) return a.e > b.e;
+    return a.id > b.id;
+  };
+  std::priority_queue<R, std::vector<R>, decltype(worse)> heap(worse);
+
+  out.parent.assign(n_ids, NONE32);
+  out.func.assign(n_ids, NONE32);
+  out.kind = kind_of;
+  out.n_ids = n_ids;
+  std::vector<uint8_t> placed(n_ids, 0);
+  for (auto& r : fn) out.func[r.id] = r.id;
+
+  struct Open {
+    R r;
+    uint32_t owner;
+  };
+  std::vector<Open> chain;  // open nested ranges, outermost first
+  size_t fi = 0, ni = 0, li = 0;
+  for (size_t b = 0; b + 1 < B.size(); ++b) {
+    const uint64_t x = B[b], y = B[b + 1];
+    while (fi < fn.size() && fn[fi].s == x) heap.push(fn[fi++]);
+    while (!heap.empty() && heap.top().e <= x) heap.pop();
+    const uint32_t owner = heap.empty() ? NONE32 : heap.top().id;
+    while (!chain.empty() && chain.back().r.e <= x) chain.pop_back();
+    // every open nested range must keep one owning function over all its addresses
+    if (!chain.empty() && chain.back().owner != owner)
+      fail(HPA_E_NOT_LAMINAR, "scope " + std::to_string(chain.back().r.id) + " spans addresses of another function");
+    while (ni < nest.size() && nest[ni].s == x) {
+      const R& r = nest[ni++];
+      if (!chain.empty() && (r.e > chain.back().r.e || chain.back().r.id == r.id))
+        fail(HPA_E_NOT_LAMINAR, "scope " + std::to_string(r.id) + " crosses scope " + std::to_string(chain.back().r.id));
+      if (owner == NONE32) fail(HPA_E_NOT_LAMINAR, "scope " + std::to_string(r.id) + " starts outside every function");
+      uint32_t par = chain.empty() ? owner : chain.back().r.id;
+      if (placed[r.id] && (out.parent[r.id] != par || out.func[r.id] != owner))
+        fail(HPA_E_NOT_LAMINAR, "ranges of scope " + std::to_string(r.id) + " have different parents");
+      placed[r.id] = 1;
+      out.parent[r.id] = par;
+      out.func[r.id] = owner;
+      chain.push_back(Open{r, owner});
+    }
+    if (owner == NONE32) continue;
+    while (li < lo.size() && d.lines[lo[li]].end <= x) ++li;
+    uint32_t f = 0, l = 0;
+    if (li < lo.size() && d.lines[lo[li]].start <= x) { f = d.lines[lo[li]].file; l = d.lines[lo[li]].line; }
+    const uint32_t sc = chain.empty() ? owner : chain.back().r.id;
+    if (!out.start.empty() && out.end.back() == x && out.scope.back() == sc && out.file.back() == f &&
+        out.line.back() == l) {
+      out.end.back() = y;
+    } else {
+      out.start.push_back(x); out.end.push_back(y);
+      out.scope.push_back(sc); out.file.push_back(f); out.line.push_back(l);
+    }
+  }
+  if (ni < nest.size()) fail(HPA_E_NOT_LAMINAR, "scope outside every function");
+}
+
+void from_intervals(const hpa_structure_desc& d, Built& out) {
+  for (uint64_t i = 0; i < d.n_iv; ++i) {
+    if (d.iv_start[i] >= d.iv_end[i]) fail(HPA_E_INVAL, "interval has start >= end");
+    if (i && d.iv_start[i] <= d.iv_start[i - 1]) fail(HPA_E_UNSORTED, "intervals not sorted by start");
+    if (i && d.iv_start[i] < d.iv_end[i - 1]) fail(HPA_E_OVERLAP, "intervals overlap");
+  }
+  out.start.assign(d.iv_start, d.iv_start + d.n_iv);
+  out.end.assign(d.iv_end, d.iv_end + d.n_iv);
+  out.scope.resize(d.n_iv);
+  for (uint64_t i = 0; i < d.n_iv; ++i) out.scope[i] = (uint32_t)i;
+  out.file.assign(d.n_iv, 0);
+  out.line.assign(d.n_iv, 0);
+}
+
+}  // namespace
+
+namespace hpa {
+void learned_train(hpa_structure_map* m, hipStream_t s);
+}
+
+hpa_structure_map::~hpa_structure_map() {
+  if (learned) hpa::learned_free(learned);
+}
+
+extern "C" hpa_status hpa_build_structure_map(hpa_ctx* ctx, const hpa_structure_desc* desc, hipStream_t stream,
+                                              hpa_structure_map** out) {
+  return guard([&] {
+    if (!ctx || !desc || !out) fail(HPA_E_INVAL, "NULL argument");
+    if (desc->n_iv && (desc->n_scopes || desc->n_lines))
+      fail(HPA_E_INVAL, "give either scopes/lines or prebuilt intervals");
+    if ((desc->n_scopes && !desc->scopes) || (desc->n_lines && !desc->lines) ||
+        (desc->n_iv && (!desc->iv_start || !desc->iv_end)))
+      fail(HPA_E_INVAL, "NULL array with nonzero count");
+    if (desc->n_iv >= NONE32 || desc->n_scopes >= NONE32 / 4) fail(HPA_E_INVAL, "too many intervals");
+    DeviceGuard g(ctx->device);
+    Built b;
+    if (desc->n_iv) from_intervals(*desc, b);
+    else sweep(*desc, b);
+    auto* m = new hpa_structure_map();
+    try {
+      m->ctx = ctx;
+      m->stream = stream;
+      m->n_iv = b.start.size();
+      m->n_ids = b.n_ids;
+      m->prebuilt = desc->n_iv != 0;
+      m->start = upload(ctx, b.start, stream);
+      m->end = upload(ctx, b.end, stream);
+      m->scope = upload(ctx, b.scope, stream);
+      m->file = upload(ctx, b.file, stream);
+      m->line = upload(ctx, b.line, stream);
+      m->parent = upload(ctx, b.parent, stream);
+      m->kind = upload(ctx, b.kind, stream);
+      m->func = upload(ctx, b.func, stream);
+      // first search level: every 2^k-th start, small enough for a cache-resident table
+      uint32_t shift = 0;
+      while ((m->n_iv >> shift) > 4096) ++shift;
+      std::vector<uint64_t> top;
+      for (uint64_t i = 0; i < m->n_iv; i += (1ull << shift)) top.push_back(b.start[i]);
+      m->top_n = (uint32_t)top.size();
+      m->top_shift = shift;
+      m->top = upload(ctx, top, stream);
+      m->h_parent = b.parent;
+      m->h_func = b.func;
+      m->h_kind = b.kind;
+      m->h_start = std::move(b.start);
+      m->h_end = std::move(b.end);
+      m->h_scope = std::move(b.scope);
+      if (desc->learned) learned_train(m, stream);
+      HPA_HIP(hipStreamSynchronize(stream));
+    } catch (...) {
+      delete m;
+      throw;
+    }
+    *out = m;
+  });
+}
+
+extern "C" hpa_status hpa_structure_map_view_get(const hpa_structure_map* m, hpa_structure_map_view* v) {
+  return guard([&] {
+    if (!m || !v) fail(HPA_E_INVAL, "NULL argument");
+    v->n_intervals = m->n_iv;
+    v->n_scope_ids = m->n_ids;
+    v->start = m->start.as<uint64_t>();
+    v->end = m->end.as<uint64_t>();
+    v->scope = m->scope.as<uint32_t>();
+    v->file = m->file.as<uint32_t>();
+    v->line = m->line.as<uint32_t>();
+    v->parent = m->parent.as<uint32_t>();
+    v->kind = m->kind.as<uint8_t>();
+    v->func = m->func.as<uint32_t>();
+  });
+}
+
+extern "C" void hpa_structure_map_free(hpa_structure_map* m) { delete m; }
+
+// ---------------------------------------------------------------------------
+// A3 plain lookup: a two-level binary search.  The first level searches a
+// table of every 2^k-th start (<= 4096 entries, 32 KB) staged in LDS; the
+// second level finishes inside one block of 2^k starts in global memory.
+// ---------------------------------------------------------------------------
+namespace {
+
+constexpr int LOOKUP_BLOCK = 256;
+
+__global__ void __launch_bounds__(LOOKUP_BLOCK)
+k_lookup_plain(const uint64_t* __restrict__ start, const uint64_t* __restrict__ end, uint64_t n_iv,
+               const uint64_t* __restrict__ top, uint32_t top_n, uint32_t shift,
+               const uint64_t* __restrict__ pc, uint64_t n, uint32_t* __restrict__ out) {
+  __shared__ uint64_t s_top[4096];
+  for (uint32_t i = threadIdx.x; i < top_n; i += LOOKUP_BLOCK) s_top[i] = top[i];
+  __syncthreads();
+  const uint64_t stride = (uint64_t)gridDim.x * LOOKUP_BLOCK;
+  for (uint64_t i = (uint64_t)blockIdx.x * LOOKUP_BLOCK + threadIdx.x; i < n; i += stride) {
+    const uint64_t q = pc[i];
+    // number of top entries <= q
+    uint32_t lo = 0, hi = top_n;
+    while (lo < hi) {
+      uint32_t mid = (lo + hi) >> 1;
+      if (s_top[mid] <= q) lo = mid + 1;
+      else hi = mid;
+    }
+    uint32_t r;
+    if (lo == 0) {
+      r = NONE32;
+    } else {
+      uint64_t b = (uint64_t)(lo - 1) << shift;
+      uint64_t e = b + (1ull << shift);
+      if (e > n_iv) e = n_iv;
+      r = find_interval(start, end, n_iv, q, b + 1, e);
+    }
+    out[i] = r;
+  }
+}
+
+}  // namespace
+
+namespace hpa {
+
+void launch_lookup_plain(const hpa_structure_map* m, const uint64_t* pc, uint64_t n, uint32_t* out, hipStream_t s) {
+  if (n == 0) return;
+  if (m->n_iv == 0) {
+    HPA_HIP(hipMemsetAsync(out, 0xFF, n * sizeof(uint32_t), s));
+    return;
+  }
+  unsigned grid = grid_for(n, LOOKUP_BLOCK, (unsigned)m->ctx->n_cu * 16);
+  k_lookup_plain<<<grid, LOOKUP_BLOCK, 0, s>>>(m->start.as<uint64_t>(), m->end.as<uint64_t>(), m->n_iv,
+                                               m->top.as<uint64_t>(), m->top_n, m->top_shift, pc, n, out);
+  HPA_HIP(hipGetLastError());
+}
+
+}  // namespace hpa
+
+extern "C" hpa_status hpa_lookup_intervals(hpa_ctx* ctx, const hpa_structure_map* map, const uint64_t* d_pc,
+                                           uint64_t n, uint32_t* d_out, int mode, hipStream_t stream) {
+  return guard([&] {
+    if (!ctx || !map) fail(HPA_E_INVAL, "NULL argument");
+    if (n && (!d_pc || !d_out)) fail(HPA_E_INVAL, "NULL array with n > 0");
+    if (map->ctx != ctx) fail(HPA_E_INVAL, "map belongs to another context");
+    DeviceGuard g(ctx->device);
+    if (mode == HPA_LOOKUP_PLAIN) {
+      launch_lookup_plain(map, d_pc, n, d_out, stream);
+    } else if (mode == HPA_LOOKUP_LEARNED) {
+      if (!map->learned) fail(HPA_E_UNSUPPORTED, "map was built without the learned index");
+      launch_lookup_learned(map, d_pc, n, d_out, stream);
+    } else {
+      fail(HPA_E_INVAL, "unknown lookup mode");
+    }
+  });
+}

@@ -1,0 +1,169 @@
+// Internal declarations shared by the library's translation units.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+#include <cstring>
+#include <string>
+#include <utility>
+#include <vector>
+
+#include "hpa.h"
+
+namespace hpa {
+
+constexpr uint32_t NONE32 = 0xFFFFFFFFu;
+constexpr uint64_t NONE64 = 0xFFFFFFFFFFFFFFFFull;
+constexpr int NS = 16;
+
+struct Error {
+  hpa_status status;
+  std::string msg;
+};
+
+[[noreturn]] void fail(hpa_status s, const std::string& msg);
+void set_last_error(const std::string& msg);
+
+#define HPA_HIP(call)                                                                          \
+  do {                                                                                         \
+    hipError_t e_ = (call);                                                                    \
+    if (e_ != hipSuccess)                                                                      \
+      ::hpa::fail(HPA_E_DEVICE, std::string(#call) + ": " + hipGetErrorString(e_));            \
+  } while (0)
+
+// Run `body` and translate exceptions into a status + thread-local message.
+template <class F>
+hpa_status guard(F&& body) {
+  try {
+    body();
+    return HPA_OK;
+  } catch (const Error& e) {
+    set_last_error(e.msg);
+    return e.status;
+  } catch (const std::bad_alloc&) {
+    set_last_error("host allocation failed");
+    return HPA_E_NOMEM;
+  } catch (const std::exception& e) {
+    set_last_error(e.what());
+    return HPA_E_DEVICE;
+  }
+}
+
+}  // namespace hpa
+
+struct hpa_ctx {
+  int device = 0;
+  hpa_allocator alloc{};
+  bool custom = false;
+  int n_cu = 256;
+};
+
+namespace hpa {
+
+void* dalloc(hpa_ctx* ctx, size_t bytes, hipStream_t s);
+void dfree(hpa_ctx* ctx, void* p, hipStream_t s);
+
+// Stream-ordered device buffer owned by a scope or a handle.
+struct DBuf {
+  hpa_ctx* ctx = nullptr;
+  hipStream_t stream = nullptr;
+  void* p = nullptr;
+  size_t bytes = 0;
+  DBuf() = default;
+  DBuf(hpa_ctx* c, size_t n, hipStream_t s) : ctx(c), stream(s), bytes(n) { p = n ? dalloc(c, n, s) : nullptr; }
+  DBuf(const DBuf&) = delete;
+  DBuf& operator=(const DBuf&) = delete;
+  DBuf(DBuf&& o) noexcept { *this = std::move(o); }
+  DBuf& operator=(DBuf&& o) noexcept {
+    release();
+    ctx = o.ctx; stream = o.stream; p = o.p; bytes = o.bytes;
+    o.p = nullptr; o.bytes = 0;
+    return *this;
+  }
+  ~DBuf() { release(); }
+  void release() {
+    if (p) dfree(ctx, p, stream);
+    p = nullptr;
+    bytes = 0;
+  }
+  template <class T>
+  T* as() const { return static_cast<T*>(p); }
+};
+
+template <class T>
+DBuf upload(hpa_ctx* ctx, const std::vector<T>& v, hipStream_t s) {
+  DBuf b(ctx, v.size() * sizeof(T), s);
+  if (!v.empty()) HPA_HIP(hipMemcpyAsync(b.p, v.data(), v.size() * sizeof(T), hipMemcpyHostToDevice, s));
+  return b;
+}
+
+struct DeviceGuard {
+  int prev = 0;
+  explicit DeviceGuard(int dev) {
+    HPA_HIP(hipGetDevice(&prev));
+    if (prev != dev) HPA_HIP(hipSetDevice(dev));
+  }
+  ~DeviceGuard() { (void)hipSetDevice(prev); }
+};
+
+inline unsigned grid_for(uint64_t n, unsigned block, unsigned cap = 1u << 20) {
+  uint64_t g = (n + block - 1) / block;
+  if (g == 0) g = 1;
+  return (unsigned)(g < cap ? g : cap);
+}
+
+// Learned interval index (device side), see learned.hip.
+struct LearnedModel;
+
+}  // namespace hpa
+
+struct hpa_structure_map {
+  hpa_ctx* ctx = nullptr;
+  hipStream_t stream = nullptr;
+  uint64_t n_iv = 0;
+  uint32_t n_ids = 0;
+  bool prebuilt = false;
+  hpa::DBuf start, end, scope, file, line;  // intervals
+  hpa::DBuf parent, kind, func;             // scope table
+  hpa::DBuf top;                            // sampled starts for the first search level
+  uint32_t top_n = 0, top_shift = 0;
+  hpa::LearnedModel* learned = nullptr;
+  std::vector<uint32_t> h_parent, h_func;   // host copies of the scope table
+  std::vector<uint8_t> h_kind;
+  std::vector<uint64_t> h_start, h_end;     // host copies of the intervals
+  std::vector<uint32_t> h_scope;
+  ~hpa_structure_map();
+};
+
+struct hpa_attribution {
+  hpa_ctx* ctx = nullptr;
+  hipStream_t stream = nullptr;
+  const hpa_structure_map* map = nullptr;
+  uint64_t n_keys = 0;
+  uint32_t n_ctx = 0;
+  hpa::DBuf ctx_id, pc, stall, count, scope, ctx_offsets;
+};
+
+namespace hpa {
+
+// Plain lookup used by several kernels: interval index of pc or NONE32.
+__device__ inline uint32_t find_interval(const uint64_t* __restrict__ start, const uint64_t* __restrict__ end,
+                                         uint64_t n, uint64_t pc, uint64_t lo, uint64_t hi) {
+  // invariant: answer (last start <= pc) lies in [lo - 1, hi - 1]
+  while (lo < hi) {
+    uint64_t mid = (lo + hi) >> 1;
+    if (start[mid] <= pc) lo = mid + 1;
+    else hi = mid;
+  }
+  if (lo == 0) return NONE32;
+  uint64_t i = lo - 1;
+  return pc < end[i] ? (uint32_t)i : NONE32;
+}
+
+void launch_lookup_plain(const hpa_structure_map* m, const uint64_t* pc, uint64_t n, uint32_t* out, hipStream_t s);
+void launch_lookup_learned(const hpa_structure_map* m, const uint64_t* pc, uint64_t n, uint32_t* out,
+                           hipStream_t s);
+void learned_free(LearnedModel* lm);
+
+}  // namespace hpa

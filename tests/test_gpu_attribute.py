@@ -1,0 +1,187 @@
+"""GPU parity of the structure map, interval lookup and attribution (A1-A4)
+against the CPU oracle, through the C ABI.  Integer results must match bit for bit."""
+import numpy as np
+import pytest
+
+import oracle
+from workloads import config1, small_config, tiny_random_case
+from workloads import handmade
+from workloads.gen import FUNC
+
+from .parity import assert_attribution_equal
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+
+
+@pytest.fixture(scope="module")
+def hpa():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    import paper_2109_06931_amd as hpa
+    hpa.lib()
+    return hpa
+
+
+@pytest.fixture(scope="module")
+def hctx(hpa):
+    return hpa.Context(0)
+
+
+def _run(hpa, hctx, w, weighted=None):
+    m = hpa.build_structure_map_workload(hctx, w)
+    om = oracle.build_map_workload(w)
+    pc, cx, st, wt = hpa.samples_to_device(w)
+    a = hpa.attribute(hctx, m, pc, cx, st, wt, w.n_ctx)
+    torch.cuda.synchronize()
+    oa = oracle.attribute(om, w.pc, w.ctx, w.stall, w.weight, w.n_ctx)
+    return m, om, a, oa
+
+
+@pytest.mark.parametrize("seed", [0, 1, 2, 3])
+def test_structure_map_matches_oracle(hpa, hctx, seed):
+    w = small_config(seed, n_samples=0) if seed else config1(n_samples=0)
+    m = hpa.build_structure_map_workload(hctx, w)
+    om = oracle.build_map_workload(w)
+    t = {k: v.cpu().numpy() for k, v in m.tensors().items()}
+    for f in ["start", "end", "scope", "file", "line", "parent", "kind", "func"]:
+        assert np.array_equal(t[f], getattr(om, f)), f
+
+
+def test_structure_map_errors(hpa, hctx):
+    cases = [
+        (dict(scope_start=[0, 16, 48], scope_end=[256, 96, 128], scope_id=[0, 1, 2], scope_kind=[0, 2, 2]),
+         hpa.E_NOT_LAMINAR),
+        (dict(scope_start=[0, 64, 32], scope_end=[256, 128, 96], scope_id=[0, 1, 2], scope_kind=[0, 0, 1]),
+         hpa.E_NOT_LAMINAR),
+        (dict(scope_start=[0, 32], scope_end=[256, 32], scope_id=[0, 1], scope_kind=[0, 2]), hpa.E_INVAL),
+        (dict(scope_start=[0], scope_end=[256], scope_id=[0], scope_kind=[0], line_start=[0, 32],
+              line_end=[64, 96], line_file=[1, 1], line_line=[1, 2]), hpa.E_OVERLAP),
+        (dict(iv_start=[10, 5], iv_end=[12, 8]), hpa.E_UNSORTED),
+        (dict(iv_start=[10, 11], iv_end=[12, 13]), hpa.E_OVERLAP),
+    ]
+    for kw, code in cases:
+        kw = {k: np.array(v) for k, v in kw.items()}
+        with pytest.raises(hpa.HpaError) as ei:
+            hpa.build_structure_map(hctx, **kw)
+        assert ei.value.code == code, kw
+
+
+@pytest.mark.parametrize("seed", [0, 1])
+def test_lookup_plain_matches_oracle(hpa, hctx, seed):
+    w = small_config(10 + seed, n_samples=0, n_funcs=3000, n_inst=200_000)
+    m = hpa.build_structure_map_workload(hctx, w)
+    om = oracle.build_map_workload(w)
+    r = np.random.default_rng(seed)
+    lo, hi = int(w.scope_start.min()) - 4096, int(w.scope_end.max()) + 4096
+    q = np.concatenate([r.integers(lo, hi, 200_000, dtype=np.uint64), om.start, om.end, om.start - np.uint64(1),
+                        np.array([0, 2**64 - 1], np.uint64)])
+    qt = torch.from_numpy(q.view(np.int64)).cuda().view(torch.uint64)
+    out = torch.empty(len(q), dtype=torch.int32, device="cuda").view(torch.uint32)
+    hpa.lookup_intervals(hctx, m, qt, out)
+    assert np.array_equal(out.cpu().numpy(), oracle.lookup(om, q))
+
+
+def test_lookup_prebuilt_intervals(hpa, hctx):
+    s = np.array([10, 20, 40], np.uint64)
+    e = np.array([15, 40, 41], np.uint64)
+    m = hpa.build_structure_map(hctx, iv_start=s, iv_end=e)
+    q = np.array([9, 10, 14, 15, 19, 20, 39, 40, 41, 1 << 40], np.uint64)
+    qt = torch.from_numpy(q.view(np.int64)).cuda().view(torch.uint64)
+    out = torch.empty(len(q), dtype=torch.int32, device="cuda").view(torch.uint32)
+    hpa.lookup_intervals(hctx, m, qt, out)
+    assert out.cpu().numpy().tolist() == [0xFFFFFFFF, 0, 0, 0xFFFFFFFF, 0xFFFFFFFF, 1, 1, 2, 0xFFFFFFFF, 0xFFFFFFFF]
+
+
+@pytest.mark.parametrize("seed", list(range(6)))
+def test_attribute_tiny(hpa, hctx, seed):
+    w = tiny_random_case(seed, n_samples=2000 + 700 * seed, n_ctx=3 + seed, weighted=seed % 2 == 1)
+    m, om, a, oa = _run(hpa, hctx, w)
+    assert_attribution_equal(a.numpy(), oa, f"tiny{seed}")
+
+
+@pytest.mark.parametrize("seed,kw", [
+    (1, {}),
+    (2, dict(weighted=True)),
+    (3, dict(shuffled=True)),
+    (4, dict(seg_mean=20000.0)),
+    (5, dict(seg_mean=30.0)),
+])
+def test_attribute_small(hpa, hctx, seed, kw):
+    w = small_config(seed, n_samples=300_000, **kw)
+    m, om, a, oa = _run(hpa, hctx, w)
+    assert_attribution_equal(a.numpy(), oa, f"small{seed}{kw}")
+
+
+def test_attribute_config1(hpa, hctx):
+    w = config1()
+    m, om, a, oa = _run(hpa, hctx, w)
+    assert_attribution_equal(a.numpy(), oa, "config1")
+
+
+def test_attribute_one_giant_context(hpa, hctx):
+    # every sample under one placeholder: the chunk-sort and merge path only
+    w = small_config(21, n_samples=200_000, n_ctx=3, seg_mean=5000)
+    w.ctx[:] = 1
+    m, om, a, oa = _run(hpa, hctx, w)
+    assert_attribution_equal(a.numpy(), oa, "giant")
+
+
+def test_attribute_edge_cases(hpa, hctx):
+    w = tiny_random_case(7, n_samples=5000, n_ctx=5)
+    # all samples at unmapped PCs
+    w.pc[:] = np.uint64(0x10)
+    m, om, a, oa = _run(hpa, hctx, w)
+    assert_attribution_equal(a.numpy(), oa, "unmapped")
+    # a single key
+    w.pc[:] = w.scope_start[0]
+    w.ctx[:] = 2
+    w.stall[:] = 9
+    m, om, a, oa = _run(hpa, hctx, w)
+    assert_attribution_equal(a.numpy(), oa, "single key")
+    assert a.n_keys == 1
+    # many empty contexts around a few busy ones
+    w2 = tiny_random_case(8, n_samples=3000, n_ctx=4)
+    w2.ctx_parent = np.full(70_000, 0xFFFFFFFF, np.uint32)
+    w2.ctx_entry = np.full(70_000, -1, np.int32)
+    w2.ctx = (w2.ctx.astype(np.int64) * 17_000 + 3).astype(np.uint32)
+    m, om, a, oa = _run(hpa, hctx, w2)
+    assert_attribution_equal(a.numpy(), oa, "sparse contexts")
+
+
+def test_attribute_empty(hpa, hctx):
+    w = tiny_random_case(9, n_samples=10, n_ctx=3)
+    m = hpa.build_structure_map_workload(hctx, w)
+    e64 = torch.empty(0, dtype=torch.int64, device="cuda").view(torch.uint64)
+    e32 = torch.empty(0, dtype=torch.int32, device="cuda").view(torch.uint32)
+    e8 = torch.empty(0, dtype=torch.uint8, device="cuda")
+    a = hpa.attribute(hctx, m, e64, e32, e8, None, 3)
+    assert a.n_keys == 0
+    assert a.numpy()["ctx_offsets"].tolist() == [0, 0, 0, 0]
+
+
+def test_attribute_rejects_bad_records(hpa, hctx):
+    w = tiny_random_case(10, n_samples=1000, n_ctx=3)
+    m = hpa.build_structure_map_workload(hctx, w)
+    pc, cx, st, wt = hpa.samples_to_device(w)
+    st2 = st.clone()
+    st2[500] = 16
+    with pytest.raises(hpa.HpaError) as ei:
+        hpa.attribute(hctx, m, pc, cx, st2, None, 3)
+    assert ei.value.code == hpa.E_INVAL
+    cx2 = cx.clone()
+    cx2[10] = 3
+    with pytest.raises(hpa.HpaError) as ei:
+        hpa.attribute(hctx, m, pc, cx2, st, None, 3)
+    assert ei.value.code == hpa.E_INVAL
+
+
+def test_attribute_deterministic(hpa, hctx):
+    w = small_config(31, n_samples=200_000, shuffled=True)
+    m = hpa.build_structure_map_workload(hctx, w)
+    pc, cx, st, wt = hpa.samples_to_device(w)
+    r1 = hpa.attribute(hctx, m, pc, cx, st, None, w.n_ctx).numpy()
+    r2 = hpa.attribute(hctx, m, pc, cx, st, None, w.n_ctx).numpy()
+    for k in r1:
+        assert np.array_equal(r1[k], r2[k]), k
