@@ -14,7 +14,7 @@ import os
 import numpy as np
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
-LIB_PATH = os.path.join(_HERE, "libhpa.so")
+LIB_PATH = os.environ.get("HPA_LIBRARY") or os.path.join(_HERE, "libhpa.so")
 
 OK, E_INVAL, E_UNSORTED, E_OVERLAP, E_NOT_LAMINAR, E_NOMEM, E_BUDGET, E_DEVICE, E_UNSUPPORTED = (
     0, -1, -2, -3, -4, -5, -6, -7, -8)

@@ -36,8 +36,11 @@ constexpr int SCAN_BLOCK = 256;
 constexpr int SCAN_ITEMS = 16;
 constexpr int SCAN_TILE = SCAN_BLOCK * SCAN_ITEMS;  // samples per scan tile
 
+#ifndef HPA_UNIT_ITEMS
+#define HPA_UNIT_ITEMS 32
+#endif
 constexpr int UBLOCK = 512;
-constexpr int UITEMS = 16;
+constexpr int UITEMS = HPA_UNIT_ITEMS;
 constexpr int UT = UBLOCK * UITEMS;  // unit capacity (samples)
 constexpr int UHALF = UT / 2;        // contexts up to this size are packed together
 constexpr int MAXC = 256;            // contexts per unit
@@ -302,8 +305,7 @@ struct SortSmem {
   unsigned long long prefix;
   uint32_t unit, nU;
 };
-static_assert(sizeof(uint32_t) * (Sorter::BUF_WORDS + Sorter::CNT_WORDS) >= sizeof(unsigned long long) * (UT + 1),
-              "weight prefixes must fit in the exchange and counter planes");
+static_assert(2 * Sorter::CNT_WORDS >= UT, "16-bit head positions must fit in the counter plane");
 
 // One workgroup's samples in registers: pc, (stall | local context << 4), weight.
 template <bool WEIGHTED>
@@ -319,48 +321,67 @@ struct Gathered {
   }
 };
 
-// Load sample j (0 <= j < n_u, flat = s0 + j) of a unit: run mode finds the run
-// by binary search over the unit's grouped runs; scattered mode reads flat.
+// Load the unit's samples: item i of thread t is sample j = i * UBLOCK + t
+// (flat position s0 + j in context-grouped order).  A thread's items ascend,
+// so run mode finds the run of its first item by binary search over the
+// unit's grouped runs and then walks forward with the current run cached in
+// registers; scattered mode reads flat positions, finding each item's context
+// in the LDS copy of the unit's context offsets.
 template <bool SCATTERED, bool WEIGHTED>
 __device__ inline void gather(Gathered<WEIGHTED>& g, uint64_t s0, uint64_t n_u, uint32_t cb, const Run* __restrict__ grp,
-                              uint64_t r_lo, uint64_t r_hi, const uint64_t* __restrict__ sb_lds_or_global,
+                              uint64_t r_lo, uint64_t r_hi, const uint64_t* __restrict__ sb_lds,
                               uint32_t n_cu, const uint64_t* __restrict__ pc, const uint8_t* __restrict__ stall,
                               const uint32_t* __restrict__ weight, uint32_t* err) {
+  auto load = [&](int i, uint64_t src, uint32_t lc) {
+    g.pc[i] = pc[src];
+    uint8_t st = stall[src];
+    if (st >= NS) { atomicOr(err, (uint32_t)ERR_STALL); st = 0; }
+    g.meta[i] = (uint32_t)st | (lc << 4);
+    if constexpr (WEIGHTED) g.w[i] = weight[src];
+  };
 #pragma unroll
   for (int i = 0; i < UITEMS; ++i) {
-    uint64_t j = (uint64_t)i * UBLOCK + threadIdx.x;
     g.pc[i] = 0;
     g.meta[i] = 0;
     if constexpr (WEIGHTED) g.w[i] = 0;
-    if (j >= n_u) continue;
-    uint64_t flat = s0 + j, src;
-    uint32_t c;
-    if constexpr (SCATTERED) {
-      // local context: last l with sbase[cb + l] <= flat among the unit's contexts
-      uint32_t lo = 0, hi = n_cu;
-      while (hi - lo > 1) {
-        uint32_t mid = (lo + hi) >> 1;
-        if (sb_lds_or_global[mid] <= flat) lo = mid;
-        else hi = mid;
+  }
+  if constexpr (SCATTERED) {
+    uint32_t lo = 0;
+#pragma unroll
+    for (int i = 0; i < UITEMS; ++i) {
+      const uint64_t j = (uint64_t)i * UBLOCK + threadIdx.x;
+      const uint64_t flat = s0 + j;
+      if (j < n_u) {
+        uint32_t hi = n_cu;  // last l with sb[l] <= flat, searching up from the previous item's context
+        while (hi - lo > 1) {
+          uint32_t mid = (lo + hi) >> 1;
+          if (sb_lds[mid] <= flat) lo = mid;
+          else hi = mid;
+        }
+        load(i, flat, lo);
       }
-      c = cb + lo;
-      src = flat;
-    } else {
-      uint64_t lo = r_lo, hi = r_hi;
-      while (hi - lo > 1) {
-        uint64_t mid = (lo + hi) >> 1;
-        if (grp[mid].flat <= flat) lo = mid;
-        else hi = mid;
-      }
-      Run r = grp[lo];
-      c = r.ctx;
-      src = r.start + (flat - r.flat);
     }
-    g.pc[i] = pc[src];
-    uint8_t s = stall[src];
-    if (s >= NS) { atomicOr(err, (uint32_t)ERR_STALL); s = 0; }
-    g.meta[i] = (uint32_t)s | ((c - cb) << 4);
-    if constexpr (WEIGHTED) g.w[i] = weight[src];
+  } else {
+    uint64_t r = r_lo;
+    if (n_u > threadIdx.x) {
+      const uint64_t f0 = s0 + threadIdx.x;
+      uint64_t hi = r_hi;
+      while (hi - r > 1) {
+        uint64_t mid = (r + hi) >> 1;
+        if (grp[mid].flat <= f0) r = mid;
+        else hi = mid;
+      }
+    }
+    Run cur = n_u > threadIdx.x ? grp[r] : Run{0, 0, 0, cb};
+#pragma unroll
+    for (int i = 0; i < UITEMS; ++i) {
+      const uint64_t j = (uint64_t)i * UBLOCK + threadIdx.x;
+      const uint64_t flat = s0 + j;
+      if (j < n_u) {
+        while (flat >= cur.flat + cur.len) cur = grp[++r];
+        load(i, cur.start + (flat - cur.flat), cur.ctx - cb);
+      }
+    }
   }
 }
 
@@ -372,15 +393,14 @@ __device__ inline void sort_reduce(SortSmem& sm, Gathered<WEIGHTED>& g, uint64_t
 #pragma unroll
   for (int i = 0; i < UITEMS; ++i) {
     uint64_t j = (uint64_t)i * UBLOCK + threadIdx.x;
+    key[i] = 0;
     if (j < n_u) {
       uint64_t rel = (g.pc[i] - sm.pcmin[g.lc(i)]) >> tz;
       key[i] = (K)(((uint64_t)g.lc(i) << (pcb + 4)) | (rel << 4) | g.st(i));
-    } else {
-      key[i] = (K)(1ull << kbits);  // padding sorts after every real key
     }
     val[i] = g.wt(i);
   }
-  Sorter::template sort<K, WEIGHTED>(key, val, kbits + 1, sm.buf, sm.cnt, sm.doff);
+  Sorter::template sort<K, WEIGHTED>(key, val, kbits, (int)n_u, sm.buf, sm.cnt, sm.doff);
 }
 
 __device__ inline void publish(unsigned long long* status, uint32_t u, unsigned long long flag,
@@ -388,27 +408,39 @@ __device__ inline void publish(unsigned long long* status, uint32_t u, unsigned 
   __hip_atomic_store(&status[u], (flag << 62) | value, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
 }
 
-// decoupled look-back over units in ticket order; returns the exclusive prefix
+// Decoupled look-back over units in ticket order, run by one whole wave: each
+// probe reads the status words of the 64 nearest predecessors, finds the
+// nearest one holding an inclusive prefix, and waits only if a predecessor
+// before it has not published yet.  Returns the exclusive prefix (all lanes).
 __device__ inline unsigned long long lookback(unsigned long long* status, uint32_t u, unsigned long long agg) {
+  constexpr unsigned long long VMASK = (1ull << 62) - 1;
+  const int lane = lane_id();
   if (u == 0) {
-    publish(status, 0, 2, agg);
+    if (lane == 0) publish(status, 0, 2, agg);
     return 0;
   }
-  publish(status, u, 1, agg);
+  if (lane == 0) publish(status, u, 1, agg);
   unsigned long long acc = 0;
-  int64_t j = (int64_t)u - 1;
-  while (j >= 0) {
-    unsigned long long s = __hip_atomic_load(&status[j], __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT);
-    unsigned long long f = s >> 62;
-    if (f == 0) {
-      __builtin_amdgcn_s_sleep(1);
+  int64_t base = (int64_t)u - 1;
+  while (true) {
+    const int64_t j = base - lane;
+    // before unit 0 there is nothing: read as an inclusive prefix of 0
+    unsigned long long st = j >= 0 ? __hip_atomic_load(&status[j], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)
+                                   : (2ull << 62);
+    const unsigned long long f = st >> 62;
+    const uint64_t have_p = __ballot(f == 2);
+    const uint64_t not_ready = __ballot(f == 0);
+    const int p0 = have_p ? __ffsll((long long)have_p) - 1 : WAVE;
+    const uint64_t need = p0 >= WAVE - 1 ? ~0ull : ((1ull << (p0 + 1)) - 1);
+    if (not_ready & need) {
+      __builtin_amdgcn_s_sleep(2);
       continue;
     }
-    acc += s & ((1ull << 62) - 1);
-    if (f == 2) break;
-    --j;
+    acc += wave_sum(lane <= p0 ? (st & VMASK) : 0ull);
+    if (p0 < WAVE) break;
+    base -= WAVE;
   }
-  publish(status, u, 2, acc + agg);
+  if (lane == 0) publish(status, u, 2, acc + agg);
   return acc;
 }
 
@@ -494,17 +526,24 @@ __device__ inline void key_stats(SortSmem& sm, const Gathered<WEIGHTED>& g, uint
   if (kbits > 63 && threadIdx.x == 0) atomicOr(err, (uint32_t)ERR_WIDE);
 }
 
-// After the sort: head flags, unique count, per-unique counts (in LDS), the
-// per-context unique counts.  Returns the thread's head count and fills hpos.
-template <bool WEIGHTED, class K>
-__device__ inline uint32_t find_heads(SortSmem& sm, const K (&key)[UITEMS], const uint32_t (&val)[UITEMS],
-                                      uint64_t n_u, uint32_t n_cu, int pcb, uint32_t& first_uidx, uint32_t& nU) {
+// After the sort (keys blocked in registers; for keys of <= 32 bits the sorted
+// low words also remain in the exchange plane): head flags, unique count, the
+// head position of every unique key as a 16-bit entry in the counter plane,
+// and the number of unique keys per local context.
+template <class K>
+__device__ inline K prev_last(const SortSmem& sm, int tid) {
+  return tid == 0 ? (K)0 : (K)(((uint64_t)sm.last_hi[tid - 1] << 32) | sm.last_lo[tid - 1]);
+}
+
+template <class K>
+__device__ inline uint32_t find_heads(SortSmem& sm, const K (&key)[UITEMS], uint64_t n_u, uint32_t n_cu, int pcb,
+                                      uint32_t& first_uidx, uint32_t& nU) {
   const int tid = threadIdx.x;
   sm.last_lo[tid] = (uint32_t)key[UITEMS - 1];
   sm.last_hi[tid] = (uint32_t)((uint64_t)key[UITEMS - 1] >> 32);
   for (uint32_t l = tid; l <= n_cu; l += UBLOCK) sm.ucnt[l] = 0;
   __syncthreads();
-  K prev = tid == 0 ? (K)0 : (K)(((uint64_t)sm.last_hi[tid - 1] << 32) | sm.last_lo[tid - 1]);
+  K prev = prev_last<K>(sm, tid);
   uint32_t heads = 0;
 #pragma unroll
   for (int i = 0; i < UITEMS; ++i) {
@@ -517,63 +556,93 @@ __device__ inline uint32_t find_heads(SortSmem& sm, const K (&key)[UITEMS], cons
   unsigned long long ex = block_excl_scan<UBLOCK>((unsigned long long)heads, sm.scan_tmp, &tot);
   first_uidx = (uint32_t)ex;
   nU = (uint32_t)tot;
-  // head positions (or weight prefixes) indexed by unique index, in the counter/buffer planes
-  if constexpr (WEIGHTED) {
-    unsigned long long wsum = 0;
+  uint16_t* hp = reinterpret_cast<uint16_t*>(sm.cnt);
+  prev = prev_last<K>(sm, tid);
+  uint32_t u = first_uidx;
 #pragma unroll
-    for (int i = 0; i < UITEMS; ++i)
-      if ((uint64_t)tid * UITEMS + i < n_u) wsum += val[i];
-    unsigned long long wtot;
-    unsigned long long wex = block_excl_scan<UBLOCK>(wsum, sm.scan_tmp, &wtot);
-    unsigned long long* wp = reinterpret_cast<unsigned long long*>(sm.buf);
-    prev = tid == 0 ? (K)0 : (K)(((uint64_t)sm.last_hi[tid - 1] << 32) | sm.last_lo[tid - 1]);
-    uint32_t u = first_uidx;
-    unsigned long long run = wex;
-#pragma unroll
-    for (int i = 0; i < UITEMS; ++i) {
-      uint32_t p = (uint32_t)tid * UITEMS + i;
-      bool h = p < n_u && (p == 0 || key[i] != prev);
-      if (h) wp[u++] = run;
-      if (p < n_u) run += val[i];
-      prev = key[i];
+  for (int i = 0; i < UITEMS; ++i) {
+    uint32_t p = (uint32_t)tid * UITEMS + i;
+    bool h = p < n_u && (p == 0 || key[i] != prev);
+    if (h) {
+      hp[u++] = (uint16_t)p;
+      atomicAdd(&sm.ucnt[(uint32_t)((uint64_t)key[i] >> (pcb + 4))], 1u);
     }
-    if (tid == 0) wp[nU] = wtot;
-  } else {
-    uint32_t* hp = sm.buf;
-    prev = tid == 0 ? (K)0 : (K)(((uint64_t)sm.last_hi[tid - 1] << 32) | sm.last_lo[tid - 1]);
-    uint32_t u = first_uidx;
-#pragma unroll
-    for (int i = 0; i < UITEMS; ++i) {
-      uint32_t p = (uint32_t)tid * UITEMS + i;
-      bool h = p < n_u && (p == 0 || key[i] != prev);
-      if (h) hp[u++] = p;
-      prev = key[i];
-    }
-    if (tid == 0) hp[nU] = (uint32_t)n_u;
-  }
-  // unique keys per local context
-  {
-    prev = tid == 0 ? (K)0 : (K)(((uint64_t)sm.last_hi[tid - 1] << 32) | sm.last_lo[tid - 1]);
-#pragma unroll
-    for (int i = 0; i < UITEMS; ++i) {
-      uint32_t p = (uint32_t)tid * UITEMS + i;
-      bool h = p < n_u && (p == 0 || key[i] != prev);
-      if (h) atomicAdd(&sm.ucnt[(uint32_t)((uint64_t)key[i] >> (pcb + 4))], 1u);
-      prev = key[i];
-    }
+    prev = key[i];
   }
   __syncthreads();
   return heads;
 }
 
-template <bool WEIGHTED>
-__device__ inline unsigned long long count_of(const SortSmem& sm, uint32_t u) {
-  if constexpr (WEIGHTED) {
-    const unsigned long long* wp = reinterpret_cast<const unsigned long long*>(sm.buf);
-    return wp[u + 1] - wp[u];
-  } else {
-    return (unsigned long long)(sm.buf[u + 1] - sm.buf[u]);
+__device__ inline uint32_t head_pos(const SortSmem& sm, uint32_t u, uint32_t nU, uint64_t n_u) {
+  const uint16_t* hp = reinterpret_cast<const uint16_t*>(sm.cnt);
+  return u < nU ? (uint32_t)hp[u] : (uint32_t)n_u;
+}
+
+// Weighted counts: every head writes the weight of its run inside its thread;
+// runs continuing from the previous thread are added with one atomic each.
+template <class K>
+__device__ inline void weighted_counts(const SortSmem& sm, const K (&key)[UITEMS], const uint32_t (&val)[UITEMS],
+                                       uint64_t n_u, uint32_t first_uidx, unsigned long long* count) {
+  const int tid = threadIdx.x;
+  K prev = prev_last<K>(sm, tid);
+  unsigned long long lead = 0, run = 0;
+  bool seen = false;
+  uint32_t u = first_uidx;
+#pragma unroll
+  for (int i = 0; i < UITEMS; ++i) {
+    uint32_t p = (uint32_t)tid * UITEMS + i;
+    if (p < n_u) {
+      bool h = p == 0 || key[i] != prev;
+      if (h) {
+        if (seen) count[u++] = run;
+        seen = true;
+        run = 0;
+      }
+      if (seen) run += val[i];
+      else lead += val[i];
+    }
+    prev = key[i];
   }
+  if (seen) count[u] = run;
+  __threadfence();
+  __syncthreads();
+  if (lead) atomicAdd(&count[first_uidx - 1], lead);
+}
+
+// Interval of each lane's pc, searched inside the range the wave's smallest
+// and largest pc bound (keys of a wave are close together after the sort).
+__device__ inline uint32_t scope_lookup_wave(const uint64_t* __restrict__ start, const uint64_t* __restrict__ end,
+                                             const uint32_t* __restrict__ scope, uint64_t n_iv, uint64_t pc,
+                                             bool valid) {
+  if (n_iv == 0) return NONE32;
+  uint64_t lo_pc = wave_min(valid ? pc : ~0ull);
+  uint64_t hi_pc = wave_max(valid ? pc : 0ull);
+  // wave-uniform searches: number of starts <= lo_pc and <= hi_pc
+  uint64_t a = 0, b = n_iv;
+  while (a < b) {
+    uint64_t mid = (a + b) >> 1;
+    if (start[mid] <= lo_pc) a = mid + 1;
+    else b = mid;
+  }
+  uint64_t lo = a;
+  b = n_iv;
+  while (a < b) {
+    uint64_t mid = (a + b) >> 1;
+    if (start[mid] <= hi_pc) a = mid + 1;
+    else b = mid;
+  }
+  uint64_t hi = a;
+  if (!valid) return NONE32;
+  // per lane: number of starts <= pc lies in [lo, hi]
+  a = lo;
+  b = hi;
+  while (a < b) {
+    uint64_t mid = (a + b) >> 1;
+    if (start[mid] <= pc) a = mid + 1;
+    else b = mid;
+  }
+  if (a == 0) return NONE32;
+  return pc < end[a - 1] ? scope[a - 1] : NONE32;
 }
 
 // ----------------------------------------------------------------------------
@@ -599,6 +668,61 @@ struct UnitArgs {
   OutDev out;
 };
 
+// Write the unit's unique keys.  Keys of <= 32 bits are read back from the
+// exchange plane by unique index, so consecutive lanes write consecutive
+// output slots; wider keys are written by the thread that holds them (their
+// scopes are looked up afterwards by `scope_pass`).
+template <bool WITH_SCOPE, class K, class Emit>
+__device__ inline void emit_keys(const SortSmem& sm, const K (&key)[UITEMS], uint64_t n_u, uint32_t first,
+                                 uint32_t nU, int kbits, int pcb, uint32_t tz, const MapDev& map, Emit&& emit) {
+  const uint64_t pmask = pcb >= 64 ? ~0ull : ((1ull << pcb) - 1);
+  if (kbits <= 32) {
+    for (uint32_t b0 = 0; b0 < nU; b0 += UBLOCK) {
+      const uint32_t ui = b0 + threadIdx.x;
+      const bool valid = ui < nU;
+      uint64_t kk = 0, pcv = 0;
+      uint32_t cnt = 0;
+      if (valid) {
+        uint32_t p0 = head_pos(sm, ui, nU, n_u), p1 = head_pos(sm, ui + 1, nU, n_u);
+        kk = sm.buf[Sorter::pad((int)p0)];
+        pcv = sm.pcmin[kk >> (pcb + 4)] + (((kk >> 4) & pmask) << tz);
+        cnt = p1 - p0;
+      }
+      uint32_t sc = NONE32;
+      if constexpr (WITH_SCOPE) sc = scope_lookup_wave(map.start, map.end, map.scope, map.n_iv, pcv, valid);
+      if (valid) emit(ui, (uint32_t)(kk >> (pcb + 4)), pcv, (uint8_t)(kk & 15), cnt, sc);
+    }
+  } else {
+    K prev = prev_last<K>(sm, threadIdx.x);
+    uint32_t ui = first;
+#pragma unroll
+    for (int i = 0; i < UITEMS; ++i) {
+      uint32_t p = threadIdx.x * UITEMS + i;
+      bool h = p < n_u && (p == 0 || key[i] != prev);
+      prev = key[i];
+      if (!h) continue;
+      uint64_t kk = (uint64_t)key[i];
+      uint64_t pcv = sm.pcmin[kk >> (pcb + 4)] + (((kk >> 4) & pmask) << tz);
+      uint32_t cnt = head_pos(sm, ui + 1, nU, n_u) - p;
+      emit(ui, (uint32_t)(kk >> (pcb + 4)), pcv, (uint8_t)(kk & 15), cnt, NONE32);
+      ++ui;
+    }
+  }
+}
+
+// Scopes of output keys [o0, o0 + n) from their written pcs (coalesced).
+__device__ inline void scope_pass(const MapDev& map, const uint64_t* pc, uint32_t* scope, uint64_t o0, uint32_t n) {
+  __threadfence_block();
+  __syncthreads();
+  for (uint32_t b0 = 0; b0 < n; b0 += UBLOCK) {
+    const uint32_t i = b0 + threadIdx.x;
+    const bool valid = i < n;
+    const uint64_t p = valid ? pc[o0 + i] : 0;
+    const uint32_t sc = scope_lookup_wave(map.start, map.end, map.scope, map.n_iv, p, valid);
+    if (valid) scope[o0 + i] = sc;
+  }
+}
+
 template <bool WEIGHTED, class K>
 __device__ void unit_body(SortSmem& sm, const UnitArgs& a, uint32_t u, uint32_t cb, uint32_t ce, uint64_t n_u,
                           Gathered<WEIGHTED>& g, int kbits, int pcb, uint32_t tz) {
@@ -607,8 +731,11 @@ __device__ void unit_body(SortSmem& sm, const UnitArgs& a, uint32_t u, uint32_t 
   uint32_t val[UITEMS];
   sort_reduce<WEIGHTED, K>(sm, g, n_u, n_cu, key, val, kbits, pcb, tz);
   uint32_t first, nU;
-  uint32_t heads = find_heads<WEIGHTED, K>(sm, key, val, n_u, n_cu, pcb, first, nU);
-  if (threadIdx.x == 0) sm.prefix = lookback(a.status, u, nU);
+  find_heads<K>(sm, key, n_u, n_cu, pcb, first, nU);
+  if (threadIdx.x < WAVE) {
+    unsigned long long p = lookback(a.status, u, nU);
+    if (threadIdx.x == 0) sm.prefix = p;
+  }
   __syncthreads();
   const unsigned long long prefix = sm.prefix;
   // context offsets: exclusive scan of unique counts per local context
@@ -623,31 +750,20 @@ __device__ void unit_body(SortSmem& sm, const UnitArgs& a, uint32_t u, uint32_t 
       a.info->total_keys = run;
     }
   }
-  // emit: each thread writes its heads (consecutive output slots per thread)
-  if (heads) {
-    K prev = threadIdx.x == 0 ? (K)0
-                              : (K)(((uint64_t)sm.last_hi[threadIdx.x - 1] << 32) | sm.last_lo[threadIdx.x - 1]);
-    uint32_t ui = first;
-    uint64_t hint = NONE64;
-    const uint64_t pmask = pcb >= 64 ? ~0ull : ((1ull << pcb) - 1);
-#pragma unroll
-    for (int i = 0; i < UITEMS; ++i) {
-      uint32_t p = threadIdx.x * UITEMS + i;
-      bool h = p < n_u && (p == 0 || key[i] != prev);
-      prev = key[i];
-      if (!h) continue;
-      uint64_t kk = (uint64_t)key[i];
-      uint32_t lc = (uint32_t)(kk >> (pcb + 4));
-      uint64_t pcv = sm.pcmin[lc] + (((kk >> 4) & pmask) << tz);
-      uint64_t o = prefix + ui;
-      a.out.ctx[o] = cb + lc;
-      a.out.pc[o] = pcv;
-      a.out.stall[o] = (uint8_t)(kk & 15);
-      a.out.count[o] = count_of<WEIGHTED>(sm, ui);
-      a.out.scope[o] = scope_walk(a.map.start, a.map.end, a.map.scope, a.map.n_iv, pcv, hint);
-      ++ui;
-    }
-  }
+  uint32_t* const o_ctx = a.out.ctx + prefix;
+  uint64_t* const o_pc = a.out.pc + prefix;
+  uint8_t* const o_st = a.out.stall + prefix;
+  unsigned long long* const o_cnt = a.out.count + prefix;
+  uint32_t* const o_sc = a.out.scope + prefix;
+  (void)o_sc;
+  emit_keys<false, K>(sm, key, n_u, first, nU, kbits, pcb, tz, a.map,
+                      [=](uint32_t ui, uint32_t lc, uint64_t pcv, uint8_t st, uint32_t cnt, uint32_t) {
+                        o_ctx[ui] = cb + lc;
+                        o_pc[ui] = pcv;
+                        o_st[ui] = st;
+                        if constexpr (!WEIGHTED) o_cnt[ui] = cnt;
+                      });
+  if constexpr (WEIGHTED) weighted_counts<K>(sm, key, val, n_u, first, o_cnt);
 }
 
 template <bool WEIGHTED, bool SCATTERED>
@@ -661,14 +777,16 @@ __global__ void __launch_bounds__(UBLOCK) k_units32(UnitArgs a) {
   const uint32_t cb = a.unit_begin[u], ce = a.unit_begin[u + 1];
   const int32_t big = a.unit_big[u];
   if (big >= 0) {
-    if (threadIdx.x == 0) {
+    if (threadIdx.x < WAVE) {
       unsigned long long U = a.big_U[big];
       unsigned long long p = lookback(a.status, u, U);
-      a.big_out[big] = p;
-      a.out.ctx_off[cb] = p;
-      if (u + 1 == a.n_units) {
-        a.out.ctx_off[a.n_ctx] = p + U;
-        a.info->total_keys = p + U;
+      if (threadIdx.x == 0) {
+        a.big_out[big] = p;
+        a.out.ctx_off[cb] = p;
+        if (u + 1 == a.n_units) {
+          a.out.ctx_off[a.n_ctx] = p + U;
+          a.info->total_keys = p + U;
+        }
       }
     }
     return;
@@ -686,7 +804,10 @@ __global__ void __launch_bounds__(UBLOCK) k_units32(UnitArgs a) {
   key_stats(sm, g, n_u, ce - cb, &a.info->err, kbits, pcb, tz);
   if (kbits > 63) {
     // keep the look-back chain alive; the call reports the error afterwards
-    if (threadIdx.x == 0) sm.prefix = lookback(a.status, u, 0);
+    if (threadIdx.x < WAVE) {
+      unsigned long long p = lookback(a.status, u, 0);
+      if (threadIdx.x == 0) sm.prefix = p;
+    }
     __syncthreads();
     for (uint32_t l = threadIdx.x; l < ce - cb; l += UBLOCK) a.out.ctx_off[cb + l] = sm.prefix;
     if (threadIdx.x == 0 && u + 1 == a.n_units) { a.out.ctx_off[a.n_ctx] = sm.prefix; a.info->total_keys = sm.prefix; }
@@ -760,24 +881,19 @@ __global__ void __launch_bounds__(UBLOCK) k_big_chunks(BigArgs a, ListBuf o) {
   __syncthreads();
   sort_reduce<WEIGHTED, uint64_t>(sm, g, n_u, 1, key, val, kbits, pcb, tz);
   uint32_t first, nU;
-  uint32_t heads = find_heads<WEIGHTED, uint64_t>(sm, key, val, n_u, 1, pcb, first, nU);
+  find_heads<uint64_t>(sm, key, n_u, 1, pcb, first, nU);
   if (threadIdx.x == 0) o.len[ch] = nU;
-  if (!heads) return;
-  uint64_t prev = threadIdx.x == 0 ? 0 : (((uint64_t)sm.last_hi[threadIdx.x - 1] << 32) | sm.last_lo[threadIdx.x - 1]);
-  uint32_t ui = first;
-  const uint64_t pmask = pcb >= 64 ? ~0ull : ((1ull << pcb) - 1);
-#pragma unroll
-  for (int i = 0; i < UITEMS; ++i) {
-    uint32_t p = threadIdx.x * UITEMS + i;
-    bool h = p < n_u && (p == 0 || key[i] != prev);
-    prev = key[i];
-    if (!h) continue;
-    uint64_t kk = key[i];
-    o.pc[obase + ui] = sm.pcmin[0] + (((kk >> 4) & pmask) << tz);
-    o.stall[obase + ui] = (uint8_t)(kk & 15);
-    o.cnt[obase + ui] = count_of<WEIGHTED>(sm, ui);
-    ++ui;
-  }
+  const MapDev nomap{nullptr, nullptr, nullptr, 0};
+  uint64_t* const t_pc = o.pc + obase;
+  uint8_t* const t_st = o.stall + obase;
+  unsigned long long* const t_cnt = o.cnt + obase;
+  emit_keys<false, uint64_t>(sm, key, n_u, first, nU, kbits, pcb, tz, nomap,
+                             [=](uint32_t ui, uint32_t, uint64_t pcv, uint8_t st, uint32_t cnt, uint32_t) {
+                               t_pc[ui] = pcv;
+                               t_st[ui] = st;
+                               if constexpr (!WEIGHTED) t_cnt[ui] = cnt;
+                             });
+  if constexpr (WEIGHTED) weighted_counts<uint64_t>(sm, key, val, n_u, first, t_cnt);
 }
 
 __device__ inline bool key_less(uint64_t pa, uint8_t sa, uint64_t pb, uint8_t sb) {
@@ -877,7 +993,6 @@ __global__ void __launch_bounds__(256) k_big_write(BigArgs a, ListBuf fin, const
   const uint64_t e0 = (ch - c0) * UT;
   const unsigned long long slot0 = slot_prefix[ch] - slot_prefix[c0];
   unsigned long long done = 0;
-  uint64_t hint = NONE64;
   for (uint64_t eb = e0; eb < e0 + UT && eb < len; eb += blockDim.x) {
     uint64_t e = eb + threadIdx.x;
     bool h = e < len && e < e0 + UT &&
@@ -894,7 +1009,6 @@ __global__ void __launch_bounds__(256) k_big_write(BigArgs a, ListBuf fin, const
       out.pc[o] = p;
       out.stall[o] = s;
       out.count[o] = cnt;
-      out.scope[o] = scope_walk(map.start, map.end, map.scope, map.n_iv, p, hint);
     }
     done += tot;
   }
@@ -1065,6 +1179,7 @@ extern "C" hpa_status hpa_attribute(hpa_ctx* ctx, const hpa_structure_map* map, 
                                                         d_bigout.as<uint64_t>(), md, od);
       HPA_HIP(hipGetLastError());
     }
+    launch_scope_labels(map, A->pc.as<uint64_t>(), n, &d_info.as<PlanInfo>()->total_keys, A->scope.as<uint32_t>(), s);
     HPA_HIP(hipMemcpyAsync(&info, d_info.p, sizeof(info), hipMemcpyDeviceToHost, s));
     HPA_HIP(hipStreamSynchronize(s));
     if (info.err & ERR_STALL) fail(HPA_E_INVAL, "a sample has stall >= 16");

@@ -42,6 +42,16 @@ __device__ inline T wave_max(T v) {
 }
 
 template <class T>
+__device__ inline T wave_min(T v) {
+#pragma unroll
+  for (int d = WAVE / 2; d > 0; d >>= 1) {
+    T o = __shfl_xor(v, d, WAVE);
+    v = o < v ? o : v;
+  }
+  return v;
+}
+
+template <class T>
 __device__ inline T wave_or(T v) {
 #pragma unroll
   for (int d = WAVE / 2; d > 0; d >>= 1) v |= __shfl_xor(v, d, WAVE);
@@ -95,50 +105,59 @@ struct BlockRadix {
   __device__ static inline int pad(int i) { return i + (i >> 5); }
 
   // `wide` == false: the high words of 64-bit values are all zero and stay so.
+  // Move valid values to their ranks and read them back blocked.
   template <class V>
-  __device__ static inline void exchange(V (&v)[ITEMS], const uint32_t (&rank)[ITEMS], uint32_t* s_buf,
-                                         bool wide = true) {
-    if (sizeof(V) == 8 && wide) {
-      uint32_t lo[ITEMS];
+  __device__ static inline void exchange(V (&v)[ITEMS], const uint32_t (&rank)[ITEMS], uint32_t* s_buf, bool wide,
+                                         int n, bool striped) {
+    const int tid = (int)threadIdx.x;
+    const int nplanes = (sizeof(V) == 8 && wide) ? 2 : 1;
+    uint32_t lo[ITEMS];
+    for (int plane = 0; plane < nplanes; ++plane) {
 #pragma unroll
-      for (int i = 0; i < ITEMS; ++i) s_buf[pad((int)rank[i])] = (uint32_t)v[i];
+      for (int i = 0; i < ITEMS; ++i)
+        if ((striped ? i * BLOCK + tid : tid * ITEMS + i) < n)
+          s_buf[pad((int)rank[i])] = (uint32_t)((uint64_t)v[i] >> (32 * plane));
       __syncthreads();
 #pragma unroll
-      for (int i = 0; i < ITEMS; ++i) lo[i] = s_buf[pad((int)threadIdx.x * ITEMS + i)];
+      for (int i = 0; i < ITEMS; ++i) {
+        uint32_t x = tid * ITEMS + i < n ? s_buf[pad(tid * ITEMS + i)] : 0u;
+        if (plane == 0) lo[i] = x;
+        else v[i] = (V)(((uint64_t)x << 32) | lo[i]);
+      }
       __syncthreads();
+    }
+    if (nplanes == 1) {
 #pragma unroll
-      for (int i = 0; i < ITEMS; ++i) s_buf[pad((int)rank[i])] = (uint32_t)(v[i] >> 32);
-      __syncthreads();
-#pragma unroll
-      for (int i = 0; i < ITEMS; ++i) v[i] = (V)(((uint64_t)s_buf[pad((int)threadIdx.x * ITEMS + i)] << 32) | lo[i]);
-      __syncthreads();
-    } else {
-#pragma unroll
-      for (int i = 0; i < ITEMS; ++i) s_buf[pad((int)rank[i])] = (uint32_t)v[i];
-      __syncthreads();
-#pragma unroll
-      for (int i = 0; i < ITEMS; ++i) v[i] = (V)s_buf[pad((int)threadIdx.x * ITEMS + i)];
-      __syncthreads();
+      for (int i = 0; i < ITEMS; ++i) v[i] = (V)lo[i];
     }
   }
 
-  // Sort on bits [0, bits) of key; `val` moves with its key when HAS_VAL.
+  // Sort the first n keys (in the starting arrangement: item i of thread t is
+  // element i * BLOCK + t) on bits [0, bits); `val` moves with its key when
+  // HAS_VAL.  Afterwards the sorted keys are blocked: position p is item
+  // p % ITEMS of thread p / ITEMS, and positions >= n hold no key.  When
+  // bits <= 32 (and bits > 0), s_buf[pad(p)] still holds the key at position p.
   template <class K, bool HAS_VAL>
-  __device__ static void sort(K (&key)[ITEMS], uint32_t (&val)[ITEMS], int bits, uint32_t* s_buf, uint32_t* s_cnt,
-                              uint32_t* s_doff) {
+  __device__ static void sort(K (&key)[ITEMS], uint32_t (&val)[ITEMS], int bits, int n, uint32_t* s_buf,
+                              uint32_t* s_cnt, uint32_t* s_doff) {
     const int tid = (int)threadIdx.x;
+    bool striped = true;
     for (int shift = 0; shift < bits; shift += RBITS) {
       for (int i = tid; i < CNT_WORDS / 4; i += BLOCK) reinterpret_cast<uint4*>(s_cnt)[i] = make_uint4(0, 0, 0, 0);
       __syncthreads();
       uint32_t rank[ITEMS];
 #pragma unroll
       for (int i = 0; i < ITEMS; ++i) {
-        uint32_t d = (uint32_t)(key[i] >> shift) & (D - 1);
-        uint32_t* c = &s_cnt[(d >> 1) * BLOCK + tid];
-        uint32_t sh = (d & 1) * 16;
-        uint32_t w = *c;
-        rank[i] = (w >> sh) & 0xFFFFu;
-        *c = w + (1u << sh);
+        const bool ok = (striped ? i * BLOCK + tid : tid * ITEMS + i) < n;
+        rank[i] = 0;
+        if (ok) {
+          uint32_t d = (uint32_t)(key[i] >> shift) & (D - 1);
+          uint32_t* c = &s_cnt[(d >> 1) * BLOCK + tid];
+          uint32_t sh = (d & 1) * 16;
+          uint32_t w = *c;
+          rank[i] = (w >> sh) & 0xFFFFu;
+          *c = w + (1u << sh);
+        }
       }
       __syncthreads();
       // exclusive scan of every counter column over threads; digit totals to s_doff
@@ -170,13 +189,18 @@ struct BlockRadix {
       __syncthreads();
 #pragma unroll
       for (int i = 0; i < ITEMS; ++i) {
-        uint32_t d = (uint32_t)(key[i] >> shift) & (D - 1);
-        uint32_t w = s_cnt[(d >> 1) * BLOCK + tid];
-        rank[i] += ((w >> ((d & 1) * 16)) & 0xFFFFu) + s_doff[d];
+        const bool ok = (striped ? i * BLOCK + tid : tid * ITEMS + i) < n;
+        if (ok) {
+          uint32_t d = (uint32_t)(key[i] >> shift) & (D - 1);
+          uint32_t w = s_cnt[(d >> 1) * BLOCK + tid];
+          rank[i] += ((w >> ((d & 1) * 16)) & 0xFFFFu) + s_doff[d];
+        }
       }
       __syncthreads();
-      exchange(key, rank, s_buf, bits > 32);
-      if constexpr (HAS_VAL) exchange(val, rank, s_buf);
+      // values first, so that the plane left in s_buf holds the keys' low words
+      if constexpr (HAS_VAL) exchange(val, rank, s_buf, true, n, striped);
+      exchange(key, rank, s_buf, bits > 32, n, striped);
+      striped = false;
     }
   }
 };

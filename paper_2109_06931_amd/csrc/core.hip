@@ -290,13 +290,16 @@ namespace {
 
 constexpr int LOOKUP_BLOCK = 256;
 
+template <bool LABEL>
 __global__ void __launch_bounds__(LOOKUP_BLOCK)
 k_lookup_plain(const uint64_t* __restrict__ start, const uint64_t* __restrict__ end, uint64_t n_iv,
                const uint64_t* __restrict__ top, uint32_t top_n, uint32_t shift,
-               const uint64_t* __restrict__ pc, uint64_t n, uint32_t* __restrict__ out) {
+               const uint64_t* __restrict__ pc, uint64_t n, const unsigned long long* __restrict__ n_dev,
+               const uint32_t* __restrict__ label, uint32_t* __restrict__ out) {
   __shared__ uint64_t s_top[4096];
   for (uint32_t i = threadIdx.x; i < top_n; i += LOOKUP_BLOCK) s_top[i] = top[i];
   __syncthreads();
+  if (n_dev) n = min(n, (uint64_t)*n_dev);
   const uint64_t stride = (uint64_t)gridDim.x * LOOKUP_BLOCK;
   for (uint64_t i = (uint64_t)blockIdx.x * LOOKUP_BLOCK + threadIdx.x; i < n; i += stride) {
     const uint64_t q = pc[i];
@@ -316,6 +319,7 @@ k_lookup_plain(const uint64_t* __restrict__ start, const uint64_t* __restrict__ 
       if (e > n_iv) e = n_iv;
       r = find_interval(start, end, n_iv, q, b + 1, e);
     }
+    if constexpr (LABEL) r = r == NONE32 ? NONE32 : label[r];
     out[i] = r;
   }
 }
@@ -331,8 +335,23 @@ void launch_lookup_plain(const hpa_structure_map* m, const uint64_t* pc, uint64_
     return;
   }
   unsigned grid = grid_for(n, LOOKUP_BLOCK, (unsigned)m->ctx->n_cu * 16);
-  k_lookup_plain<<<grid, LOOKUP_BLOCK, 0, s>>>(m->start.as<uint64_t>(), m->end.as<uint64_t>(), m->n_iv,
-                                               m->top.as<uint64_t>(), m->top_n, m->top_shift, pc, n, out);
+  k_lookup_plain<false><<<grid, LOOKUP_BLOCK, 0, s>>>(m->start.as<uint64_t>(), m->end.as<uint64_t>(), m->n_iv,
+                                                      m->top.as<uint64_t>(), m->top_n, m->top_shift, pc, n,
+                                                      nullptr, nullptr, out);
+  HPA_HIP(hipGetLastError());
+}
+
+void launch_scope_labels(const hpa_structure_map* m, const uint64_t* pc, uint64_t cap, const unsigned long long* n_dev,
+                         uint32_t* scope, hipStream_t s) {
+  if (cap == 0) return;
+  if (m->n_iv == 0) {
+    HPA_HIP(hipMemsetAsync(scope, 0xFF, cap * sizeof(uint32_t), s));
+    return;
+  }
+  unsigned grid = grid_for(cap, LOOKUP_BLOCK, (unsigned)m->ctx->n_cu * 16);
+  k_lookup_plain<true><<<grid, LOOKUP_BLOCK, 0, s>>>(m->start.as<uint64_t>(), m->end.as<uint64_t>(), m->n_iv,
+                                                     m->top.as<uint64_t>(), m->top_n, m->top_shift, pc, cap, n_dev,
+                                                     m->scope.as<uint32_t>(), scope);
   HPA_HIP(hipGetLastError());
 }
 

@@ -162,6 +162,9 @@ __device__ inline uint32_t find_interval(const uint64_t* __restrict__ start, con
 }
 
 void launch_lookup_plain(const hpa_structure_map* m, const uint64_t* pc, uint64_t n, uint32_t* out, hipStream_t s);
+// scope[i] = innermost scope of pc[i] for i < min(cap, *n_dev) (n_dev: device counter, may be NULL)
+void launch_scope_labels(const hpa_structure_map* m, const uint64_t* pc, uint64_t cap, const unsigned long long* n_dev,
+                         uint32_t* scope, hipStream_t s);
 void launch_lookup_learned(const hpa_structure_map* m, const uint64_t* pc, uint64_t n, uint32_t* out,
                            hipStream_t s);
 void learned_free(LearnedModel* lm);

@@ -346,22 +346,20 @@ def _kernels(n_funcs, site_callee):
     return np.nonzero(indeg == 0)[0]
 
 
-def _reach(n_funcs, site_caller, site_callee, k):
-    order = np.argsort(site_caller, kind="stable")
-    ptr = np.zeros(n_funcs + 1, dtype=np.int64)
-    np.cumsum(np.bincount(site_caller.astype(np.int64), minlength=n_funcs), out=ptr[1:])
-    callee_sorted = site_callee[order]
-    seen = np.zeros(n_funcs, dtype=bool)
-    seen[k] = True
-    stack, out = [int(k)], [int(k)]
-    while stack:
-        v = stack.pop()
-        for w in callee_sorted[ptr[v]:ptr[v + 1]].tolist():
-            if not seen[w]:
-                seen[w] = True
-                stack.append(w)
-                out.append(w)
-    return np.array(sorted(out), dtype=np.int64)
+def _reach(n_funcs, site_caller, site_callee, k, _cache={}):
+    """Functions reachable from k over call edges (k included), ascending."""
+    from scipy.sparse import csr_matrix
+    from scipy.sparse.csgraph import breadth_first_order
+    key = (id(site_caller), id(site_callee), n_funcs)
+    g = _cache.get(key)
+    if g is None or g[0] is not site_caller:
+        m = csr_matrix((np.ones(len(site_caller), np.int8), (site_caller.astype(np.int64),
+                                                             site_callee.astype(np.int64))),
+                       shape=(n_funcs, n_funcs))
+        _cache.clear()
+        _cache[key] = g = (site_caller, m)
+    order = breadth_first_order(g[1], int(k), directed=True, return_predecessors=False)
+    return np.sort(order).astype(np.int64)
 
 
 # ----------------------------------------------------------------------------
@@ -409,14 +407,24 @@ def _zipf_blocks(rng, item_lists, s):
 
 
 def _stall_tables(rng, n_inst, alpha=0.5):
-    g = rng.standard_gamma(alpha, size=(n_inst, N_STALL))
+    """Per instruction, a Dirichlet(alpha) distribution over the 16 stall
+    reasons, quantised to a STALL_TABLE-entry inverse-CDF table: entry j holds
+    the reason whose CDF interval contains (j + 0.5) / STALL_TABLE."""
+    if alpha == 0.5:
+        # Gamma(1/2, 1) is Z^2 / 2 for a standard normal Z; the factor cancels below
+        g = rng.standard_normal(size=(n_inst, N_STALL))
+        g *= g
+    else:
+        g = rng.standard_gamma(alpha, size=(n_inst, N_STALL))
     g /= np.maximum(g.sum(axis=1, keepdims=True), 1e-300)
     cdf = np.cumsum(g, axis=1)
-    q = (np.arange(STALL_TABLE, dtype=np.float64) + 0.5) / STALL_TABLE
-    tab = np.empty((n_inst, STALL_TABLE), dtype=np.uint8)
-    for j in range(STALL_TABLE):
-        tab[:, j] = np.minimum((cdf < q[j]).sum(axis=1), N_STALL - 1)
-    return tab
+    # first table entry j with (j + 0.5) / T > cdf[s]; entry j's reason counts those s
+    first = np.clip(np.ceil(cdf * STALL_TABLE - 0.5), 0, STALL_TABLE).astype(np.int64)
+    flat = (first * n_inst + np.arange(n_inst, dtype=np.int64)[:, None]).ravel()
+    cnt = np.bincount(flat, minlength=n_inst * (STALL_TABLE + 1)).astype(np.uint8)
+    cnt = cnt.reshape(STALL_TABLE + 1, n_inst)[:STALL_TABLE]
+    tab = np.minimum(np.cumsum(cnt, axis=0, dtype=np.uint8), N_STALL - 1)
+    return np.ascontiguousarray(tab.T)
 
 
 def make_samples(w: Workload, n: int, seg_mean: float, zipf_s: float, mode: str,
