@@ -349,6 +349,7 @@ __device__ inline void gather(Gathered<WEIGHTED>& g, uint64_t s0, uint64_t n_u, 
     uint32_t lo = 0;
 #pragma unroll
     for (int i = 0; i < UITEMS; ++i) {
+      if ((uint64_t)i * UBLOCK >= n_u) continue;
       const uint64_t j = (uint64_t)i * UBLOCK + threadIdx.x;
       const uint64_t flat = s0 + j;
       if (j < n_u) {
@@ -375,6 +376,7 @@ __device__ inline void gather(Gathered<WEIGHTED>& g, uint64_t s0, uint64_t n_u, 
     Run cur = n_u > threadIdx.x ? grp[r] : Run{0, 0, 0, cb};
 #pragma unroll
     for (int i = 0; i < UITEMS; ++i) {
+      if ((uint64_t)i * UBLOCK >= n_u) continue;
       const uint64_t j = (uint64_t)i * UBLOCK + threadIdx.x;
       const uint64_t flat = s0 + j;
       if (j < n_u) {
@@ -504,17 +506,21 @@ __device__ inline void key_stats(SortSmem& sm, const Gathered<WEIGHTED>& g, uint
   if (threadIdx.x == 0) { sm.red_or = 0; sm.red_max = 0; }
   __syncthreads();
 #pragma unroll
-  for (int i = 0; i < UITEMS; ++i)
+  for (int i = 0; i < UITEMS; ++i) {
+    if ((uint64_t)i * UBLOCK >= n_u) continue;
     if ((uint64_t)i * UBLOCK + threadIdx.x < n_u) atomicMin(&sm.pcmin[g.lc(i)], (unsigned long long)g.pc[i]);
+  }
   __syncthreads();
   unsigned long long o = 0, mx = 0;
 #pragma unroll
-  for (int i = 0; i < UITEMS; ++i)
+  for (int i = 0; i < UITEMS; ++i) {
+    if ((uint64_t)i * UBLOCK >= n_u) continue;
     if ((uint64_t)i * UBLOCK + threadIdx.x < n_u) {
       unsigned long long r = g.pc[i] - sm.pcmin[g.lc(i)];
       o |= r;
       mx = r > mx ? r : mx;
     }
+  }
   o = wave_or(o);
   mx = wave_max(mx);
   if (lane_id() == 0) { atomicOr(&sm.red_or, o); atomicMax(&sm.red_max, mx); }

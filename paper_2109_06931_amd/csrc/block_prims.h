@@ -111,18 +111,29 @@ struct BlockRadix {
                                          int n, bool striped) {
     const int tid = (int)threadIdx.x;
     const int nplanes = (sizeof(V) == 8 && wide) ? 2 : 1;
+    // a wave whose first blocked position is past n holds nothing after the exchange
+    const bool wave_has = (int)(threadIdx.x & ~(WAVE - 1)) * ITEMS < n;
     uint32_t lo[ITEMS];
     for (int plane = 0; plane < nplanes; ++plane) {
+      if (striped) {
 #pragma unroll
-      for (int i = 0; i < ITEMS; ++i)
-        if ((striped ? i * BLOCK + tid : tid * ITEMS + i) < n)
-          s_buf[pad((int)rank[i])] = (uint32_t)((uint64_t)v[i] >> (32 * plane));
+        for (int i = 0; i < ITEMS; ++i) {
+          if (i * BLOCK >= n) continue;
+          if (i * BLOCK + tid < n) s_buf[pad((int)rank[i])] = (uint32_t)((uint64_t)v[i] >> (32 * plane));
+        }
+      } else if (wave_has) {
+#pragma unroll
+        for (int i = 0; i < ITEMS; ++i)
+          if (tid * ITEMS + i < n) s_buf[pad((int)rank[i])] = (uint32_t)((uint64_t)v[i] >> (32 * plane));
+      }
       __syncthreads();
+      if (wave_has) {
 #pragma unroll
-      for (int i = 0; i < ITEMS; ++i) {
-        uint32_t x = tid * ITEMS + i < n ? s_buf[pad(tid * ITEMS + i)] : 0u;
-        if (plane == 0) lo[i] = x;
-        else v[i] = (V)(((uint64_t)x << 32) | lo[i]);
+        for (int i = 0; i < ITEMS; ++i) {
+          uint32_t x = tid * ITEMS + i < n ? s_buf[pad(tid * ITEMS + i)] : 0u;
+          if (plane == 0) lo[i] = x;
+          else v[i] = (V)(((uint64_t)x << 32) | lo[i]);
+        }
       }
       __syncthreads();
     }
@@ -146,17 +157,22 @@ struct BlockRadix {
       for (int i = tid; i < CNT_WORDS / 4; i += BLOCK) reinterpret_cast<uint4*>(s_cnt)[i] = make_uint4(0, 0, 0, 0);
       __syncthreads();
       uint32_t rank[ITEMS];
+      const bool wave_has = striped || (int)(threadIdx.x & ~(WAVE - 1)) * ITEMS < n;
 #pragma unroll
-      for (int i = 0; i < ITEMS; ++i) {
-        const bool ok = (striped ? i * BLOCK + tid : tid * ITEMS + i) < n;
-        rank[i] = 0;
-        if (ok) {
-          uint32_t d = (uint32_t)(key[i] >> shift) & (D - 1);
-          uint32_t* c = &s_cnt[(d >> 1) * BLOCK + tid];
-          uint32_t sh = (d & 1) * 16;
-          uint32_t w = *c;
-          rank[i] = (w >> sh) & 0xFFFFu;
-          *c = w + (1u << sh);
+      for (int i = 0; i < ITEMS; ++i) rank[i] = 0;
+      if (wave_has) {
+#pragma unroll
+        for (int i = 0; i < ITEMS; ++i) {
+          if (striped && i * BLOCK >= n) continue;
+          const bool ok = (striped ? i * BLOCK + tid : tid * ITEMS + i) < n;
+          if (ok) {
+            uint32_t d = (uint32_t)(key[i] >> shift) & (D - 1);
+            uint32_t* c = &s_cnt[(d >> 1) * BLOCK + tid];
+            uint32_t sh = (d & 1) * 16;
+            uint32_t w = *c;
+            rank[i] = (w >> sh) & 0xFFFFu;
+            *c = w + (1u << sh);
+          }
         }
       }
       __syncthreads();
@@ -187,13 +203,16 @@ struct BlockRadix {
         }
       }
       __syncthreads();
+      if (wave_has) {
 #pragma unroll
-      for (int i = 0; i < ITEMS; ++i) {
-        const bool ok = (striped ? i * BLOCK + tid : tid * ITEMS + i) < n;
-        if (ok) {
-          uint32_t d = (uint32_t)(key[i] >> shift) & (D - 1);
-          uint32_t w = s_cnt[(d >> 1) * BLOCK + tid];
-          rank[i] += ((w >> ((d & 1) * 16)) & 0xFFFFu) + s_doff[d];
+        for (int i = 0; i < ITEMS; ++i) {
+          if (striped && i * BLOCK >= n) continue;
+          const bool ok = (striped ? i * BLOCK + tid : tid * ITEMS + i) < n;
+          if (ok) {
+            uint32_t d = (uint32_t)(key[i] >> shift) & (D - 1);
+            uint32_t w = s_cnt[(d >> 1) * BLOCK + tid];
+            rank[i] += ((w >> ((d & 1) * 16)) & 0xFFFFu) + s_doff[d];
+          }
         }
       }
       __syncthreads();

@@ -3,6 +3,7 @@
 
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
 #include <cstdint>
 #include <cstring>
 #include <string>
@@ -91,10 +92,16 @@ struct DBuf {
   T* as() const { return static_cast<T*>(p); }
 };
 
+// Copy a host vector into a new device buffer (at least one element, so that
+// empty arrays still have a valid address).  The source is pageable memory, so
+// the copy completes before returning; use on set-up paths only.
 template <class T>
 DBuf upload(hpa_ctx* ctx, const std::vector<T>& v, hipStream_t s) {
-  DBuf b(ctx, v.size() * sizeof(T), s);
-  if (!v.empty()) HPA_HIP(hipMemcpyAsync(b.p, v.data(), v.size() * sizeof(T), hipMemcpyHostToDevice, s));
+  DBuf b(ctx, std::max<size_t>(v.size(), 1) * sizeof(T), s);
+  if (!v.empty()) {
+    HPA_HIP(hipMemcpyAsync(b.p, v.data(), v.size() * sizeof(T), hipMemcpyHostToDevice, s));
+    HPA_HIP(hipStreamSynchronize(s));
+  }
   return b;
 }
 
