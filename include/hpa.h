@@ -101,6 +101,25 @@ typedef struct hpa_ctx hpa_ctx;
 hpa_status hpa_ctx_create(int device, const hpa_allocator* alloc, hpa_ctx** out);
 void hpa_ctx_destroy(hpa_ctx* ctx);
 
+/* Stage timing, for profiling the library's own calls (not part of the
+ * method).  When enabled, hpa_attribute records a hipEvent pair around each
+ * of its stages on the call's stream and, after its final synchronisation,
+ * adds the elapsed device time to the context's table, one row per stage
+ * name: calls counted, and the items the stage read (samples or keys) and
+ * wrote (keys).  hpa_ctx_set_timing(ctx, on) clears the table.  Names are
+ * static strings owned by the library.  hpa_ctx_get_timing copies up to cap
+ * rows into host memory `out` and sets *n_stages to the number of rows.
+ * Errors: HPA_E_INVAL (NULL ctx or n_stages, or out NULL with cap > 0). */
+typedef struct {
+  const char* name;
+  double ms;            /* summed device time over calls */
+  uint64_t calls;
+  uint64_t items_in;    /* summed over calls */
+  uint64_t items_out;
+} hpa_stage_time;
+hpa_status hpa_ctx_set_timing(hpa_ctx* ctx, int enable);
+hpa_status hpa_ctx_get_timing(const hpa_ctx* ctx, hpa_stage_time* out, uint32_t cap, uint32_t* n_stages);
+
 /* ------------------------------------------------------------------------ */
 /* A1: structure map (Section 5; Section 6.1 calling-context expansion)      */
 /* ------------------------------------------------------------------------ */

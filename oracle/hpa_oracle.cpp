@@ -22,8 +22,8 @@
 //                           up the tree) and Section 7.1 (warp issue rate
 //                           W = (S - S_stall) / S).
 //
-// Where the paper is silent the readings below are used (each is listed with
-// its reason in the design notes of the repository):
+// Where the paper is silent, ambiguous or self-contradictory, these readings
+// are used:
 //   R1 a record without a weight counts once;
 //   R2 stall reason 0 is "not stalled", 1..15 are stalls;
 //   R3 unmapped PCs are kept under scope UNMAPPED and an <unknown> CCT node;

@@ -83,6 +83,10 @@ class _MetricsView(C.Structure):
                 ("host_W", P), ("n_scope_rows", U64), ("sc_offsets", P), ("sc_scope", P), ("sc_val", P)]
 
 
+class _StageTime(C.Structure):
+    _fields_ = [("name", C.c_char_p), ("ms", C.c_double), ("calls", U64), ("items_in", U64), ("items_out", U64)]
+
+
 _lib = None
 
 
@@ -98,6 +102,8 @@ def lib():
         L.hpa_ctx_create.argtypes = [I, P, PP]
         L.hpa_ctx_destroy.argtypes = [P]
         L.hpa_ctx_destroy.restype = None
+        L.hpa_ctx_set_timing.argtypes = [P, I]
+        L.hpa_ctx_get_timing.argtypes = [P, C.POINTER(_StageTime), U32, C.POINTER(U32)]
         L.hpa_build_structure_map.argtypes = [P, C.POINTER(_StructureDesc), P, PP]
         L.hpa_structure_map_view_get.argtypes = [P, C.POINTER(_MapView)]
         L.hpa_structure_map_free.argtypes = [P]
@@ -200,6 +206,19 @@ class Context:
         self.h = C.c_void_p()
         _check(lib().hpa_ctx_create(device, None, C.byref(self.h)), "hpa_ctx_create")
         self.device = device
+
+    def set_timing(self, on: bool = True):
+        """hpa_ctx_set_timing: per-stage device timing of later calls (clears the table)."""
+        _check(lib().hpa_ctx_set_timing(self.h, int(bool(on))), "hpa_ctx_set_timing")
+
+    def timing(self) -> dict:
+        """hpa_ctx_get_timing: {stage name: dict(ms, calls, items_in, items_out)}."""
+        n = U32(0)
+        _check(lib().hpa_ctx_get_timing(self.h, None, 0, C.byref(n)), "hpa_ctx_get_timing")
+        rows = (_StageTime * max(n.value, 1))()
+        _check(lib().hpa_ctx_get_timing(self.h, rows, n.value, C.byref(n)), "hpa_ctx_get_timing")
+        return {r.name.decode(): dict(ms=r.ms, calls=r.calls, items_in=r.items_in, items_out=r.items_out)
+                for r in rows[:n.value]}
 
     def __del__(self):
         if getattr(self, "h", None) and _lib is not None:

@@ -1057,7 +1057,9 @@ extern "C" hpa_status hpa_attribute(hpa_ctx* ctx, const hpa_structure_map* map, 
       *out = hold.release();
       return;
     }
+    StageTimer tm(ctx, s);
     // --- scan ctx, plan ---
+    tm.begin("scan_plan");
     const uint64_t run_cap = std::min<uint64_t>(std::max<uint64_t>(n / 8, 1024), 1ull << 24);
     DBuf d_info(ctx, sizeof(PlanInfo), s);
     DBuf d_hist(ctx, (uint64_t)C * 8, s);
@@ -1084,6 +1086,7 @@ extern "C" hpa_status hpa_attribute(hpa_ctx* ctx, const hpa_structure_map* map, 
                                     d_bctx.as<uint32_t>(), d_bsb.as<uint64_t>(), d_bch.as<uint64_t>(),
                                     d_info.as<PlanInfo>());
     HPA_HIP(hipGetLastError());
+    tm.end(n, 0);
     PlanInfo info;
     HPA_HIP(hipMemcpyAsync(&info, d_info.p, sizeof(info), hipMemcpyDeviceToHost, s));
     HPA_HIP(hipStreamSynchronize(s));
@@ -1097,6 +1100,7 @@ extern "C" hpa_status hpa_attribute(hpa_ctx* ctx, const hpa_structure_map* map, 
     const uint64_t* src_pc = smp->pc;
     const uint8_t* src_st = smp->stall;
     const uint32_t* src_w = smp->weight;
+    tm.begin(scattered ? "scatter" : "group_runs");
     if (!scattered) {
       d_grp = DBuf(ctx, std::max<uint64_t>(info.n_runs, 1) * sizeof(Run), s);
       k_group_runs<<<grid_for(info.n_runs, 256, ctx->n_cu * 8), 256, 0, s>>>(
@@ -1115,6 +1119,7 @@ extern "C" hpa_status hpa_attribute(hpa_ctx* ctx, const hpa_structure_map* map, 
       src_st = d_sst.as<uint8_t>();
       src_w = weighted ? d_sw.as<uint32_t>() : nullptr;
     }
+    tm.end(scattered ? n : info.n_runs, 0);
     d_runs.release();
     // --- big contexts ---
     DBuf d_bigU(ctx, ((uint64_t)info.n_big + 1) * 8, s);
@@ -1127,6 +1132,7 @@ extern "C" hpa_status hpa_attribute(hpa_ctx* ctx, const hpa_structure_map* map, 
                d_bctx.as<uint32_t>(), d_bsb.as<uint64_t>(), d_bch.as<uint64_t>(), info.n_big, info.n_chunks,
                d_info.as<PlanInfo>()};
     if (info.n_big) {
+      tm.begin("big_sort");
       const uint64_t bs = info.big_samples;
       for (int k = 0; k < 2; ++k) {
         lbuf[k][0] = DBuf(ctx, bs * 8, s);
@@ -1156,6 +1162,7 @@ extern "C" hpa_status hpa_attribute(hpa_ctx* ctx, const hpa_structure_map* map, 
       k_big_heads<<<g, 256, 0, s>>>(ba, L[fin], d_slot.as<unsigned long long>());
       k_big_scan<<<1, 1024, 0, s>>>(ba, d_slot.as<unsigned long long>(), d_bigU.as<uint64_t>());
       HPA_HIP(hipGetLastError());
+      tm.end(info.big_samples, 0);
     }
     // --- ordered unit pass ---
     DBuf d_status(ctx, (uint64_t)info.n_units * 8, s);
@@ -1171,6 +1178,7 @@ extern "C" hpa_status hpa_attribute(hpa_ctx* ctx, const hpa_structure_map* map, 
                 info.n_units, C, md, od};
     {
       unsigned g = info.n_units;
+      tm.begin("units");
       if (weighted) {
         if (scattered) k_units32<true, true><<<g, UBLOCK, 0, s>>>(ua);
         else k_units32<true, false><<<g, UBLOCK, 0, s>>>(ua);
@@ -1179,18 +1187,36 @@ extern "C" hpa_status hpa_attribute(hpa_ctx* ctx, const hpa_structure_map* map, 
         else k_units32<false, false><<<g, UBLOCK, 0, s>>>(ua);
       }
       HPA_HIP(hipGetLastError());
+      tm.end();
     }
     if (info.n_big) {
+      tm.begin("big_write");
       k_big_write<<<(unsigned)info.n_chunks, 256, 0, s>>>(ba, L[fin], d_slot.as<unsigned long long>(),
                                                         d_bigout.as<uint64_t>(), md, od);
       HPA_HIP(hipGetLastError());
+      tm.end();
     }
+    tm.begin("scope_labels");
     launch_scope_labels(map, A->pc.as<uint64_t>(), n, &d_info.as<PlanInfo>()->total_keys, A->scope.as<uint32_t>(), s);
+    tm.end();
     HPA_HIP(hipMemcpyAsync(&info, d_info.p, sizeof(info), hipMemcpyDeviceToHost, s));
     HPA_HIP(hipStreamSynchronize(s));
     if (info.err & ERR_STALL) fail(HPA_E_INVAL, "a sample has stall >= 16");
     if (info.err & ERR_WIDE) fail(HPA_E_UNSUPPORTED, "the PCs of one context span more than 2^56 bytes");
     A->n_keys = info.total_keys;
+    if (tm.on()) {
+      std::vector<uint64_t> bu(info.n_big);
+      if (info.n_big) {
+        HPA_HIP(hipMemcpyAsync(bu.data(), d_bigU.p, info.n_big * 8, hipMemcpyDeviceToHost, s));
+        HPA_HIP(hipStreamSynchronize(s));
+      }
+      uint64_t big_keys = 0;
+      for (uint64_t v : bu) big_keys += v;
+      tm.items("units", n - info.big_samples, info.total_keys - big_keys);
+      tm.items("big_write", 0, big_keys);
+      tm.items("scope_labels", info.total_keys, info.total_keys);
+      tm.collect();
+    }
     *out = hold.release();
   });
 }

@@ -66,6 +66,76 @@ extern "C" hpa_status hpa_ctx_create(int device, const hpa_allocator* alloc, hpa
 
 extern "C" void hpa_ctx_destroy(hpa_ctx* ctx) { delete ctx; }
 
+extern "C" hpa_status hpa_ctx_set_timing(hpa_ctx* ctx, int enable) {
+  return guard([&] {
+    if (!ctx) fail(HPA_E_INVAL, "ctx is NULL");
+    ctx->timing = enable != 0;
+    ctx->stages.clear();
+  });
+}
+
+extern "C" hpa_status hpa_ctx_get_timing(const hpa_ctx* ctx, hpa_stage_time* out, uint32_t cap, uint32_t* n_stages) {
+  return guard([&] {
+    if (!ctx || !n_stages || (cap && !out)) fail(HPA_E_INVAL, "NULL argument");
+    const uint32_t n = (uint32_t)ctx->stages.size();
+    for (uint32_t i = 0; i < n && i < cap; ++i) out[i] = ctx->stages[i];
+    *n_stages = n;
+  });
+}
+
+namespace hpa {
+
+StageTimer::~StageTimer() {
+  for (auto& sp : spans_) {
+    (void)hipEventDestroy(sp.a);
+    if (sp.b) (void)hipEventDestroy(sp.b);
+  }
+}
+
+void StageTimer::begin(const char* name) {
+  if (!on_) return;
+  Span sp{name, nullptr, nullptr, 0, 0};
+  HPA_HIP(hipEventCreate(&sp.a));
+  spans_.push_back(sp);
+  HPA_HIP(hipEventRecord(spans_.back().a, s_));
+}
+
+void StageTimer::end(uint64_t items_in, uint64_t items_out) {
+  if (!on_ || spans_.empty()) return;
+  Span& sp = spans_.back();
+  HPA_HIP(hipEventCreate(&sp.b));
+  HPA_HIP(hipEventRecord(sp.b, s_));
+  sp.in = items_in;
+  sp.out = items_out;
+}
+
+void StageTimer::items(const char* name, uint64_t items_in, uint64_t items_out) {
+  for (auto& sp : spans_)
+    if (!strcmp(sp.name, name)) { sp.in = items_in; sp.out = items_out; }
+}
+
+void StageTimer::collect() {
+  if (!on_) return;
+  for (auto& sp : spans_) {
+    if (!sp.b) continue;
+    float ms = 0.f;
+    HPA_HIP(hipEventElapsedTime(&ms, sp.a, sp.b));
+    hpa_stage_time* row = nullptr;
+    for (auto& r : ctx_->stages)
+      if (!strcmp(r.name, sp.name)) row = &r;
+    if (!row) {
+      ctx_->stages.push_back(hpa_stage_time{sp.name, 0.0, 0, 0, 0});
+      row = &ctx_->stages.back();
+    }
+    row->ms += ms;
+    row->calls += 1;
+    row->items_in += sp.in;
+    row->items_out += sp.out;
+  }
+}
+
+}  // namespace hpa
+
 // ---------------------------------------------------------------------------
 // A1: structure map (Section 5 function relocation/splitting, line map and
 // inlined code; Section 6.1 calling-context expansion).  Host sweep over the

@@ -58,6 +58,8 @@ struct hpa_ctx {
   hpa_allocator alloc{};
   bool custom = false;
   int n_cu = 256;
+  bool timing = false;
+  std::vector<hpa_stage_time> stages;  // accumulated stage timings
 };
 
 namespace hpa {
@@ -112,6 +114,31 @@ struct DeviceGuard {
     if (prev != dev) HPA_HIP(hipSetDevice(dev));
   }
   ~DeviceGuard() { (void)hipSetDevice(prev); }
+};
+
+// hipEvent pairs around the stages of one call, on one stream; inert unless
+// the context has timing on.  collect() runs after the stream is synchronised.
+class StageTimer {
+ public:
+  StageTimer(hpa_ctx* ctx, hipStream_t s) : ctx_(ctx), s_(s), on_(ctx->timing) {}
+  ~StageTimer();
+  void begin(const char* name);
+  void end(uint64_t items_in = 0, uint64_t items_out = 0);
+  // set the item counts of an earlier span by name (known only after a sync)
+  void items(const char* name, uint64_t items_in, uint64_t items_out);
+  void collect();
+  bool on() const { return on_; }
+
+ private:
+  struct Span {
+    const char* name;
+    hipEvent_t a, b;
+    uint64_t in, out;
+  };
+  hpa_ctx* ctx_;
+  hipStream_t s_;
+  bool on_;
+  std::vector<Span> spans_;
 };
 
 inline unsigned grid_for(uint64_t n, unsigned block, unsigned cap = 1u << 20) {
