@@ -36,19 +36,16 @@ constexpr int SCAN_BLOCK = 256;
 constexpr int SCAN_ITEMS = 16;
 constexpr int SCAN_TILE = SCAN_BLOCK * SCAN_ITEMS;  // samples per scan tile
 
-#ifndef HPA_UNIT_ITEMS
-#define HPA_UNIT_ITEMS 32
-#endif
 constexpr int UBLOCK = 512;
-constexpr int UITEMS = HPA_UNIT_ITEMS;
+constexpr int UITEMS = 16;
 constexpr int UT = UBLOCK * UITEMS;  // unit capacity (samples)
 constexpr int UHALF = UT / 2;        // contexts up to this size are packed together
-constexpr int MAXC = 256;            // contexts per unit
-constexpr int RBITS = 5;
-using Sorter = BlockRadix<UBLOCK, UITEMS, RBITS>;
+constexpr int MAXC = 64;             // contexts per unit
+using Sorter = BlockRadix<UBLOCK, UITEMS>;
 
 constexpr uint64_t M40 = (1ull << 40) - 1;
-constexpr int ERR_CTX = 1, ERR_STALL = 2, ERR_WIDE = 4;
+constexpr int ERR_CTX = 1, ERR_STALL = 2, ERR_WIDE = 4, ERR_RETRY = 8;
+constexpr uint64_t WIDE_CHUNK = ~0ull;  // chunk list length: left for the general chunk kernel
 
 struct Run {
   uint64_t start;  // first sample index in the input
@@ -294,8 +291,13 @@ __global__ void k_scatter(const uint64_t* __restrict__ pc, const uint32_t* __res
 // Shared pieces of the sort workgroups (units and big-context chunks)
 // ----------------------------------------------------------------------------
 struct SortSmem {
+  // exchange plane of the sort; afterwards the unit's unique keys (keys of at
+  // most 32 bits)
   uint32_t buf[Sorter::BUF_WORDS];
-  uint32_t cnt[Sorter::CNT_WORDS];  // radix counters; later head positions / weight prefixes
+  union {
+    uint32_t cnt[Sorter::CNT_WORDS];  // radix counter columns during the sort
+    uint16_t upos[UT + 2];            // then: sorted position of every unique key, closed by n_u
+  };
   uint32_t doff[Sorter::DOFF_WORDS];
   unsigned long long pcmin[MAXC];
   uint32_t ucnt[MAXC + 1];
@@ -304,8 +306,10 @@ struct SortSmem {
   uint32_t last_hi[UBLOCK], last_lo[UBLOCK];
   unsigned long long prefix;
   uint32_t unit, nU;
+  uint64_t wlo[DENSE_MAX_WIN], whi[DENSE_MAX_WIN], wd[DENSE_MAX_WIN + 1];  // dense windows
+  uint32_t far;  // a sample of the workgroup has no dense coordinate
 };
-static_assert(2 * Sorter::CNT_WORDS >= UT, "16-bit head positions must fit in the counter plane");
+static_assert(UT < 65536, "16-bit sorted positions");
 
 // One workgroup's samples in registers: pc, (stall | local context << 4), weight.
 template <bool WEIGHTED>
@@ -387,22 +391,83 @@ __device__ inline void gather(Gathered<WEIGHTED>& g, uint64_t s0, uint64_t n_u, 
   }
 }
 
-// Sort the unit's keys and find the unique keys.  Returns false (and flags
-// ERR_WIDE) when the packed key needs more than 63 bits.
+// Stage the dense window tables in LDS (the caller synchronises before use)
+// and clear the far flag.
+__device__ inline DenseDev stage_dense(SortSmem& sm, const DenseDev& t) {
+  if (threadIdx.x == 0) sm.far = 0;
+  for (uint32_t i = threadIdx.x; i < t.n_win; i += UBLOCK) {
+    sm.wlo[i] = t.lo[i];
+    sm.whi[i] = t.hi[i];
+  }
+  // a map without dense coordinates has no tables (n_win == 0, null pointers)
+  if (t.n_win)
+    for (uint32_t i = threadIdx.x; i <= t.n_win; i += UBLOCK) sm.wd[i] = t.d[i];
+  return DenseDev{sm.wlo, sm.whi, sm.wd, t.scope_of, t.n_win, t.tz};
+}
+
+// Replace every gathered pc by its dense coordinate; a pc without one sets
+// sm.far (the workgroup then gathers again and keeps raw pcs).
+template <bool WEIGHTED>
+__device__ inline void densify(SortSmem& sm, Gathered<WEIGHTED>& g, uint64_t n_u, const DenseDev& t) {
+  bool bad = false;
+#pragma unroll
+  for (int i = 0; i < UITEMS; ++i) {
+    if ((uint64_t)i * UBLOCK >= n_u) continue;
+    if ((uint64_t)i * UBLOCK + threadIdx.x < n_u) {
+      uint64_t D;
+      if (to_dense(t, g.pc[i], D)) g.pc[i] = D;
+      else bad = true;
+    }
+  }
+  if (bad) atomicOr(&sm.far, 1u);
+}
+
+// Innermost scope of a pc: the dense table when the pc has a coordinate,
+// else a binary search over the intervals.
+__device__ inline uint32_t scope_of_pc(const DenseDev& t, bool dense, const uint64_t* start, const uint64_t* end,
+                                       const uint32_t* scope, uint64_t n_iv, uint64_t pc) {
+  uint64_t D;
+  if (dense && to_dense(t, pc, D)) return t.scope_of[D];
+  const uint32_t i = find_interval(start, end, n_iv, pc, 0, n_iv);
+  return i == NONE32 ? NONE32 : scope[i];
+}
+
+// Build the unit's keys (local context, coordinate relative to the context's
+// smallest, stall) and sort them.  Keys of at most 32 bits take one 32-bit
+// sort; wider keys take two chained 32-bit sorts (low word first, the high
+// word carried along, then the high word), which is the same LSD order.
 template <bool WEIGHTED, class K>
 __device__ inline void sort_reduce(SortSmem& sm, Gathered<WEIGHTED>& g, uint64_t n_u, uint32_t n_cu, K (&key)[UITEMS],
                                    uint32_t (&val)[UITEMS], int kbits, int pcb, uint32_t tz) {
+  uint32_t lo[UITEMS], hi[UITEMS];
 #pragma unroll
   for (int i = 0; i < UITEMS; ++i) {
-    uint64_t j = (uint64_t)i * UBLOCK + threadIdx.x;
-    key[i] = 0;
+    const uint64_t j = (uint64_t)i * UBLOCK + threadIdx.x;
+    uint64_t k = 0;
     if (j < n_u) {
-      uint64_t rel = (g.pc[i] - sm.pcmin[g.lc(i)]) >> tz;
-      key[i] = (K)(((uint64_t)g.lc(i) << (pcb + 4)) | (rel << 4) | g.st(i));
+      const uint64_t rel = (g.pc[i] - sm.pcmin[g.lc(i)]) >> tz;
+      k = ((uint64_t)g.lc(i) << (pcb + 4)) | (rel << 4) | g.st(i);
     }
+    lo[i] = (uint32_t)k;
+    hi[i] = (uint32_t)(k >> 32);
     val[i] = g.wt(i);
   }
-  Sorter::template sort<K, WEIGHTED>(key, val, kbits, (int)n_u, sm.buf, sm.cnt, sm.doff);
+  if constexpr (sizeof(K) == 4) {
+    if constexpr (WEIGHTED) Sorter::template sort<1>(lo, val, hi, kbits, (int)n_u, true, sm.buf, sm.cnt, sm.doff);
+    else Sorter::template sort<0>(lo, val, hi, kbits, (int)n_u, true, sm.buf, sm.cnt, sm.doff);
+#pragma unroll
+    for (int i = 0; i < UITEMS; ++i) key[i] = (K)lo[i];
+  } else {
+    if constexpr (WEIGHTED) {
+      Sorter::template sort<2>(lo, hi, val, 32, (int)n_u, true, sm.buf, sm.cnt, sm.doff);
+      Sorter::template sort<2>(hi, lo, val, kbits - 32, (int)n_u, false, sm.buf, sm.cnt, sm.doff);
+    } else {
+      Sorter::template sort<1>(lo, hi, val, 32, (int)n_u, true, sm.buf, sm.cnt, sm.doff);
+      Sorter::template sort<1>(hi, lo, val, kbits - 32, (int)n_u, false, sm.buf, sm.cnt, sm.doff);
+    }
+#pragma unroll
+    for (int i = 0; i < UITEMS; ++i) key[i] = (K)(((uint64_t)hi[i] << 32) | lo[i]);
+  }
 }
 
 __device__ inline void publish(unsigned long long* status, uint32_t u, unsigned long long flag,
@@ -446,42 +511,6 @@ __device__ inline unsigned long long lookback(unsigned long long* status, uint32
   return acc;
 }
 
-// Find the interval of pc starting from a known lower bound (keys of one
-// context come in ascending pc order, so the walk is short).
-__device__ inline uint32_t scope_walk(const uint64_t* __restrict__ start, const uint64_t* __restrict__ end,
-                                      const uint32_t* __restrict__ scope, uint64_t n_iv, uint64_t pc, uint64_t& hint) {
-  // hint: index with start[hint] <= pc is not guaranteed; restart when pc is below
-  uint64_t i = hint;
-  if (n_iv == 0) return NONE32;
-  if (i >= n_iv || start[i] > pc) {
-    uint64_t lo = 0, hi = n_iv;
-    while (lo < hi) {
-      uint64_t mid = (lo + hi) >> 1;
-      if (start[mid] <= pc) lo = mid + 1;
-      else hi = mid;
-    }
-    if (lo == 0) { hint = 0; return NONE32; }
-    i = lo - 1;
-  } else {
-    int steps = 0;
-    while (i + 1 < n_iv && start[i + 1] <= pc) {
-      ++i;
-      if (++steps == 8) {
-        uint64_t lo = i, hi = n_iv;
-        while (lo < hi) {
-          uint64_t mid = (lo + hi) >> 1;
-          if (start[mid] <= pc) lo = mid + 1;
-          else hi = mid;
-        }
-        i = lo - 1;
-        break;
-      }
-    }
-  }
-  hint = i;
-  return pc < end[i] ? scope[i] : NONE32;
-}
-
 struct MapDev {
   const uint64_t* start;
   const uint64_t* end;
@@ -508,7 +537,17 @@ __device__ inline void key_stats(SortSmem& sm, const Gathered<WEIGHTED>& g, uint
 #pragma unroll
   for (int i = 0; i < UITEMS; ++i) {
     if ((uint64_t)i * UBLOCK >= n_u) continue;
-    if ((uint64_t)i * UBLOCK + threadIdx.x < n_u) atomicMin(&sm.pcmin[g.lc(i)], (unsigned long long)g.pc[i]);
+    const bool v = (uint64_t)i * UBLOCK + threadIdx.x < n_u;
+    // items of one wave mostly share a context: reduce in the wave first
+    const uint32_t lc = v ? g.lc(i) : NONE32;
+    const uint32_t lc0 = wave_min(lc);
+    if (lc0 == NONE32) continue;  // no valid item in this wave
+    if (wave_max(v ? lc : lc0) == lc0) {
+      const unsigned long long m = wave_min(v ? (unsigned long long)g.pc[i] : ~0ull);
+      if (lane_id() == 0) atomicMin(&sm.pcmin[lc0], m);
+    } else if (v) {
+      atomicMin(&sm.pcmin[lc], (unsigned long long)g.pc[i]);
+    }
   }
   __syncthreads();
   unsigned long long o = 0, mx = 0;
@@ -532,10 +571,10 @@ __device__ inline void key_stats(SortSmem& sm, const Gathered<WEIGHTED>& g, uint
   if (kbits > 63 && threadIdx.x == 0) atomicOr(err, (uint32_t)ERR_WIDE);
 }
 
-// After the sort (keys blocked in registers; for keys of <= 32 bits the sorted
-// low words also remain in the exchange plane): head flags, unique count, the
-// head position of every unique key as a 16-bit entry in the counter plane,
-// and the number of unique keys per local context.
+// After the sort (keys blocked in registers): head flags, the unique count,
+// the sorted position of every unique key (sm.upos, closed by n_u), the keys
+// themselves compacted into sm.buf when they fit 32 bits, and the number of
+// unique keys per local context.
 template <class K>
 __device__ inline K prev_last(const SortSmem& sm, int tid) {
   return tid == 0 ? (K)0 : (K)(((uint64_t)sm.last_hi[tid - 1] << 32) | sm.last_lo[tid - 1]);
@@ -562,7 +601,6 @@ __device__ inline uint32_t find_heads(SortSmem& sm, const K (&key)[UITEMS], uint
   unsigned long long ex = block_excl_scan<UBLOCK>((unsigned long long)heads, sm.scan_tmp, &tot);
   first_uidx = (uint32_t)ex;
   nU = (uint32_t)tot;
-  uint16_t* hp = reinterpret_cast<uint16_t*>(sm.cnt);
   prev = prev_last<K>(sm, tid);
   uint32_t u = first_uidx;
 #pragma unroll
@@ -570,18 +608,16 @@ __device__ inline uint32_t find_heads(SortSmem& sm, const K (&key)[UITEMS], uint
     uint32_t p = (uint32_t)tid * UITEMS + i;
     bool h = p < n_u && (p == 0 || key[i] != prev);
     if (h) {
-      hp[u++] = (uint16_t)p;
+      sm.upos[u] = (uint16_t)p;
+      if constexpr (sizeof(K) == 4) sm.buf[u] = (uint32_t)key[i];
       atomicAdd(&sm.ucnt[(uint32_t)((uint64_t)key[i] >> (pcb + 4))], 1u);
+      ++u;
     }
     prev = key[i];
   }
+  if (tid == 0) sm.upos[nU] = (uint16_t)n_u;
   __syncthreads();
   return heads;
-}
-
-__device__ inline uint32_t head_pos(const SortSmem& sm, uint32_t u, uint32_t nU, uint64_t n_u) {
-  const uint16_t* hp = reinterpret_cast<const uint16_t*>(sm.cnt);
-  return u < nU ? (uint32_t)hp[u] : (uint32_t)n_u;
 }
 
 // Weighted counts: every head writes the weight of its run inside its thread;
@@ -615,42 +651,6 @@ __device__ inline void weighted_counts(const SortSmem& sm, const K (&key)[UITEMS
   if (lead) atomicAdd(&count[first_uidx - 1], lead);
 }
 
-// Interval of each lane's pc, searched inside the range the wave's smallest
-// and largest pc bound (keys of a wave are close together after the sort).
-__device__ inline uint32_t scope_lookup_wave(const uint64_t* __restrict__ start, const uint64_t* __restrict__ end,
-                                             const uint32_t* __restrict__ scope, uint64_t n_iv, uint64_t pc,
-                                             bool valid) {
-  if (n_iv == 0) return NONE32;
-  uint64_t lo_pc = wave_min(valid ? pc : ~0ull);
-  uint64_t hi_pc = wave_max(valid ? pc : 0ull);
-  // wave-uniform searches: number of starts <= lo_pc and <= hi_pc
-  uint64_t a = 0, b = n_iv;
-  while (a < b) {
-    uint64_t mid = (a + b) >> 1;
-    if (start[mid] <= lo_pc) a = mid + 1;
-    else b = mid;
-  }
-  uint64_t lo = a;
-  b = n_iv;
-  while (a < b) {
-    uint64_t mid = (a + b) >> 1;
-    if (start[mid] <= hi_pc) a = mid + 1;
-    else b = mid;
-  }
-  uint64_t hi = a;
-  if (!valid) return NONE32;
-  // per lane: number of starts <= pc lies in [lo, hi]
-  a = lo;
-  b = hi;
-  while (a < b) {
-    uint64_t mid = (a + b) >> 1;
-    if (start[mid] <= pc) a = mid + 1;
-    else b = mid;
-  }
-  if (a == 0) return NONE32;
-  return pc < end[a - 1] ? scope[a - 1] : NONE32;
-}
-
 // ----------------------------------------------------------------------------
 // units: the ordered pass
 // ----------------------------------------------------------------------------
@@ -672,31 +672,25 @@ struct UnitArgs {
   uint32_t n_ctx;
   MapDev map;
   OutDev out;
+  DenseDev dd;
+  int dense;  // the map has dense coordinates: units write scope labels themselves
 };
 
-// Write the unit's unique keys.  Keys of <= 32 bits are read back from the
-// exchange plane by unique index, so consecutive lanes write consecutive
-// output slots; wider keys are written by the thread that holds them (their
-// scopes are looked up afterwards by `scope_pass`).
-template <bool WITH_SCOPE, class K, class Emit>
+// Hand the unit's unique keys to `emit(ui, local ctx, coordinate, stall,
+// count)` in unique-key order.  32-bit keys come from their compacted copy in
+// LDS, so consecutive lanes take consecutive keys (coalesced output); wider
+// keys are emitted by the thread that holds them.  The coordinate is the
+// dense coordinate or the pc, whichever the keys were built from.
+template <class K, class Emit>
 __device__ inline void emit_keys(const SortSmem& sm, const K (&key)[UITEMS], uint64_t n_u, uint32_t first,
-                                 uint32_t nU, int kbits, int pcb, uint32_t tz, const MapDev& map, Emit&& emit) {
+                                 uint32_t nU, int pcb, uint32_t tz, Emit&& emit) {
   const uint64_t pmask = pcb >= 64 ? ~0ull : ((1ull << pcb) - 1);
-  if (kbits <= 32) {
-    for (uint32_t b0 = 0; b0 < nU; b0 += UBLOCK) {
-      const uint32_t ui = b0 + threadIdx.x;
-      const bool valid = ui < nU;
-      uint64_t kk = 0, pcv = 0;
-      uint32_t cnt = 0;
-      if (valid) {
-        uint32_t p0 = head_pos(sm, ui, nU, n_u), p1 = head_pos(sm, ui + 1, nU, n_u);
-        kk = sm.buf[Sorter::pad((int)p0)];
-        pcv = sm.pcmin[kk >> (pcb + 4)] + (((kk >> 4) & pmask) << tz);
-        cnt = p1 - p0;
-      }
-      uint32_t sc = NONE32;
-      if constexpr (WITH_SCOPE) sc = scope_lookup_wave(map.start, map.end, map.scope, map.n_iv, pcv, valid);
-      if (valid) emit(ui, (uint32_t)(kk >> (pcb + 4)), pcv, (uint8_t)(kk & 15), cnt, sc);
+  if constexpr (sizeof(K) == 4) {
+    for (uint32_t ui = threadIdx.x; ui < nU; ui += UBLOCK) {
+      const uint64_t kk = sm.buf[ui];
+      const uint32_t cnt = (uint32_t)sm.upos[ui + 1] - (uint32_t)sm.upos[ui];
+      const uint32_t lc = (uint32_t)(kk >> (pcb + 4));
+      emit(ui, lc, sm.pcmin[lc] + (((kk >> 4) & pmask) << tz), (uint8_t)(kk & 15), cnt);
     }
   } else {
     K prev = prev_last<K>(sm, threadIdx.x);
@@ -707,31 +701,17 @@ __device__ inline void emit_keys(const SortSmem& sm, const K (&key)[UITEMS], uin
       bool h = p < n_u && (p == 0 || key[i] != prev);
       prev = key[i];
       if (!h) continue;
-      uint64_t kk = (uint64_t)key[i];
-      uint64_t pcv = sm.pcmin[kk >> (pcb + 4)] + (((kk >> 4) & pmask) << tz);
-      uint32_t cnt = head_pos(sm, ui + 1, nU, n_u) - p;
-      emit(ui, (uint32_t)(kk >> (pcb + 4)), pcv, (uint8_t)(kk & 15), cnt, NONE32);
+      const uint64_t kk = (uint64_t)key[i];
+      const uint32_t lc = (uint32_t)(kk >> (pcb + 4));
+      emit(ui, lc, sm.pcmin[lc] + (((kk >> 4) & pmask) << tz), (uint8_t)(kk & 15), (uint32_t)sm.upos[ui + 1] - p);
       ++ui;
     }
   }
 }
 
-// Scopes of output keys [o0, o0 + n) from their written pcs (coalesced).
-__device__ inline void scope_pass(const MapDev& map, const uint64_t* pc, uint32_t* scope, uint64_t o0, uint32_t n) {
-  __threadfence_block();
-  __syncthreads();
-  for (uint32_t b0 = 0; b0 < n; b0 += UBLOCK) {
-    const uint32_t i = b0 + threadIdx.x;
-    const bool valid = i < n;
-    const uint64_t p = valid ? pc[o0 + i] : 0;
-    const uint32_t sc = scope_lookup_wave(map.start, map.end, map.scope, map.n_iv, p, valid);
-    if (valid) scope[o0 + i] = sc;
-  }
-}
-
 template <bool WEIGHTED, class K>
-__device__ void unit_body(SortSmem& sm, const UnitArgs& a, uint32_t u, uint32_t cb, uint32_t ce, uint64_t n_u,
-                          Gathered<WEIGHTED>& g, int kbits, int pcb, uint32_t tz) {
+__device__ __forceinline__ void unit_body(SortSmem& sm, const UnitArgs& a, uint32_t u, uint32_t cb, uint32_t ce, uint64_t n_u,
+                          Gathered<WEIGHTED>& g, int kbits, int pcb, uint32_t tz, bool dense, const DenseDev& t) {
   const uint32_t n_cu = ce - cb;
   K key[UITEMS];
   uint32_t val[UITEMS];
@@ -761,18 +741,32 @@ __device__ void unit_body(SortSmem& sm, const UnitArgs& a, uint32_t u, uint32_t 
   uint8_t* const o_st = a.out.stall + prefix;
   unsigned long long* const o_cnt = a.out.count + prefix;
   uint32_t* const o_sc = a.out.scope + prefix;
-  (void)o_sc;
-  emit_keys<false, K>(sm, key, n_u, first, nU, kbits, pcb, tz, a.map,
-                      [=](uint32_t ui, uint32_t lc, uint64_t pcv, uint8_t st, uint32_t cnt, uint32_t) {
-                        o_ctx[ui] = cb + lc;
-                        o_pc[ui] = pcv;
-                        o_st[ui] = st;
-                        if constexpr (!WEIGHTED) o_cnt[ui] = cnt;
-                      });
+  const MapDev map = a.map;
+  const int label = a.dense;  // without dense coordinates a separate pass labels every key
+  emit_keys<K>(sm, key, n_u, first, nU, pcb, tz,
+               [=](uint32_t ui, uint32_t lc, uint64_t v, uint8_t st, uint32_t cnt) {
+                 o_ctx[ui] = cb + lc;
+                 o_st[ui] = st;
+                 if constexpr (!WEIGHTED) o_cnt[ui] = cnt;
+                 if (dense) {
+                   o_pc[ui] = from_dense(t, v);
+                   o_sc[ui] = t.scope_of[v];
+                 } else {
+                   o_pc[ui] = v;
+                   if (label) {  // a unit with a pc off the dense grid: binary search
+                     const uint32_t iv = find_interval(map.start, map.end, map.n_iv, v, 0, map.n_iv);
+                     o_sc[ui] = iv == NONE32 ? NONE32 : map.scope[iv];
+                   }
+                 }
+               });
   if constexpr (WEIGHTED) weighted_counts<K>(sm, key, val, n_u, first, o_cnt);
 }
 
-template <bool WEIGHTED, bool SCATTERED>
+// GENERAL = false: keys of at most 32 bits only (registers sized for them); a
+// unit that needs wider keys keeps the look-back chain alive with an empty
+// aggregate and raises ERR_RETRY, and the host reruns the pass with
+// GENERAL = true, which handles every unit.
+template <bool WEIGHTED, bool SCATTERED, bool GENERAL>
 __global__ void __launch_bounds__(UBLOCK) k_units32(UnitArgs a) {
   __shared__ SortSmem sm;
   __shared__ uint64_t s_sb[MAXC + 1];
@@ -800,16 +794,27 @@ __global__ void __launch_bounds__(UBLOCK) k_units32(UnitArgs a) {
   const uint64_t s0 = a.sbase[cb];
   const uint64_t n_u = a.sbase[ce] - s0;
   for (uint32_t l = threadIdx.x; l <= ce - cb; l += UBLOCK) s_sb[l] = a.sbase[cb + l];
+  const DenseDev t = stage_dense(sm, a.dd);  // LDS view (empty when the map has no dense coordinates)
   __syncthreads();
   Gathered<WEIGHTED> g;
   gather<SCATTERED, WEIGHTED>(g, s0, n_u, cb, a.grouped, SCATTERED ? 0 : a.rbase[cb], SCATTERED ? 0 : a.rbase[ce],
                               s_sb, ce - cb, a.pc, a.stall, a.weight, &a.info->err);
+  bool dense = false;
+  if (a.dense) {
+    densify(sm, g, n_u, t);
+    __syncthreads();
+    dense = sm.far == 0;
+    if (!dense)
+      gather<SCATTERED, WEIGHTED>(g, s0, n_u, cb, a.grouped, SCATTERED ? 0 : a.rbase[cb],
+                                  SCATTERED ? 0 : a.rbase[ce], s_sb, ce - cb, a.pc, a.stall, a.weight, &a.info->err);
+  }
   // key width decides the register type of the sort
   int kbits, pcb;
   uint32_t tz;
   key_stats(sm, g, n_u, ce - cb, &a.info->err, kbits, pcb, tz);
-  if (kbits > 63) {
-    // keep the look-back chain alive; the call reports the error afterwards
+  if (kbits > 63 || (!GENERAL && kbits > 32)) {
+    // keep the look-back chain alive; the call reports the error (or reruns) afterwards
+    if (!GENERAL && kbits <= 63 && threadIdx.x == 0) atomicOr(&a.info->err, (uint32_t)ERR_RETRY);
     if (threadIdx.x < WAVE) {
       unsigned long long p = lookback(a.status, u, 0);
       if (threadIdx.x == 0) sm.prefix = p;
@@ -820,7 +825,13 @@ __global__ void __launch_bounds__(UBLOCK) k_units32(UnitArgs a) {
     return;
   }
   __syncthreads();
-  unit_body<WEIGHTED, uint64_t>(sm, a, u, cb, ce, n_u, g, kbits, pcb, tz);
+  if constexpr (GENERAL) {
+    if (kbits > 32) {
+      unit_body<WEIGHTED, uint64_t>(sm, a, u, cb, ce, n_u, g, kbits, pcb, tz, dense, t);
+      return;
+    }
+  }
+  unit_body<WEIGHTED, uint32_t>(sm, a, u, cb, ce, n_u, g, kbits, pcb, tz, dense, t);
 }
 
 // ----------------------------------------------------------------------------
@@ -839,6 +850,8 @@ struct BigArgs {
   uint32_t n_big;
   uint64_t n_chunks;
   PlanInfo* info;
+  DenseDev dd;
+  int dense;
 };
 
 struct ListBuf {
@@ -858,11 +871,36 @@ __device__ inline uint32_t chunk_owner(const uint64_t* big_chunk, uint32_t n_big
   return lo;
 }
 
-template <bool WEIGHTED, bool SCATTERED>
+// Sort one chunk of a big context and write its unique keys (real pcs) as a
+// sorted list.
+template <bool WEIGHTED, class K>
+__device__ __forceinline__ void chunk_body(SortSmem& sm, const ListBuf& o, uint64_t ch, uint64_t obase, Gathered<WEIGHTED>& g,
+                           uint64_t n_u, int kbits, int pcb, uint32_t tz, bool dense, const DenseDev& t) {
+  K key[UITEMS];
+  uint32_t val[UITEMS];
+  sort_reduce<WEIGHTED, K>(sm, g, n_u, 1, key, val, kbits, pcb, tz);
+  uint32_t first, nU;
+  find_heads<K>(sm, key, n_u, 1, pcb, first, nU);
+  if (threadIdx.x == 0) o.len[ch] = nU;
+  uint64_t* const t_pc = o.pc + obase;
+  uint8_t* const t_st = o.stall + obase;
+  unsigned long long* const t_cnt = o.cnt + obase;
+  emit_keys<K>(sm, key, n_u, first, nU, pcb, tz, [=](uint32_t ui, uint32_t, uint64_t v, uint8_t st, uint32_t cnt) {
+    t_pc[ui] = dense ? from_dense(t, v) : v;
+    t_st[ui] = st;
+    if constexpr (!WEIGHTED) t_cnt[ui] = cnt;
+  });
+  if constexpr (WEIGHTED) weighted_counts<K>(sm, key, val, n_u, first, t_cnt);
+}
+
+// GENERAL = false sorts the chunks whose keys fit 32 bits and marks the others
+// (list length WIDE_CHUNK); GENERAL = true, launched next, sorts only those.
+template <bool WEIGHTED, bool SCATTERED, bool GENERAL>
 __global__ void __launch_bounds__(UBLOCK) k_big_chunks(BigArgs a, ListBuf o) {
   __shared__ SortSmem sm;
   __shared__ uint64_t s_sb[2];
   const uint64_t ch = blockIdx.x;
+  if (GENERAL && o.len[ch] != WIDE_CHUNK) return;
   const uint32_t b = chunk_owner(a.big_chunk, a.n_big, ch);
   const uint32_t c = a.big_ctx[b];
   const uint64_t j = ch - a.big_chunk[b];
@@ -870,10 +908,20 @@ __global__ void __launch_bounds__(UBLOCK) k_big_chunks(BigArgs a, ListBuf o) {
   const uint64_t s0 = a.sbase[c] + j * UT;
   const uint64_t n_u = min((uint64_t)UT, nc - j * UT);
   if (threadIdx.x == 0) { s_sb[0] = a.sbase[c]; s_sb[1] = a.sbase[c + 1]; }
+  const DenseDev t = stage_dense(sm, a.dd);  // LDS view (empty when the map has no dense coordinates)
   __syncthreads();
   Gathered<WEIGHTED> g;
   gather<SCATTERED, WEIGHTED>(g, s0, n_u, c, a.grouped, SCATTERED ? 0 : a.rbase[c], SCATTERED ? 0 : a.rbase[c + 1],
                               s_sb, 1, a.pc, a.stall, a.weight, &a.info->err);
+  bool dense = false;
+  if (a.dense) {
+    densify(sm, g, n_u, t);
+    __syncthreads();
+    dense = sm.far == 0;
+    if (!dense)
+      gather<SCATTERED, WEIGHTED>(g, s0, n_u, c, a.grouped, SCATTERED ? 0 : a.rbase[c], SCATTERED ? 0 : a.rbase[c + 1],
+                                  s_sb, 1, a.pc, a.stall, a.weight, &a.info->err);
+  }
   int kbits, pcb;
   uint32_t tz;
   key_stats(sm, g, n_u, 1, &a.info->err, kbits, pcb, tz);
@@ -882,24 +930,13 @@ __global__ void __launch_bounds__(UBLOCK) k_big_chunks(BigArgs a, ListBuf o) {
     if (threadIdx.x == 0) o.len[ch] = 0;
     return;
   }
-  uint64_t key[UITEMS];
-  uint32_t val[UITEMS];
+  if (!GENERAL && kbits > 32) {
+    if (threadIdx.x == 0) o.len[ch] = WIDE_CHUNK;
+    return;
+  }
   __syncthreads();
-  sort_reduce<WEIGHTED, uint64_t>(sm, g, n_u, 1, key, val, kbits, pcb, tz);
-  uint32_t first, nU;
-  find_heads<uint64_t>(sm, key, n_u, 1, pcb, first, nU);
-  if (threadIdx.x == 0) o.len[ch] = nU;
-  const MapDev nomap{nullptr, nullptr, nullptr, 0};
-  uint64_t* const t_pc = o.pc + obase;
-  uint8_t* const t_st = o.stall + obase;
-  unsigned long long* const t_cnt = o.cnt + obase;
-  emit_keys<false, uint64_t>(sm, key, n_u, first, nU, kbits, pcb, tz, nomap,
-                             [=](uint32_t ui, uint32_t, uint64_t pcv, uint8_t st, uint32_t cnt, uint32_t) {
-                               t_pc[ui] = pcv;
-                               t_st[ui] = st;
-                               if constexpr (!WEIGHTED) t_cnt[ui] = cnt;
-                             });
-  if constexpr (WEIGHTED) weighted_counts<uint64_t>(sm, key, val, n_u, first, t_cnt);
+  if constexpr (GENERAL) chunk_body<WEIGHTED, uint64_t>(sm, o, ch, obase, g, n_u, kbits, pcb, tz, dense, t);
+  else chunk_body<WEIGHTED, uint32_t>(sm, o, ch, obase, g, n_u, kbits, pcb, tz, dense, t);
 }
 
 __device__ inline bool key_less(uint64_t pa, uint8_t sa, uint64_t pb, uint8_t sb) {
@@ -1015,6 +1052,7 @@ __global__ void __launch_bounds__(256) k_big_write(BigArgs a, ListBuf fin, const
       out.pc[o] = p;
       out.stall[o] = s;
       out.count[o] = cnt;
+      if (a.dense) out.scope[o] = scope_of_pc(a.dd, true, map.start, map.end, map.scope, map.n_iv, p);
     }
     done += tot;
   }
@@ -1131,6 +1169,10 @@ extern "C" hpa_status hpa_attribute(hpa_ctx* ctx, const hpa_structure_map* map, 
     BigArgs ba{src_pc, src_st, src_w, d_sbase.as<uint64_t>(), d_rbase.as<uint64_t>(), d_grp.as<Run>(),
                d_bctx.as<uint32_t>(), d_bsb.as<uint64_t>(), d_bch.as<uint64_t>(), info.n_big, info.n_chunks,
                d_info.as<PlanInfo>()};
+    const DenseDev dd{map->win_lo.as<uint64_t>(), map->win_hi.as<uint64_t>(), map->win_d.as<uint64_t>(),
+                      map->scope_of.as<uint32_t>(), map->n_win, map->dense_tz};
+    ba.dd = dd;
+    ba.dense = map->dense ? 1 : 0;
     if (info.n_big) {
       tm.begin("big_sort");
       const uint64_t bs = info.big_samples;
@@ -1143,12 +1185,23 @@ extern "C" hpa_status hpa_attribute(hpa_ctx* ctx, const hpa_structure_map* map, 
                        lbuf[k][2].as<unsigned long long>(), lbuf[k][3].as<uint64_t>()};
       }
       unsigned g = (unsigned)info.n_chunks;
+      // the narrow kernel first; the general one then takes the chunks it left
       if (weighted) {
-        if (scattered) k_big_chunks<true, true><<<g, UBLOCK, 0, s>>>(ba, L[0]);
-        else k_big_chunks<true, false><<<g, UBLOCK, 0, s>>>(ba, L[0]);
+        if (scattered) {
+          k_big_chunks<true, true, false><<<g, UBLOCK, 0, s>>>(ba, L[0]);
+          k_big_chunks<true, true, true><<<g, UBLOCK, 0, s>>>(ba, L[0]);
+        } else {
+          k_big_chunks<true, false, false><<<g, UBLOCK, 0, s>>>(ba, L[0]);
+          k_big_chunks<true, false, true><<<g, UBLOCK, 0, s>>>(ba, L[0]);
+        }
       } else {
-        if (scattered) k_big_chunks<false, true><<<g, UBLOCK, 0, s>>>(ba, L[0]);
-        else k_big_chunks<false, false><<<g, UBLOCK, 0, s>>>(ba, L[0]);
+        if (scattered) {
+          k_big_chunks<false, true, false><<<g, UBLOCK, 0, s>>>(ba, L[0]);
+          k_big_chunks<false, true, true><<<g, UBLOCK, 0, s>>>(ba, L[0]);
+        } else {
+          k_big_chunks<false, false, false><<<g, UBLOCK, 0, s>>>(ba, L[0]);
+          k_big_chunks<false, false, true><<<g, UBLOCK, 0, s>>>(ba, L[0]);
+        }
       }
       HPA_HIP(hipGetLastError());
       int r = 0;
@@ -1176,31 +1229,51 @@ extern "C" hpa_status hpa_attribute(hpa_ctx* ctx, const hpa_structure_map* map, 
                 d_ubeg.as<uint32_t>(), d_ubig.as<int32_t>(), d_bigU.as<uint64_t>(), d_bigout.as<uint64_t>(),
                 d_status.as<unsigned long long>(), d_ticket.as<unsigned int>(), d_info.as<PlanInfo>(),
                 info.n_units, C, md, od};
-    {
-      unsigned g = info.n_units;
+    ua.dd = dd;
+    ua.dense = map->dense ? 1 : 0;
+    // unit pass (+ big-context write and labels); `general` handles every key width
+    auto unit_pass = [&](bool general) {
+      const unsigned g = info.n_units;
       tm.begin("units");
+#define HPA_UNITS(W, S)                                                              \
+  do {                                                                               \
+    if (general) k_units32<W, S, true><<<g, UBLOCK, 0, s>>>(ua);                     \
+    else k_units32<W, S, false><<<g, UBLOCK, 0, s>>>(ua);                            \
+  } while (0)
       if (weighted) {
-        if (scattered) k_units32<true, true><<<g, UBLOCK, 0, s>>>(ua);
-        else k_units32<true, false><<<g, UBLOCK, 0, s>>>(ua);
+        if (scattered) HPA_UNITS(true, true);
+        else HPA_UNITS(true, false);
       } else {
-        if (scattered) k_units32<false, true><<<g, UBLOCK, 0, s>>>(ua);
-        else k_units32<false, false><<<g, UBLOCK, 0, s>>>(ua);
+        if (scattered) HPA_UNITS(false, true);
+        else HPA_UNITS(false, false);
       }
+#undef HPA_UNITS
       HPA_HIP(hipGetLastError());
       tm.end();
+      if (info.n_big) {
+        tm.begin("big_write");
+        k_big_write<<<(unsigned)info.n_chunks, 256, 0, s>>>(ba, L[fin], d_slot.as<unsigned long long>(),
+                                                          d_bigout.as<uint64_t>(), md, od);
+        HPA_HIP(hipGetLastError());
+        tm.end();
+      }
+      if (!map->dense) {
+        // no dense coordinates: label every key with a binary search
+        tm.begin("scope_labels");
+        launch_scope_labels(map, A->pc.as<uint64_t>(), n, &d_info.as<PlanInfo>()->total_keys,
+                            A->scope.as<uint32_t>(), s);
+        tm.end();
+      }
+      HPA_HIP(hipMemcpyAsync(&info, d_info.p, sizeof(info), hipMemcpyDeviceToHost, s));
+      HPA_HIP(hipStreamSynchronize(s));
+    };
+    unit_pass(false);
+    if (info.err & ERR_RETRY) {
+      // some unit needs keys wider than 32 bits: redo the pass with the general kernel
+      HPA_HIP(hipMemsetAsync(d_status.p, 0, (uint64_t)info.n_units * 8, s));
+      HPA_HIP(hipMemsetAsync(d_ticket.p, 0, 8, s));
+      unit_pass(true);
     }
-    if (info.n_big) {
-      tm.begin("big_write");
-      k_big_write<<<(unsigned)info.n_chunks, 256, 0, s>>>(ba, L[fin], d_slot.as<unsigned long long>(),
-                                                        d_bigout.as<uint64_t>(), md, od);
-      HPA_HIP(hipGetLastError());
-      tm.end();
-    }
-    tm.begin("scope_labels");
-    launch_scope_labels(map, A->pc.as<uint64_t>(), n, &d_info.as<PlanInfo>()->total_keys, A->scope.as<uint32_t>(), s);
-    tm.end();
-    HPA_HIP(hipMemcpyAsync(&info, d_info.p, sizeof(info), hipMemcpyDeviceToHost, s));
-    HPA_HIP(hipStreamSynchronize(s));
     if (info.err & ERR_STALL) fail(HPA_E_INVAL, "a sample has stall >= 16");
     if (info.err & ERR_WIDE) fail(HPA_E_UNSUPPORTED, "the PCs of one context span more than 2^56 bytes");
     A->n_keys = info.total_keys;
@@ -1214,7 +1287,7 @@ extern "C" hpa_status hpa_attribute(hpa_ctx* ctx, const hpa_structure_map* map, 
       for (uint64_t v : bu) big_keys += v;
       tm.items("units", n - info.big_samples, info.total_keys - big_keys);
       tm.items("big_write", 0, big_keys);
-      tm.items("scope_labels", info.total_keys, info.total_keys);
+      if (!map->dense) tm.items("scope_labels", info.total_keys, info.total_keys);
       tm.collect();
     }
     *out = hold.release();

@@ -84,105 +84,75 @@ __device__ inline T block_excl_scan(T v, T* s_tmp, T* total) {
   return r;
 }
 
-// LSD radix sort of BLOCK * ITEMS keys held in registers (blocked arrangement
-// after every pass: thread t holds sequence positions t*ITEMS .. t*ITEMS+ITEMS-1).
-// Digit ranks come from per-thread counters in LDS, one column per thread, so
-// counting is conflict-free and stable.  Two 16-bit counters share a word
-// (digits 2k and 2k+1); a column scan over threads scans both halves at once
-// because no half can exceed BLOCK * ITEMS < 65536.  Keys and values travel
-// through one padded 32-bit LDS plane at a time.
-template <int BLOCK, int ITEMS, int RBITS>
+// LSD radix sort of up to BLOCK * ITEMS keys held in registers, 4-bit digits.
+//
+// Order: item i of thread t stands at position t * ITEMS + i ("blocked"), and
+// every pass is stable in that order.  The starting order is whatever the
+// caller gathered (for an aggregation the order of equal keys is irrelevant);
+// only the validity test differs: in the starting arrangement item i of
+// thread t is valid when i * BLOCK + t < n ("striped"), afterwards when
+// t * ITEMS + i < n.
+//
+// A pass: each thread counts its digits in registers (four 8-bit counters per
+// 32-bit register, so ITEMS <= 255); the 16 counts, widened to 16-bit pairs,
+// go to LDS as 8 columns of one word per thread; every column is scanned over
+// the threads (wave scans), which gives each thread its exclusive prefix per
+// digit, and the digit totals are scanned into digit offsets; each item's new
+// position is digit offset + thread prefix + running count, and the key is
+// written there in the exchange plane and read back blocked.
+template <int BLOCK, int ITEMS>
 struct BlockRadix {
   static constexpr int T = BLOCK * ITEMS;
-  static constexpr int D = 1 << RBITS;
   static constexpr int NW = BLOCK / WAVE;
-  static constexpr int BUF_WORDS = T + T / 32;    // exchange plane, padded every 32 words
-  static constexpr int CNT_WORDS = (D / 2) * BLOCK;
-  static constexpr int DOFF_WORDS = D;
+  static constexpr int BUF_WORDS = T + T / 32;  // exchange plane, padded every 32 words
+  static constexpr int CNT_WORDS = 8 * BLOCK;   // 8 columns of 16-bit digit pairs
+  static constexpr int DOFF_WORDS = 16;
   static_assert(T < 65536, "16-bit counters");
-  static_assert(RBITS >= 1, "digit pairs");
+  static_assert(ITEMS <= 255, "8-bit per-thread counters");
 
   __device__ static inline int pad(int i) { return i + (i >> 5); }
 
-  // `wide` == false: the high words of 64-bit values are all zero and stay so.
-  // Move valid values to their ranks and read them back blocked.
-  template <class V>
-  __device__ static inline void exchange(V (&v)[ITEMS], const uint32_t (&rank)[ITEMS], uint32_t* s_buf, bool wide,
-                                         int n, bool striped) {
-    const int tid = (int)threadIdx.x;
-    const int nplanes = (sizeof(V) == 8 && wide) ? 2 : 1;
-    // a wave whose first blocked position is past n holds nothing after the exchange
-    const bool wave_has = (int)(threadIdx.x & ~(WAVE - 1)) * ITEMS < n;
-    uint32_t lo[ITEMS];
-    for (int plane = 0; plane < nplanes; ++plane) {
-      if (striped) {
-#pragma unroll
-        for (int i = 0; i < ITEMS; ++i) {
-          if (i * BLOCK >= n) continue;
-          if (i * BLOCK + tid < n) s_buf[pad((int)rank[i])] = (uint32_t)((uint64_t)v[i] >> (32 * plane));
-        }
-      } else if (wave_has) {
-#pragma unroll
-        for (int i = 0; i < ITEMS; ++i)
-          if (tid * ITEMS + i < n) s_buf[pad((int)rank[i])] = (uint32_t)((uint64_t)v[i] >> (32 * plane));
-      }
-      __syncthreads();
-      if (wave_has) {
-#pragma unroll
-        for (int i = 0; i < ITEMS; ++i) {
-          uint32_t x = tid * ITEMS + i < n ? s_buf[pad(tid * ITEMS + i)] : 0u;
-          if (plane == 0) lo[i] = x;
-          else v[i] = (V)(((uint64_t)x << 32) | lo[i]);
-        }
-      }
-      __syncthreads();
-    }
-    if (nplanes == 1) {
-#pragma unroll
-      for (int i = 0; i < ITEMS; ++i) v[i] = (V)lo[i];
-    }
+  // register counters: digit d is byte (d & 7) of h[d >> 3] (two 64-bit words,
+  // indexed by shifts so that nothing becomes an indexed private array)
+  __device__ static inline uint32_t get8(uint64_t h0, uint64_t h1, uint32_t d) {
+    return (uint32_t)(((d & 8) ? h1 : h0) >> ((d & 7) * 8)) & 0xFFu;
+  }
+  __device__ static inline void inc8(uint64_t& h0, uint64_t& h1, uint32_t d) {
+    const uint64_t one = 1ull << ((d & 7) * 8);
+    h0 += (d & 8) ? 0ull : one;
+    h1 += (d & 8) ? one : 0ull;
   }
 
-  // Sort the first n keys (in the starting arrangement: item i of thread t is
-  // element i * BLOCK + t) on bits [0, bits); `val` moves with its key when
-  // HAS_VAL.  Afterwards the sorted keys are blocked: position p is item
-  // p % ITEMS of thread p / ITEMS, and positions >= n hold no key.  When
-  // bits <= 32 (and bits > 0), s_buf[pad(p)] still holds the key at position p.
-  template <class K, bool HAS_VAL>
-  __device__ static void sort(K (&key)[ITEMS], uint32_t (&val)[ITEMS], int bits, int n, uint32_t* s_buf,
-                              uint32_t* s_cnt, uint32_t* s_doff) {
+  // Sort the first n 32-bit keys on bits [0, bits); the NV payload arrays
+  // (v0, then v1) move with their keys.  Afterwards position p is item
+  // p % ITEMS of thread p / ITEMS; positions >= n hold no key.  `striped`
+  // gives the validity test of the starting arrangement.  s_buf: BUF_WORDS,
+  // s_cnt: CNT_WORDS, s_doff: DOFF_WORDS (separate regions).
+  template <int NV>
+  __device__ static __forceinline__ void sort(uint32_t (&key)[ITEMS], uint32_t (&v0)[ITEMS], uint32_t (&v1)[ITEMS],
+                                              int bits, int n, bool striped, uint32_t* s_buf, uint32_t* s_cnt,
+                                              uint32_t* s_doff) {
     const int tid = (int)threadIdx.x;
-    bool striped = true;
-    for (int shift = 0; shift < bits; shift += RBITS) {
-      for (int i = tid; i < CNT_WORDS / 4; i += BLOCK) reinterpret_cast<uint4*>(s_cnt)[i] = make_uint4(0, 0, 0, 0);
-      __syncthreads();
-      uint32_t rank[ITEMS];
-      const bool wave_has = striped || (int)(threadIdx.x & ~(WAVE - 1)) * ITEMS < n;
+    for (int shift = 0; shift < bits; shift += 4) {
+      // 1. per-thread digit counts
+      uint64_t h0 = 0, h1 = 0;
 #pragma unroll
-      for (int i = 0; i < ITEMS; ++i) rank[i] = 0;
-      if (wave_has) {
+      for (int i = 0; i < ITEMS; ++i)
+        if ((striped ? i * BLOCK + tid : tid * ITEMS + i) < n) inc8(h0, h1, (key[i] >> shift) & 15u);
+      // 2. widen to 16-bit pairs: column k holds digits 2k (low) and 2k+1 (high)
 #pragma unroll
-        for (int i = 0; i < ITEMS; ++i) {
-          if (striped && i * BLOCK >= n) continue;
-          const bool ok = (striped ? i * BLOCK + tid : tid * ITEMS + i) < n;
-          if (ok) {
-            uint32_t d = (uint32_t)(key[i] >> shift) & (D - 1);
-            uint32_t* c = &s_cnt[(d >> 1) * BLOCK + tid];
-            uint32_t sh = (d & 1) * 16;
-            uint32_t w = *c;
-            rank[i] = (w >> sh) & 0xFFFFu;
-            *c = w + (1u << sh);
-          }
-        }
+      for (int k = 0; k < 8; ++k) {
+        const uint32_t w = (uint32_t)(((k & 4) ? h1 : h0) >> (16 * (k & 3)));
+        s_cnt[k * BLOCK + tid] = (w & 0xFFu) | ((w & 0xFF00u) << 8);
       }
       __syncthreads();
-      // exclusive scan of every counter column over threads; digit totals to s_doff
-      for (int k = wave_id(); k < D / 2; k += NW) {
+      // 3. exclusive scan of every column over the threads; digit totals
+      for (int k = wave_id(); k < 8; k += NW) {
         uint32_t run = 0;
 #pragma unroll
         for (int c0 = 0; c0 < BLOCK; c0 += WAVE) {
-          uint32_t a = s_cnt[k * BLOCK + c0 + lane_id()];
-          uint32_t inc = wave_incl_scan(a);
+          const uint32_t a = s_cnt[k * BLOCK + c0 + lane_id()];
+          const uint32_t inc = wave_incl_scan(a);
           s_cnt[k * BLOCK + c0 + lane_id()] = run + inc - a;
           run += __shfl(inc, WAVE - 1, WAVE);
         }
@@ -193,34 +163,59 @@ struct BlockRadix {
       }
       __syncthreads();
       if (tid < WAVE) {
-        uint32_t acc = 0;
-        for (int d0 = 0; d0 < D; d0 += WAVE) {
-          int d = d0 + lane_id();
-          uint32_t a = d < D ? s_doff[d] : 0;
-          uint32_t inc = wave_incl_scan(a);
-          if (d < D) s_doff[d] = acc + inc - a;
-          acc += __shfl(inc, WAVE - 1, WAVE);
-        }
+        const uint32_t a = lane_id() < 16 ? s_doff[lane_id()] : 0u;
+        const uint32_t inc = wave_incl_scan(a);
+        if (lane_id() < 16) s_doff[lane_id()] = inc - a;
       }
       __syncthreads();
-      if (wave_has) {
+      // 4. positions: digit offset + thread prefix + running count
+      uint64_t r0 = 0, r1 = 0;
+      if constexpr (NV == 0) {
+        // one plane: write each key as soon as its position is known
 #pragma unroll
         for (int i = 0; i < ITEMS; ++i) {
-          if (striped && i * BLOCK >= n) continue;
-          const bool ok = (striped ? i * BLOCK + tid : tid * ITEMS + i) < n;
-          if (ok) {
-            uint32_t d = (uint32_t)(key[i] >> shift) & (D - 1);
-            uint32_t w = s_cnt[(d >> 1) * BLOCK + tid];
-            rank[i] += ((w >> ((d & 1) * 16)) & 0xFFFFu) + s_doff[d];
+          if ((striped ? i * BLOCK + tid : tid * ITEMS + i) < n) {
+            const uint32_t d = (key[i] >> shift) & 15u;
+            const uint32_t pre = (s_cnt[(d >> 1) * BLOCK + tid] >> ((d & 1) * 16)) & 0xFFFFu;
+            s_buf[pad((int)(s_doff[d] + pre + get8(r0, r1, d)))] = key[i];
+            inc8(r0, r1, d);
           }
         }
+        __syncthreads();
+#pragma unroll
+        for (int i = 0; i < ITEMS; ++i) key[i] = tid * ITEMS + i < n ? s_buf[pad(tid * ITEMS + i)] : 0u;
+        __syncthreads();
+      } else {
+        uint32_t pos[ITEMS];
+#pragma unroll
+        for (int i = 0; i < ITEMS; ++i) {
+          pos[i] = 0;
+          if ((striped ? i * BLOCK + tid : tid * ITEMS + i) < n) {
+            const uint32_t d = (key[i] >> shift) & 15u;
+            const uint32_t pre = (s_cnt[(d >> 1) * BLOCK + tid] >> ((d & 1) * 16)) & 0xFFFFu;
+            pos[i] = s_doff[d] + pre + get8(r0, r1, d);
+            inc8(r0, r1, d);
+          }
+        }
+        exchange_u32(v0, pos, s_buf, n, striped);
+        if constexpr (NV == 2) exchange_u32(v1, pos, s_buf, n, striped);
+        exchange_u32(key, pos, s_buf, n, striped);
       }
-      __syncthreads();
-      // values first, so that the plane left in s_buf holds the keys' low words
-      if constexpr (HAS_VAL) exchange(val, rank, s_buf, true, n, striped);
-      exchange(key, rank, s_buf, bits > 32, n, striped);
       striped = false;
     }
+  }
+
+  // Move valid v[i] to position pos[i] and read the plane back blocked.
+  __device__ static inline void exchange_u32(uint32_t (&v)[ITEMS], const uint32_t (&pos)[ITEMS], uint32_t* s_buf,
+                                             int n, bool striped) {
+    const int tid = (int)threadIdx.x;
+#pragma unroll
+    for (int i = 0; i < ITEMS; ++i)
+      if ((striped ? i * BLOCK + tid : tid * ITEMS + i) < n) s_buf[pad((int)pos[i])] = v[i];
+    __syncthreads();
+#pragma unroll
+    for (int i = 0; i < ITEMS; ++i) v[i] = tid * ITEMS + i < n ? s_buf[pad(tid * ITEMS + i)] : 0u;
+    __syncthreads();
   }
 };
 

@@ -280,6 +280,75 @@ hpa_structure_map::~hpa_structure_map() {
   if (learned) hpa::learned_free(learned);
 }
 
+namespace {
+
+// Dense coordinates for a map (see hpa_structure_map): intervals closer than
+// `gap` form one cluster; each cluster widened by 1 MiB on both sides (so
+// nearby addresses outside every function stay on the grid) and rounded to
+// 4 KiB pages is a window; overlapping windows merge.  The gap grows until at
+// most DENSE_MAX_WIN windows remain.  The grid step 2^tz is the largest power
+// of two (at most 4 KiB) dividing every interval boundary.
+void build_dense(hpa_structure_map* m, const std::vector<uint64_t>& start, const std::vector<uint64_t>& end,
+                 const std::vector<uint32_t>& scope, hipStream_t stream) {
+  const size_t n = start.size();
+  if (n == 0) return;
+  uint64_t orv = 0;
+  for (size_t i = 0; i < n; ++i) orv |= start[i] | end[i];
+  const uint32_t tz = orv ? std::min<uint32_t>((uint32_t)__builtin_ctzll(orv), 12) : 12;
+  const uint64_t MARGIN = 1ull << 20, PAGE = 4096, TOP = ~0ull & ~(PAGE - 1);
+  std::vector<std::pair<uint64_t, uint64_t>> win;
+  for (uint64_t gap = 1ull << 21;; gap = gap > (1ull << 60) ? ~0ull : gap * 4) {
+    std::vector<std::pair<uint64_t, uint64_t>> cl;
+    uint64_t lo = start[0], hi = end[0];
+    for (size_t i = 1; i < n; ++i) {
+      if (start[i] - hi <= gap) {
+        hi = std::max(hi, end[i]);
+      } else {
+        cl.push_back({lo, hi});
+        lo = start[i];
+        hi = end[i];
+      }
+    }
+    cl.push_back({lo, hi});
+    win.clear();
+    for (auto [l, h] : cl) {
+      uint64_t l2 = (l >= MARGIN ? l - MARGIN : 0) & ~(PAGE - 1);
+      uint64_t h2 = h >= TOP - MARGIN ? TOP : ((h + MARGIN + PAGE - 1) & ~(PAGE - 1));
+      if (!win.empty() && l2 <= win.back().second) win.back().second = std::max(win.back().second, h2);
+      else win.push_back({l2, h2});
+    }
+    if (win.size() <= DENSE_MAX_WIN || gap == ~0ull) break;
+  }
+  if (win.size() > DENSE_MAX_WIN) return;
+  std::vector<uint64_t> lo(win.size()), hi(win.size()), d(win.size() + 1);
+  uint64_t total = 0;
+  for (size_t w = 0; w < win.size(); ++w) {
+    lo[w] = win[w].first;
+    hi[w] = win[w].second;
+    d[w] = total;
+    total += (hi[w] - lo[w]) >> tz;
+    if (total > (1ull << 26)) return;
+  }
+  d[win.size()] = total;
+  std::vector<uint32_t> tab(total, NONE32);
+  size_t w = 0;
+  for (size_t i = 0; i < n; ++i) {
+    while (start[i] >= hi[w]) ++w;
+    const uint64_t a = d[w] + ((start[i] - lo[w]) >> tz), b = d[w] + ((end[i] - lo[w]) >> tz);
+    std::fill(tab.begin() + a, tab.begin() + b, scope[i]);
+  }
+  m->dense = true;
+  m->dense_tz = tz;
+  m->n_win = (uint32_t)win.size();
+  m->n_dense = total;
+  m->win_lo = upload(m->ctx, lo, stream);
+  m->win_hi = upload(m->ctx, hi, stream);
+  m->win_d = upload(m->ctx, d, stream);
+  m->scope_of = upload(m->ctx, tab, stream);
+}
+
+}  // namespace
+
 extern "C" hpa_status hpa_build_structure_map(hpa_ctx* ctx, const hpa_structure_desc* desc, hipStream_t stream,
                                               hpa_structure_map** out) {
   return guard([&] {
@@ -317,6 +386,7 @@ extern "C" hpa_status hpa_build_structure_map(hpa_ctx* ctx, const hpa_structure_
       m->top_n = (uint32_t)top.size();
       m->top_shift = shift;
       m->top = upload(ctx, top, stream);
+      build_dense(m, b.start, b.end, b.scope, stream);
       m->h_parent = b.parent;
       m->h_func = b.func;
       m->h_kind = b.kind;

@@ -167,6 +167,16 @@ struct hpa_structure_map {
   std::vector<uint8_t> h_kind;
   std::vector<uint64_t> h_start, h_end;     // host copies of the intervals
   std::vector<uint32_t> h_scope;
+  // Dense instruction coordinates.  The code lies in a few windows
+  // [win_lo, win_hi); an address inside window w that is a multiple of
+  // 2^dense_tz away from win_lo[w] has the coordinate
+  // win_d[w] + ((pc - win_lo[w]) >> dense_tz), and scope_of[coordinate] is its
+  // innermost scope.  dense is false when there is no code or the coordinates
+  // would need more than 2^26 entries.
+  bool dense = false;
+  uint32_t dense_tz = 0, n_win = 0;
+  uint64_t n_dense = 0;
+  hpa::DBuf win_lo, win_hi, win_d, scope_of;
   ~hpa_structure_map();
 };
 
@@ -180,6 +190,46 @@ struct hpa_attribution {
 };
 
 namespace hpa {
+
+constexpr uint32_t DENSE_MAX_WIN = 64;  // windows are staged in LDS by the kernels
+
+// Device view of the dense coordinates (tables may be staged in LDS).
+struct DenseDev {
+  const uint64_t* lo;
+  const uint64_t* hi;
+  const uint64_t* d;         // n_win + 1 entries: first coordinate of each window, then the total
+  const uint32_t* scope_of;  // n_dense entries (global memory)
+  uint32_t n_win;
+  uint32_t tz;
+};
+
+__device__ inline uint32_t last_le(const uint64_t* a, uint32_t n, uint64_t v) {
+  // last i < n with a[i] <= v, or n when there is none (a ascending)
+  if (n == 0 || a[0] > v) return n;
+  uint32_t lo = 0, hi = n;
+  while (hi - lo > 1) {
+    const uint32_t mid = (lo + hi) >> 1;
+    if (a[mid] <= v) lo = mid;
+    else hi = mid;
+  }
+  return lo;
+}
+
+// Coordinate of pc, or false when pc lies outside every window or off the grid.
+__device__ inline bool to_dense(const DenseDev& t, uint64_t pc, uint64_t& D) {
+  if (t.n_win == 0) return false;
+  const uint32_t w = last_le(t.lo, t.n_win, pc);
+  if (w == t.n_win || pc >= t.hi[w]) return false;
+  const uint64_t off = pc - t.lo[w];
+  if (off & ((1ull << t.tz) - 1)) return false;
+  D = t.d[w] + (off >> t.tz);
+  return true;
+}
+
+__device__ inline uint64_t from_dense(const DenseDev& t, uint64_t D) {
+  const uint32_t w = last_le(t.d, t.n_win, D);
+  return t.lo[w] + ((D - t.d[w]) << t.tz);
+}
 
 // Plain lookup used by several kernels: interval index of pc or NONE32.
 __device__ inline uint32_t find_interval(const uint64_t* __restrict__ start, const uint64_t* __restrict__ end,

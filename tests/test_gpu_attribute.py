@@ -185,3 +185,50 @@ def test_attribute_deterministic(hpa, hctx):
     r2 = hpa.attribute(hctx, m, pc, cx, st, None, w.n_ctx).numpy()
     for k in r1:
         assert np.array_equal(r1[k], r2[k]), k
+
+
+@pytest.mark.parametrize("weighted", [False, True])
+def test_attribute_far_and_offgrid_pcs(hpa, hctx, weighted):
+    """PCs far outside the code (keys wider than 32 bits: the unit pass reruns
+    with the general kernel) and PCs off the instruction grid (raw-pc keys)."""
+    w = tiny_random_case(11, n_samples=20_000, n_ctx=6, weighted=weighted)
+    w.pc[::7] += np.uint64(1 << 50)
+    m, om, a, oa = _run(hpa, hctx, w)
+    assert_attribution_equal(a.numpy(), oa, "far")
+    w = tiny_random_case(12, n_samples=20_000, n_ctx=6, weighted=weighted)
+    w.pc[::5] += np.uint64(3)
+    m, om, a, oa = _run(hpa, hctx, w)
+    assert_attribution_equal(a.numpy(), oa, "off-grid")
+
+
+def test_attribute_giant_context_far_pcs(hpa, hctx):
+    # one context over many chunks, some chunks with far PCs (general chunk kernel)
+    w = small_config(22, n_samples=120_000, n_ctx=3, seg_mean=5000)
+    w.ctx[:] = 2
+    w.pc[50_000:50_100] += np.uint64(1 << 52)
+    m, om, a, oa = _run(hpa, hctx, w)
+    assert_attribution_equal(a.numpy(), oa, "giant far")
+
+
+def test_attribute_map_without_dense_coordinates(hpa, hctx):
+    """Functions scattered far apart: the map has no dense coordinates, so
+    every key is labelled by the separate binary-search pass."""
+    r = np.random.default_rng(5)
+    n_f = 200
+    starts = (np.arange(n_f, dtype=np.uint64) << np.uint64(36)) + np.uint64(0x1000)
+    w = tiny_random_case(13, n_samples=10, n_ctx=4)
+    w.scope_start = starts
+    w.scope_end = starts + np.uint64(256)
+    w.scope_id = np.arange(n_f, dtype=np.uint32)
+    w.scope_kind = np.zeros(n_f, dtype=np.uint32)
+    w.line_start = w.line_end = w.line_file = w.line_line = None
+    w.n_scope_ids = n_f
+    n = 50_000
+    f = r.integers(0, n_f, n).astype(np.uint64)
+    w.pc = starts[f] + (r.integers(0, 16, n).astype(np.uint64) << np.uint64(4))
+    w.pc[::97] = np.uint64(5)
+    w.ctx = np.repeat(r.integers(0, 4, n // 500), 500).astype(np.uint32)
+    w.stall = r.integers(0, 16, n).astype(np.uint8)
+    w.weight = None
+    m, om, a, oa = _run(hpa, hctx, w)
+    assert_attribution_equal(a.numpy(), oa, "no dense map")
