@@ -36,7 +36,7 @@ constexpr int SCAN_BLOCK = 256;
 constexpr int SCAN_ITEMS = 16;
 constexpr int SCAN_TILE = SCAN_BLOCK * SCAN_ITEMS;  // samples per scan tile
 
-constexpr int UBLOCK = 512;
+constexpr int UBLOCK = 1024;
 constexpr int UITEMS = 16;
 constexpr int UT = UBLOCK * UITEMS;  // unit capacity (samples)
 constexpr int UHALF = UT / 2;        // contexts up to this size are packed together
@@ -70,6 +70,27 @@ __device__ inline int bits_for(uint64_t v) { return v ? 64 - __clzll(v) : 0; }
 // ----------------------------------------------------------------------------
 // scan_ctx: run detection over ctx[] (Section 4.2: one placeholder per buffer)
 // ----------------------------------------------------------------------------
+// Each workgroup owns a contiguous range of tiles.  It counts the run heads of
+// its range first, reserves that many run slots with one atomic, then walks the
+// range again writing the runs and adding each run to its context's histogram
+// word (one 64-bit atomic per run: run count << 40 | samples).  A run is cut at
+// every tile start.
+__device__ inline void scan_tile_heads(const uint32_t* __restrict__ ctx, uint64_t t0, int cnt, uint32_t* s_ctx,
+                                       uint64_t (&mask)[SCAN_ITEMS]) {
+  const int tid = threadIdx.x;
+#pragma unroll
+  for (int i = 0; i < SCAN_ITEMS; ++i) {
+    const int j = i * SCAN_BLOCK + tid;
+    if (j < cnt) s_ctx[j] = ctx[t0 + j];
+  }
+  __syncthreads();
+#pragma unroll
+  for (int i = 0; i < SCAN_ITEMS; ++i) {
+    const int j = i * SCAN_BLOCK + tid;
+    mask[i] = __ballot(j < cnt && (j == 0 || s_ctx[j] != s_ctx[j - 1]));
+  }
+}
+
 __global__ void __launch_bounds__(SCAN_BLOCK)
 k_scan_ctx(const uint32_t* __restrict__ ctx, uint64_t n, uint32_t n_ctx, unsigned long long* __restrict__ hist,
            Run* __restrict__ runs, uint64_t run_cap, PlanInfo* __restrict__ info) {
@@ -80,58 +101,73 @@ k_scan_ctx(const uint32_t* __restrict__ ctx, uint64_t n, uint32_t n_ctx, unsigne
   __shared__ uint32_t s_R;
   const int tid = threadIdx.x;
   const uint64_t n_tiles = (n + SCAN_TILE - 1) / SCAN_TILE;
-  for (uint64_t tile = blockIdx.x; tile < n_tiles; tile += gridDim.x) {
+  const uint64_t per = (n_tiles + gridDim.x - 1) / gridDim.x;
+  const uint64_t tb = (uint64_t)blockIdx.x * per, te = min(n_tiles, tb + per);
+  if (tb >= te) return;
+  // 1. count the heads of the range
+  unsigned long long mine = 0;
+  for (uint64_t tile = tb; tile < te; ++tile) {
     const uint64_t t0 = tile * SCAN_TILE;
     const int cnt = (int)min((uint64_t)SCAN_TILE, n - t0);
-#pragma unroll
-    for (int i = 0; i < SCAN_ITEMS; ++i) {
-      int j = i * SCAN_BLOCK + tid;
-      if (j < cnt) s_ctx[j] = ctx[t0 + j];
-    }
-    __syncthreads();
-    // head flags in striped order; rank among heads = prefix over (item, wave, lane)
     uint64_t mask[SCAN_ITEMS];
+    scan_tile_heads(ctx, t0, cnt, s_ctx, mask);
+    if (lane_id() == 0)
 #pragma unroll
-    for (int i = 0; i < SCAN_ITEMS; ++i) {
-      int j = i * SCAN_BLOCK + tid;
-      bool h = j < cnt && (j == 0 || s_ctx[j] != s_ctx[j - 1]);
-      mask[i] = __ballot(h);
-      if (lane_id() == 0) s_wcnt[i][wave_id()] = (uint32_t)__popcll(mask[i]);
-    }
+      for (int i = 0; i < SCAN_ITEMS; ++i) mine += (unsigned long long)__popcll(mask[i]);
+    __syncthreads();
+  }
+  if (lane_id() == 0) s_wcnt[0][wave_id()] = (uint32_t)mine;
+  __syncthreads();
+  if (tid == 0) {
+    unsigned long long tot = 0;
+    for (int w = 0; w < SCAN_BLOCK / WAVE; ++w) tot += s_wcnt[0][w];
+    s_base = atomicAdd(&info->n_runs, tot);
+  }
+  __syncthreads();
+  unsigned long long base = s_base;
+  // 2. write the runs
+  for (uint64_t tile = tb; tile < te; ++tile) {
+    const uint64_t t0 = tile * SCAN_TILE;
+    const int cnt = (int)min((uint64_t)SCAN_TILE, n - t0);
+    uint64_t mask[SCAN_ITEMS];
+    scan_tile_heads(ctx, t0, cnt, s_ctx, mask);
+    // rank among the tile's heads = prefix over (item, wave, lane)
+    if (lane_id() == 0)
+#pragma unroll
+      for (int i = 0; i < SCAN_ITEMS; ++i) s_wcnt[i][wave_id()] = (uint32_t)__popcll(mask[i]);
     __syncthreads();
     if (tid == 0) {
       uint32_t run = 0;
       for (int i = 0; i < SCAN_ITEMS; ++i)
         for (int w = 0; w < SCAN_BLOCK / WAVE; ++w) {
-          uint32_t t = s_wcnt[i][w];
+          const uint32_t t = s_wcnt[i][w];
           s_wcnt[i][w] = run;
           run += t;
         }
       s_R = run;
-      s_base = atomicAdd(&info->n_runs, (unsigned long long)run);
     }
     __syncthreads();
 #pragma unroll
     for (int i = 0; i < SCAN_ITEMS; ++i) {
-      int j = i * SCAN_BLOCK + tid;
-      uint64_t below = mask[i] & ((1ull << lane_id()) - 1);
+      const int j = i * SCAN_BLOCK + tid;
+      const uint64_t below = mask[i] & ((1ull << lane_id()) - 1);
       if ((mask[i] >> lane_id()) & 1) s_head[s_wcnt[i][wave_id()] + (uint32_t)__popcll(below)] = (uint32_t)j;
     }
     __syncthreads();
     const uint32_t R = s_R;
-    const unsigned long long base = s_base;
     for (uint32_t k = tid; k < R; k += SCAN_BLOCK) {
-      uint32_t p = s_head[k];
-      uint32_t len = (k + 1 < R ? s_head[k + 1] : (uint32_t)cnt) - p;
-      uint32_t c = s_ctx[p];
+      const uint32_t p = s_head[k];
+      const uint32_t len = (k + 1 < R ? s_head[k + 1] : (uint32_t)cnt) - p;
+      const uint32_t c = s_ctx[p];
       if (c >= n_ctx) {
         atomicOr(&info->err, (uint32_t)ERR_CTX);
         continue;
       }
       atomicAdd(&hist[c], (1ull << 40) | (unsigned long long)len);
-      uint64_t g = base + k;
+      const uint64_t g = base + k;
       if (g < run_cap) runs[g] = Run{t0 + p, 0, len, c};
     }
+    base += R;
     __syncthreads();
   }
 }
