@@ -13,11 +13,12 @@
 //               into work units of <= T samples, list of contexts > T samples.
 //   group_runs  order the run list by context (atomic cursors; a run learns
 //               its offset inside its context from the same atomic).
-//   units       one workgroup per unit, taken in context order by ticket:
-//               gather the unit's samples from its runs (pc 8 B + stall 1 B,
-//               read once), pack keys relative to each context's smallest pc,
-//               LSD radix sort in LDS, run-length reduce, decoupled look-back
-//               over units for the output offset, scope lookup, write.
+//   units       one workgroup per unit: gather the unit's samples from its
+//               runs (pc 8 B + stall 1 B, read once), map pcs to dense
+//               coordinates, pack keys, LSD radix sort in LDS, run-length
+//               reduce, stage the packed unique keys at the unit's first sample
+//               position; then a scan gives the output offsets and a write
+//               pass unpacks the keys (pc, scope label from the dense table).
 //   big path    contexts over T samples: chunk sort, pairwise merge rounds,
 //               duplicate combine, written where the unit pass placed them.
 //
@@ -44,7 +45,7 @@ constexpr int MAXC = 64;             // contexts per unit
 using Sorter = BlockRadix<UBLOCK, UITEMS>;
 
 constexpr uint64_t M40 = (1ull << 40) - 1;
-constexpr int ERR_CTX = 1, ERR_STALL = 2, ERR_WIDE = 4, ERR_RETRY = 8;
+constexpr int ERR_CTX = 1, ERR_STALL = 2, ERR_WIDE = 4;
 constexpr uint64_t WIDE_CHUNK = ~0ull;  // chunk list length: left for the general chunk kernel
 
 struct Run {
@@ -337,7 +338,7 @@ struct SortSmem {
   uint32_t doff[Sorter::DOFF_WORDS];
   unsigned long long pcmin[MAXC];
   uint32_t ucnt[MAXC + 1];
-  unsigned long long red_or, red_max;
+  unsigned long long red_or, red_max, red_min, red_ref;
   unsigned long long scan_tmp[UBLOCK / WAVE + 1];
   uint32_t last_hi[UBLOCK], last_lo[UBLOCK];
   unsigned long long prefix;
@@ -506,47 +507,6 @@ __device__ inline void sort_reduce(SortSmem& sm, Gathered<WEIGHTED>& g, uint64_t
   }
 }
 
-__device__ inline void publish(unsigned long long* status, uint32_t u, unsigned long long flag,
-                               unsigned long long value) {
-  __hip_atomic_store(&status[u], (flag << 62) | value, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
-}
-
-// Decoupled look-back over units in ticket order, run by one whole wave: each
-// probe reads the status words of the 64 nearest predecessors, finds the
-// nearest one holding an inclusive prefix, and waits only if a predecessor
-// before it has not published yet.  Returns the exclusive prefix (all lanes).
-__device__ inline unsigned long long lookback(unsigned long long* status, uint32_t u, unsigned long long agg) {
-  constexpr unsigned long long VMASK = (1ull << 62) - 1;
-  const int lane = lane_id();
-  if (u == 0) {
-    if (lane == 0) publish(status, 0, 2, agg);
-    return 0;
-  }
-  if (lane == 0) publish(status, u, 1, agg);
-  unsigned long long acc = 0;
-  int64_t base = (int64_t)u - 1;
-  while (true) {
-    const int64_t j = base - lane;
-    // before unit 0 there is nothing: read as an inclusive prefix of 0
-    unsigned long long st = j >= 0 ? __hip_atomic_load(&status[j], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)
-                                   : (2ull << 62);
-    const unsigned long long f = st >> 62;
-    const uint64_t have_p = __ballot(f == 2);
-    const uint64_t not_ready = __ballot(f == 0);
-    const int p0 = have_p ? __ffsll((long long)have_p) - 1 : WAVE;
-    const uint64_t need = p0 >= WAVE - 1 ? ~0ull : ((1ull << (p0 + 1)) - 1);
-    if (not_ready & need) {
-      __builtin_amdgcn_s_sleep(2);
-      continue;
-    }
-    acc += wave_sum(lane <= p0 ? (st & VMASK) : 0ull);
-    if (p0 < WAVE) break;
-    base -= WAVE;
-  }
-  if (lane == 0) publish(status, u, 2, acc + agg);
-  return acc;
-}
-
 struct MapDev {
   const uint64_t* start;
   const uint64_t* end;
@@ -563,48 +523,47 @@ struct OutDev {
   uint64_t* ctx_off;
 };
 
-// Per-unit key statistics: per-context smallest pc, common trailing zeros, widest span.
+// Per-unit key statistics: the unit's smallest coordinate (every context's key
+// is taken relative to it), the common trailing zeros of all differences, and
+// the span in bits.  The lowest set bit of a - b is the lowest bit where a and
+// b differ, so the common trailing zeros of all differences are those of the
+// OR of every value XOR one reference value.
 template <bool WEIGHTED>
 __device__ inline void key_stats(SortSmem& sm, const Gathered<WEIGHTED>& g, uint64_t n_u, uint32_t n_cu, uint32_t* err,
                                  int& kbits, int& pcb, uint32_t& tz) {
-  for (uint32_t l = threadIdx.x; l < n_cu; l += UBLOCK) sm.pcmin[l] = ~0ull;
-  if (threadIdx.x == 0) { sm.red_or = 0; sm.red_max = 0; }
+  if (threadIdx.x == 0) { sm.red_or = 0; sm.red_max = 0; sm.red_min = ~0ull; }
+  const uint64_t ref = n_u ? g.pc[0] : 0;  // thread 0's first item; broadcast below
+  if (threadIdx.x == 0) sm.red_ref = ref;
   __syncthreads();
-#pragma unroll
-  for (int i = 0; i < UITEMS; ++i) {
-    if ((uint64_t)i * UBLOCK >= n_u) continue;
-    const bool v = (uint64_t)i * UBLOCK + threadIdx.x < n_u;
-    // items of one wave mostly share a context: reduce in the wave first
-    const uint32_t lc = v ? g.lc(i) : NONE32;
-    const uint32_t lc0 = wave_min(lc);
-    if (lc0 == NONE32) continue;  // no valid item in this wave
-    if (wave_max(v ? lc : lc0) == lc0) {
-      const unsigned long long m = wave_min(v ? (unsigned long long)g.pc[i] : ~0ull);
-      if (lane_id() == 0) atomicMin(&sm.pcmin[lc0], m);
-    } else if (v) {
-      atomicMin(&sm.pcmin[lc], (unsigned long long)g.pc[i]);
-    }
-  }
-  __syncthreads();
-  unsigned long long o = 0, mx = 0;
+  const uint64_t r = sm.red_ref;
+  unsigned long long mn = ~0ull, mx = 0, ox = 0;
 #pragma unroll
   for (int i = 0; i < UITEMS; ++i) {
     if ((uint64_t)i * UBLOCK >= n_u) continue;
     if ((uint64_t)i * UBLOCK + threadIdx.x < n_u) {
-      unsigned long long r = g.pc[i] - sm.pcmin[g.lc(i)];
-      o |= r;
-      mx = r > mx ? r : mx;
+      const unsigned long long v = g.pc[i];
+      mn = v < mn ? v : mn;
+      mx = v > mx ? v : mx;
+      ox |= v ^ r;
     }
   }
-  o = wave_or(o);
+  mn = wave_min(mn);
   mx = wave_max(mx);
-  if (lane_id() == 0) { atomicOr(&sm.red_or, o); atomicMax(&sm.red_max, mx); }
+  ox = wave_or(ox);
+  if (lane_id() == 0) {
+    atomicMin(&sm.red_min, mn);
+    atomicMax(&sm.red_max, mx);
+    atomicOr(&sm.red_or, ox);
+  }
   __syncthreads();
+  const unsigned long long lo = sm.red_min;
   tz = sm.red_or ? (uint32_t)__ffsll((long long)sm.red_or) - 1 : 0;
-  pcb = bits_for(sm.red_max >> tz);
+  pcb = bits_for((sm.red_max - lo) >> tz);
+  for (uint32_t l = threadIdx.x; l < n_cu; l += UBLOCK) sm.pcmin[l] = lo;
   int cbits = bits_for(n_cu > 0 ? n_cu - 1 : 0);
   kbits = cbits + pcb + 4;
   if (kbits > 63 && threadIdx.x == 0) atomicOr(err, (uint32_t)ERR_WIDE);
+  __syncthreads();
 }
 
 // After the sort (keys blocked in registers): head flags, the unique count,
@@ -688,8 +647,25 @@ __device__ inline void weighted_counts(const SortSmem& sm, const K (&key)[UITEMS
 }
 
 // ----------------------------------------------------------------------------
-// units: the ordered pass
+// units: sort pass, offsets, write pass
+//
+// The sort pass treats every unit on its own: the unit's unique keys, still
+// packed and in order, go to a staging area at the unit's first sample
+// position (a unit never has more unique keys than samples) together with
+// their counts and the unit's decoding parameters.  A scan over the units'
+// key counts then gives every unit its output offset and every context its
+// key range, and the write pass unpacks the keys (coordinate -> pc, scope
+// label) into the outputs.  No unit waits for another.
 // ----------------------------------------------------------------------------
+struct UnitMeta {
+  unsigned long long lo;  // smallest coordinate of the unit (keys are relative to it)
+  uint32_t nU;            // unique keys
+  uint16_t pcb, tz;       // coordinate field width, common trailing zeros
+  uint32_t flags;         // UM_* bits
+  uint32_t pad;
+};
+constexpr uint32_t UM_DONE = 1, UM_WIDE = 2, UM_DENSE = 4;
+
 struct UnitArgs {
   const uint64_t* pc;
   const uint8_t* stall;
@@ -699,134 +675,73 @@ struct UnitArgs {
   const Run* grouped;
   const uint32_t* unit_begin;
   const int32_t* unit_big;
-  const uint64_t* big_U;
-  uint64_t* big_out;
-  unsigned long long* status;
-  unsigned int* ticket;
   PlanInfo* info;
   uint32_t n_units;
   uint32_t n_ctx;
-  MapDev map;
-  OutDev out;
   DenseDev dd;
-  int dense;  // the map has dense coordinates: units write scope labels themselves
+  int dense;                   // the map has dense coordinates
+  UnitMeta* meta;              // per unit
+  uint32_t* ucnt;              // per unit, MAXC entries: unique keys per local context
+  uint32_t* skey;              // staging, by sample position: packed key (low word)
+  uint32_t* shi;               // high word (units with keys wider than 32 bits)
+  uint32_t* scnt;              // count (unweighted)
+  unsigned long long* scnt64;  // count (weighted)
 };
 
-// Hand the unit's unique keys to `emit(ui, local ctx, coordinate, stall,
-// count)` in unique-key order.  32-bit keys come from their compacted copy in
-// LDS, so consecutive lanes take consecutive keys (coalesced output); wider
-// keys are emitted by the thread that holds them.  The coordinate is the
-// dense coordinate or the pc, whichever the keys were built from.
-template <class K, class Emit>
-__device__ inline void emit_keys(const SortSmem& sm, const K (&key)[UITEMS], uint64_t n_u, uint32_t first,
-                                 uint32_t nU, int pcb, uint32_t tz, Emit&& emit) {
-  const uint64_t pmask = pcb >= 64 ? ~0ull : ((1ull << pcb) - 1);
-  if constexpr (sizeof(K) == 4) {
-    for (uint32_t ui = threadIdx.x; ui < nU; ui += UBLOCK) {
-      const uint64_t kk = sm.buf[ui];
-      const uint32_t cnt = (uint32_t)sm.upos[ui + 1] - (uint32_t)sm.upos[ui];
-      const uint32_t lc = (uint32_t)(kk >> (pcb + 4));
-      emit(ui, lc, sm.pcmin[lc] + (((kk >> 4) & pmask) << tz), (uint8_t)(kk & 15), cnt);
-    }
-  } else {
-    K prev = prev_last<K>(sm, threadIdx.x);
-    uint32_t ui = first;
-#pragma unroll
-    for (int i = 0; i < UITEMS; ++i) {
-      uint32_t p = threadIdx.x * UITEMS + i;
-      bool h = p < n_u && (p == 0 || key[i] != prev);
-      prev = key[i];
-      if (!h) continue;
-      const uint64_t kk = (uint64_t)key[i];
-      const uint32_t lc = (uint32_t)(kk >> (pcb + 4));
-      emit(ui, lc, sm.pcmin[lc] + (((kk >> 4) & pmask) << tz), (uint8_t)(kk & 15), (uint32_t)sm.upos[ui + 1] - p);
-      ++ui;
-    }
-  }
-}
-
+// Stage the unit's unique keys, counts and decoding parameters.
 template <bool WEIGHTED, class K>
-__device__ __forceinline__ void unit_body(SortSmem& sm, const UnitArgs& a, uint32_t u, uint32_t cb, uint32_t ce, uint64_t n_u,
-                          Gathered<WEIGHTED>& g, int kbits, int pcb, uint32_t tz, bool dense, const DenseDev& t) {
+__device__ __forceinline__ void unit_body(SortSmem& sm, const UnitArgs& a, uint32_t u, uint32_t cb, uint32_t ce,
+                                          uint64_t n_u, Gathered<WEIGHTED>& g, int kbits, int pcb, uint32_t tz,
+                                          bool dense) {
   const uint32_t n_cu = ce - cb;
   K key[UITEMS];
   uint32_t val[UITEMS];
   sort_reduce<WEIGHTED, K>(sm, g, n_u, n_cu, key, val, kbits, pcb, tz);
   uint32_t first, nU;
   find_heads<K>(sm, key, n_u, n_cu, pcb, first, nU);
-  if (threadIdx.x < WAVE) {
-    unsigned long long p = lookback(a.status, u, nU);
-    if (threadIdx.x == 0) sm.prefix = p;
-  }
-  __syncthreads();
-  const unsigned long long prefix = sm.prefix;
-  // context offsets: exclusive scan of unique counts per local context
-  if (threadIdx.x == 0) {
-    unsigned long long run = prefix;
-    for (uint32_t l = 0; l < n_cu; ++l) {
-      a.out.ctx_off[cb + l] = run;
-      run += sm.ucnt[l];
+  const uint64_t s0 = a.sbase[cb];
+  for (uint32_t l = threadIdx.x; l < n_cu; l += UBLOCK) a.ucnt[(uint64_t)u * MAXC + l] = sm.ucnt[l];
+  if (threadIdx.x == 0)
+    a.meta[u] = UnitMeta{sm.pcmin[0], nU, (uint16_t)pcb, (uint16_t)tz,
+                         UM_DONE | (sizeof(K) == 8 ? UM_WIDE : 0u) | (dense ? UM_DENSE : 0u), 0u};
+  uint32_t* const skey = a.skey + s0;
+  uint32_t* const scnt = a.scnt + s0;
+  if constexpr (sizeof(K) == 4) {
+    // consecutive lanes take consecutive keys from the compacted copy in LDS
+    for (uint32_t ui = threadIdx.x; ui < nU; ui += UBLOCK) {
+      skey[ui] = sm.buf[ui];
+      if constexpr (!WEIGHTED) scnt[ui] = (uint32_t)sm.upos[ui + 1] - (uint32_t)sm.upos[ui];
     }
-    if (u + 1 == a.n_units) {
-      a.out.ctx_off[a.n_ctx] = run;
-      a.info->total_keys = run;
+  } else {
+    uint32_t* const shi = a.shi + s0;
+    K prev = prev_last<K>(sm, threadIdx.x);
+    uint32_t ui = first;
+#pragma unroll
+    for (int i = 0; i < UITEMS; ++i) {
+      const uint32_t p = threadIdx.x * UITEMS + i;
+      const bool h = p < n_u && (p == 0 || key[i] != prev);
+      prev = key[i];
+      if (!h) continue;
+      skey[ui] = (uint32_t)(uint64_t)key[i];
+      shi[ui] = (uint32_t)((uint64_t)key[i] >> 32);
+      if constexpr (!WEIGHTED) scnt[ui] = (uint32_t)sm.upos[ui + 1] - p;
+      ++ui;
     }
   }
-  uint32_t* const o_ctx = a.out.ctx + prefix;
-  uint64_t* const o_pc = a.out.pc + prefix;
-  uint8_t* const o_st = a.out.stall + prefix;
-  unsigned long long* const o_cnt = a.out.count + prefix;
-  uint32_t* const o_sc = a.out.scope + prefix;
-  const MapDev map = a.map;
-  const int label = a.dense;  // without dense coordinates a separate pass labels every key
-  emit_keys<K>(sm, key, n_u, first, nU, pcb, tz,
-               [=](uint32_t ui, uint32_t lc, uint64_t v, uint8_t st, uint32_t cnt) {
-                 o_ctx[ui] = cb + lc;
-                 o_st[ui] = st;
-                 if constexpr (!WEIGHTED) o_cnt[ui] = cnt;
-                 if (dense) {
-                   o_pc[ui] = from_dense(t, v);
-                   o_sc[ui] = t.scope_of[v];
-                 } else {
-                   o_pc[ui] = v;
-                   if (label) {  // a unit with a pc off the dense grid: binary search
-                     const uint32_t iv = find_interval(map.start, map.end, map.n_iv, v, 0, map.n_iv);
-                     o_sc[ui] = iv == NONE32 ? NONE32 : map.scope[iv];
-                   }
-                 }
-               });
-  if constexpr (WEIGHTED) weighted_counts<K>(sm, key, val, n_u, first, o_cnt);
+  if constexpr (WEIGHTED) weighted_counts<K>(sm, key, val, n_u, first, a.scnt64 + s0);
 }
 
-// GENERAL = false: keys of at most 32 bits only (registers sized for them); a
-// unit that needs wider keys keeps the look-back chain alive with an empty
-// aggregate and raises ERR_RETRY, and the host reruns the pass with
-// GENERAL = true, which handles every unit.
+// Sort pass.  GENERAL = false handles keys of at most 32 bits (registers sized
+// for them) and marks the other units UM_WIDE; GENERAL = true, launched next,
+// handles only those.
 template <bool WEIGHTED, bool SCATTERED, bool GENERAL>
 __global__ void __launch_bounds__(UBLOCK) k_units32(UnitArgs a) {
   __shared__ SortSmem sm;
   __shared__ uint64_t s_sb[MAXC + 1];
-  if (threadIdx.x == 0) sm.unit = atomicAdd(a.ticket, 1u);
-  __syncthreads();
-  const uint32_t u = sm.unit;
-  if (u >= a.n_units) return;
+  const uint32_t u = blockIdx.x;
+  if (a.unit_big[u] >= 0) return;  // a big context: its keys come from the chunk path
+  if (GENERAL && a.meta[u].flags != UM_WIDE) return;
   const uint32_t cb = a.unit_begin[u], ce = a.unit_begin[u + 1];
-  const int32_t big = a.unit_big[u];
-  if (big >= 0) {
-    if (threadIdx.x < WAVE) {
-      unsigned long long U = a.big_U[big];
-      unsigned long long p = lookback(a.status, u, U);
-      if (threadIdx.x == 0) {
-        a.big_out[big] = p;
-        a.out.ctx_off[cb] = p;
-        if (u + 1 == a.n_units) {
-          a.out.ctx_off[a.n_ctx] = p + U;
-          a.info->total_keys = p + U;
-        }
-      }
-    }
-    return;
-  }
   const uint64_t s0 = a.sbase[cb];
   const uint64_t n_u = a.sbase[ce] - s0;
   for (uint32_t l = threadIdx.x; l <= ce - cb; l += UBLOCK) s_sb[l] = a.sbase[cb + l];
@@ -848,26 +763,122 @@ __global__ void __launch_bounds__(UBLOCK) k_units32(UnitArgs a) {
   int kbits, pcb;
   uint32_t tz;
   key_stats(sm, g, n_u, ce - cb, &a.info->err, kbits, pcb, tz);
-  if (kbits > 63 || (!GENERAL && kbits > 32)) {
-    // keep the look-back chain alive; the call reports the error (or reruns) afterwards
-    if (!GENERAL && kbits <= 63 && threadIdx.x == 0) atomicOr(&a.info->err, (uint32_t)ERR_RETRY);
-    if (threadIdx.x < WAVE) {
-      unsigned long long p = lookback(a.status, u, 0);
-      if (threadIdx.x == 0) sm.prefix = p;
-    }
-    __syncthreads();
-    for (uint32_t l = threadIdx.x; l < ce - cb; l += UBLOCK) a.out.ctx_off[cb + l] = sm.prefix;
-    if (threadIdx.x == 0 && u + 1 == a.n_units) { a.out.ctx_off[a.n_ctx] = sm.prefix; a.info->total_keys = sm.prefix; }
+  if (kbits > 63) {  // reported as an error after the call; the unit contributes nothing
+    for (uint32_t l = threadIdx.x; l < ce - cb; l += UBLOCK) a.ucnt[(uint64_t)u * MAXC + l] = 0;
+    if (threadIdx.x == 0) a.meta[u] = UnitMeta{0, 0, 0, 0, UM_DONE, 0};
+    return;
+  }
+  if (!GENERAL && kbits > 32) {
+    if (threadIdx.x == 0) a.meta[u] = UnitMeta{0, 0, 0, 0, UM_WIDE, 0};
     return;
   }
   __syncthreads();
   if constexpr (GENERAL) {
     if (kbits > 32) {
-      unit_body<WEIGHTED, uint64_t>(sm, a, u, cb, ce, n_u, g, kbits, pcb, tz, dense, t);
+      unit_body<WEIGHTED, uint64_t>(sm, a, u, cb, ce, n_u, g, kbits, pcb, tz, dense);
       return;
     }
   }
-  unit_body<WEIGHTED, uint32_t>(sm, a, u, cb, ce, n_u, g, kbits, pcb, tz, dense, t);
+  unit_body<WEIGHTED, uint32_t>(sm, a, u, cb, ce, n_u, g, kbits, pcb, tz, dense);
+}
+
+// Output offsets: exclusive scan of the units' key counts (a big context's
+// count comes from the chunk path), one workgroup.
+__global__ void __launch_bounds__(1024) k_unit_offsets(const UnitMeta* __restrict__ meta,
+                                                       const int32_t* __restrict__ unit_big,
+                                                       const uint64_t* __restrict__ big_U, uint32_t n_units,
+                                                       uint32_t n_ctx, uint64_t* __restrict__ unit_off,
+                                                       uint64_t* __restrict__ ctx_off, PlanInfo* __restrict__ info) {
+  __shared__ unsigned long long s_tmp[1024 / WAVE + 1];
+  unsigned long long carry = 0;
+  for (uint32_t b0 = 0; b0 < n_units; b0 += 1024) {
+    const uint32_t u = b0 + threadIdx.x;
+    unsigned long long v = 0;
+    if (u < n_units) {
+      const int32_t big = unit_big[u];
+      v = big >= 0 ? big_U[big] : meta[u].nU;
+    }
+    unsigned long long tot;
+    const unsigned long long ex = block_excl_scan<1024>(v, s_tmp, &tot);
+    if (u < n_units) unit_off[u] = carry + ex;
+    carry += tot;
+  }
+  if (threadIdx.x == 0) {
+    unit_off[n_units] = carry;
+    ctx_off[n_ctx] = carry;
+    info->total_keys = carry;
+  }
+}
+
+// Context offsets: one wave per unit scans its per-context key counts.
+__global__ void __launch_bounds__(256) k_ctx_offsets(const uint32_t* __restrict__ unit_begin,
+                                                     const int32_t* __restrict__ unit_big,
+                                                     const uint32_t* __restrict__ ucnt,
+                                                     const uint64_t* __restrict__ unit_off, uint32_t n_units,
+                                                     uint64_t* __restrict__ ctx_off, uint64_t* __restrict__ big_out) {
+  const uint32_t u = blockIdx.x * (256 / WAVE) + wave_id();
+  if (u >= n_units) return;
+  const uint32_t cb = unit_begin[u], ce = unit_begin[u + 1];
+  const uint64_t off = unit_off[u];
+  const int32_t big = unit_big[u];
+  if (big >= 0) {  // one context
+    if (lane_id() == 0) {
+      ctx_off[cb] = off;
+      big_out[big] = off;
+    }
+    return;
+  }
+  const uint32_t l = lane_id();
+  const uint32_t v = l < ce - cb ? ucnt[(uint64_t)u * MAXC + l] : 0u;
+  const uint32_t inc = wave_incl_scan(v);
+  if (l < ce - cb) ctx_off[cb + l] = off + inc - v;
+}
+
+// Write pass: unpack every unit's staged keys into the outputs.
+constexpr int WBLOCK = 256;
+__global__ void __launch_bounds__(WBLOCK) k_units_write(UnitArgs a, const uint64_t* __restrict__ unit_off,
+                                                       MapDev map, OutDev out, int weighted) {
+  __shared__ uint64_t s_lo[DENSE_MAX_WIN], s_hi[DENSE_MAX_WIN], s_d[DENSE_MAX_WIN + 1];
+  const uint32_t u = blockIdx.x;
+  if (a.unit_big[u] >= 0) return;
+  const UnitMeta m = a.meta[u];
+  if (m.nU == 0) return;
+  const bool dense = (m.flags & UM_DENSE) != 0, wide = (m.flags & UM_WIDE) != 0;
+  DenseDev t = a.dd;
+  if (a.dense) {
+    for (uint32_t i = threadIdx.x; i < t.n_win; i += WBLOCK) {
+      s_lo[i] = t.lo[i];
+      s_hi[i] = t.hi[i];
+    }
+    for (uint32_t i = threadIdx.x; i <= t.n_win; i += WBLOCK) s_d[i] = t.d[i];
+    t.lo = s_lo;
+    t.hi = s_hi;
+    t.d = s_d;
+  }
+  __syncthreads();
+  const uint32_t cb = a.unit_begin[u];
+  const uint64_t s0 = a.sbase[cb], o0 = unit_off[u];
+  const uint64_t pmask = m.pcb >= 64 ? ~0ull : ((1ull << m.pcb) - 1);
+  for (uint32_t ui = threadIdx.x; ui < m.nU; ui += WBLOCK) {
+    uint64_t k = a.skey[s0 + ui];
+    if (wide) k |= (uint64_t)a.shi[s0 + ui] << 32;
+    const uint32_t lc = (uint32_t)(k >> (m.pcb + 4));
+    const uint64_t v = m.lo + (((k >> 4) & pmask) << m.tz);
+    const uint64_t o = o0 + ui;
+    out.ctx[o] = cb + lc;
+    out.stall[o] = (uint8_t)(k & 15);
+    out.count[o] = weighted ? a.scnt64[s0 + ui] : (unsigned long long)a.scnt[s0 + ui];
+    if (dense) {
+      out.pc[o] = from_dense(t, v);
+      out.scope[o] = t.scope_of[v];
+    } else {
+      out.pc[o] = v;
+      if (a.dense) {  // a unit with a pc off the dense grid: binary search
+        const uint32_t iv = find_interval(map.start, map.end, map.n_iv, v, 0, map.n_iv);
+        out.scope[o] = iv == NONE32 ? NONE32 : map.scope[iv];
+      }
+    }
+  }
 }
 
 // ----------------------------------------------------------------------------
@@ -905,6 +916,39 @@ __device__ inline uint32_t chunk_owner(const uint64_t* big_chunk, uint32_t n_big
     else hi = mid;
   }
   return lo;
+}
+
+// Hand the sorted unique keys to `emit(ui, local ctx, coordinate, stall,
+// count)` in unique-key order.  32-bit keys come from their compacted copy in
+// LDS, so consecutive lanes take consecutive keys (coalesced output); wider
+// keys are emitted by the thread that holds them.  The coordinate is the
+// dense coordinate or the pc, whichever the keys were built from.
+template <class K, class Emit>
+__device__ inline void emit_keys(const SortSmem& sm, const K (&key)[UITEMS], uint64_t n_u, uint32_t first,
+                                 uint32_t nU, int pcb, uint32_t tz, Emit&& emit) {
+  const uint64_t pmask = pcb >= 64 ? ~0ull : ((1ull << pcb) - 1);
+  if constexpr (sizeof(K) == 4) {
+    for (uint32_t ui = threadIdx.x; ui < nU; ui += UBLOCK) {
+      const uint64_t kk = sm.buf[ui];
+      const uint32_t cnt = (uint32_t)sm.upos[ui + 1] - (uint32_t)sm.upos[ui];
+      const uint32_t lc = (uint32_t)(kk >> (pcb + 4));
+      emit(ui, lc, sm.pcmin[lc] + (((kk >> 4) & pmask) << tz), (uint8_t)(kk & 15), cnt);
+    }
+  } else {
+    K prev = prev_last<K>(sm, threadIdx.x);
+    uint32_t ui = first;
+#pragma unroll
+    for (int i = 0; i < UITEMS; ++i) {
+      uint32_t p = threadIdx.x * UITEMS + i;
+      bool h = p < n_u && (p == 0 || key[i] != prev);
+      prev = key[i];
+      if (!h) continue;
+      const uint64_t kk = (uint64_t)key[i];
+      const uint32_t lc = (uint32_t)(kk >> (pcb + 4));
+      emit(ui, lc, sm.pcmin[lc] + (((kk >> 4) & pmask) << tz), (uint8_t)(kk & 15), (uint32_t)sm.upos[ui + 1] - p);
+      ++ui;
+    }
+  }
 }
 
 // Sort one chunk of a big context and write its unique keys (real pcs) as a
@@ -1253,63 +1297,63 @@ extern "C" hpa_status hpa_attribute(hpa_ctx* ctx, const hpa_structure_map* map, 
       HPA_HIP(hipGetLastError());
       tm.end(info.big_samples, 0);
     }
-    // --- ordered unit pass ---
-    DBuf d_status(ctx, (uint64_t)info.n_units * 8, s);
-    DBuf d_ticket(ctx, 8, s);
-    HPA_HIP(hipMemsetAsync(d_status.p, 0, (uint64_t)info.n_units * 8, s));
-    HPA_HIP(hipMemsetAsync(d_ticket.p, 0, 8, s));
+    // --- unit passes: sort (narrow, then the wide units), offsets, write ---
+    const uint32_t NU = info.n_units;
+    DBuf d_meta(ctx, std::max<uint64_t>(NU, 1) * sizeof(UnitMeta), s);
+    DBuf d_ucnt(ctx, std::max<uint64_t>(NU, 1) * MAXC * 4, s);
+    DBuf d_uoff(ctx, ((uint64_t)NU + 1) * 8, s);
+    DBuf d_skey(ctx, n * 4, s), d_shi(ctx, n * 4, s), d_scnt;
+    if (weighted) d_scnt = DBuf(ctx, n * 8, s);
+    else d_scnt = DBuf(ctx, n * 4, s);
     MapDev md{map->start.as<uint64_t>(), map->end.as<uint64_t>(), map->scope.as<uint32_t>(), map->n_iv};
     OutDev od{A->ctx_id.as<uint32_t>(), A->pc.as<uint64_t>(), A->stall.as<uint8_t>(),
               A->count.as<unsigned long long>(), A->scope.as<uint32_t>(), A->ctx_offsets.as<uint64_t>()};
     UnitArgs ua{src_pc, src_st, src_w, d_sbase.as<uint64_t>(), d_rbase.as<uint64_t>(), d_grp.as<Run>(),
-                d_ubeg.as<uint32_t>(), d_ubig.as<int32_t>(), d_bigU.as<uint64_t>(), d_bigout.as<uint64_t>(),
-                d_status.as<unsigned long long>(), d_ticket.as<unsigned int>(), d_info.as<PlanInfo>(),
-                info.n_units, C, md, od};
-    ua.dd = dd;
-    ua.dense = map->dense ? 1 : 0;
-    // unit pass (+ big-context write and labels); `general` handles every key width
-    auto unit_pass = [&](bool general) {
-      const unsigned g = info.n_units;
-      tm.begin("units");
-#define HPA_UNITS(W, S)                                                              \
-  do {                                                                               \
-    if (general) k_units32<W, S, true><<<g, UBLOCK, 0, s>>>(ua);                     \
-    else k_units32<W, S, false><<<g, UBLOCK, 0, s>>>(ua);                            \
+                d_ubeg.as<uint32_t>(), d_ubig.as<int32_t>(), d_info.as<PlanInfo>(), NU, C, dd,
+                map->dense ? 1 : 0, d_meta.as<UnitMeta>(), d_ucnt.as<uint32_t>(), d_skey.as<uint32_t>(),
+                d_shi.as<uint32_t>(), weighted ? nullptr : d_scnt.as<uint32_t>(),
+                weighted ? d_scnt.as<unsigned long long>() : nullptr};
+    tm.begin("units");
+#define HPA_UNITS(W, S)                                  \
+  do {                                                   \
+    k_units32<W, S, false><<<NU, UBLOCK, 0, s>>>(ua);    \
+    k_units32<W, S, true><<<NU, UBLOCK, 0, s>>>(ua);     \
   } while (0)
-      if (weighted) {
-        if (scattered) HPA_UNITS(true, true);
-        else HPA_UNITS(true, false);
-      } else {
-        if (scattered) HPA_UNITS(false, true);
-        else HPA_UNITS(false, false);
-      }
+    if (weighted) {
+      if (scattered) HPA_UNITS(true, true);
+      else HPA_UNITS(true, false);
+    } else {
+      if (scattered) HPA_UNITS(false, true);
+      else HPA_UNITS(false, false);
+    }
 #undef HPA_UNITS
+    HPA_HIP(hipGetLastError());
+    tm.end();
+    tm.begin("unit_write");
+    k_unit_offsets<<<1, 1024, 0, s>>>(d_meta.as<UnitMeta>(), d_ubig.as<int32_t>(), d_bigU.as<uint64_t>(), NU, C,
+                                      d_uoff.as<uint64_t>(), A->ctx_offsets.as<uint64_t>(), d_info.as<PlanInfo>());
+    k_ctx_offsets<<<(NU + 3) / 4, 256, 0, s>>>(d_ubeg.as<uint32_t>(), d_ubig.as<int32_t>(), d_ucnt.as<uint32_t>(),
+                                              d_uoff.as<uint64_t>(), NU, A->ctx_offsets.as<uint64_t>(),
+                                              d_bigout.as<uint64_t>());
+    k_units_write<<<NU, WBLOCK, 0, s>>>(ua, d_uoff.as<uint64_t>(), md, od, weighted ? 1 : 0);
+    HPA_HIP(hipGetLastError());
+    tm.end();
+    if (info.n_big) {
+      tm.begin("big_write");
+      k_big_write<<<(unsigned)info.n_chunks, 256, 0, s>>>(ba, L[fin], d_slot.as<unsigned long long>(),
+                                                        d_bigout.as<uint64_t>(), md, od);
       HPA_HIP(hipGetLastError());
       tm.end();
-      if (info.n_big) {
-        tm.begin("big_write");
-        k_big_write<<<(unsigned)info.n_chunks, 256, 0, s>>>(ba, L[fin], d_slot.as<unsigned long long>(),
-                                                          d_bigout.as<uint64_t>(), md, od);
-        HPA_HIP(hipGetLastError());
-        tm.end();
-      }
-      if (!map->dense) {
-        // no dense coordinates: label every key with a binary search
-        tm.begin("scope_labels");
-        launch_scope_labels(map, A->pc.as<uint64_t>(), n, &d_info.as<PlanInfo>()->total_keys,
-                            A->scope.as<uint32_t>(), s);
-        tm.end();
-      }
-      HPA_HIP(hipMemcpyAsync(&info, d_info.p, sizeof(info), hipMemcpyDeviceToHost, s));
-      HPA_HIP(hipStreamSynchronize(s));
-    };
-    unit_pass(false);
-    if (info.err & ERR_RETRY) {
-      // some unit needs keys wider than 32 bits: redo the pass with the general kernel
-      HPA_HIP(hipMemsetAsync(d_status.p, 0, (uint64_t)info.n_units * 8, s));
-      HPA_HIP(hipMemsetAsync(d_ticket.p, 0, 8, s));
-      unit_pass(true);
     }
+    if (!map->dense) {
+      // no dense coordinates: label every key with a binary search
+      tm.begin("scope_labels");
+      launch_scope_labels(map, A->pc.as<uint64_t>(), n, &d_info.as<PlanInfo>()->total_keys, A->scope.as<uint32_t>(),
+                          s);
+      tm.end();
+    }
+    HPA_HIP(hipMemcpyAsync(&info, d_info.p, sizeof(info), hipMemcpyDeviceToHost, s));
+    HPA_HIP(hipStreamSynchronize(s));
     if (info.err & ERR_STALL) fail(HPA_E_INVAL, "a sample has stall >= 16");
     if (info.err & ERR_WIDE) fail(HPA_E_UNSUPPORTED, "the PCs of one context span more than 2^56 bytes");
     A->n_keys = info.total_keys;
@@ -1322,6 +1366,7 @@ extern "C" hpa_status hpa_attribute(hpa_ctx* ctx, const hpa_structure_map* map, 
       uint64_t big_keys = 0;
       for (uint64_t v : bu) big_keys += v;
       tm.items("units", n - info.big_samples, info.total_keys - big_keys);
+      tm.items("unit_write", info.total_keys - big_keys, info.total_keys - big_keys);
       tm.items("big_write", 0, big_keys);
       if (!map->dense) tm.items("scope_labels", info.total_keys, info.total_keys);
       tm.collect();
