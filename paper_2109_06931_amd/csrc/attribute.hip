@@ -340,6 +340,7 @@ struct SortSmem {
   uint32_t ucnt[MAXC + 1];
   unsigned long long red_or, red_max, red_min, red_ref;
   unsigned long long scan_tmp[UBLOCK / WAVE + 1];
+  uint32_t scan_tmp32[UBLOCK / WAVE + 1];
   uint32_t last_hi[UBLOCK], last_lo[UBLOCK];
   unsigned long long prefix;
   uint32_t unit, nU;
@@ -477,10 +478,14 @@ template <bool WEIGHTED, class K>
 __device__ inline void sort_reduce(SortSmem& sm, Gathered<WEIGHTED>& g, uint64_t n_u, uint32_t n_cu, K (&key)[UITEMS],
                                    uint32_t (&val)[UITEMS], int kbits, int pcb, uint32_t tz) {
   uint32_t lo[UITEMS], hi[UITEMS];
+  // 32-bit keys (kbits <= 31): an empty slot holds 1 << kbits, above every
+  // real key, so sorting kbits + 1 bits leaves the real keys first and the
+  // sort needs no per-slot test
+  const uint64_t empty = sizeof(K) == 4 ? (1ull << kbits) : 0ull;
 #pragma unroll
   for (int i = 0; i < UITEMS; ++i) {
     const uint64_t j = (uint64_t)i * UBLOCK + threadIdx.x;
-    uint64_t k = 0;
+    uint64_t k = empty;
     if (j < n_u) {
       const uint64_t rel = (g.pc[i] - sm.pcmin[g.lc(i)]) >> tz;
       k = ((uint64_t)g.lc(i) << (pcb + 4)) | (rel << 4) | g.st(i);
@@ -490,8 +495,9 @@ __device__ inline void sort_reduce(SortSmem& sm, Gathered<WEIGHTED>& g, uint64_t
     val[i] = g.wt(i);
   }
   if constexpr (sizeof(K) == 4) {
-    if constexpr (WEIGHTED) Sorter::template sort<1>(lo, val, hi, kbits, (int)n_u, true, sm.buf, sm.cnt, sm.doff);
-    else Sorter::template sort<0>(lo, val, hi, kbits, (int)n_u, true, sm.buf, sm.cnt, sm.doff);
+    if constexpr (WEIGHTED)
+      Sorter::template sort<1, true>(lo, val, hi, kbits + 1, (int)n_u, true, sm.buf, sm.cnt, sm.doff);
+    else Sorter::template sort<0, true>(lo, val, hi, kbits + 1, (int)n_u, true, sm.buf, sm.cnt, sm.doff);
 #pragma unroll
     for (int i = 0; i < UITEMS; ++i) key[i] = (K)lo[i];
   } else {
@@ -592,10 +598,10 @@ __device__ inline uint32_t find_heads(SortSmem& sm, const K (&key)[UITEMS], uint
     heads += h;
     prev = key[i];
   }
-  unsigned long long tot;
-  unsigned long long ex = block_excl_scan<UBLOCK>((unsigned long long)heads, sm.scan_tmp, &tot);
-  first_uidx = (uint32_t)ex;
-  nU = (uint32_t)tot;
+  uint32_t tot;
+  const uint32_t ex = block_excl_scan<UBLOCK>(heads, sm.scan_tmp32, &tot);
+  first_uidx = ex;
+  nU = tot;
   prev = prev_last<K>(sm, tid);
   uint32_t u = first_uidx;
 #pragma unroll
@@ -768,13 +774,13 @@ __global__ void __launch_bounds__(UBLOCK) k_units32(UnitArgs a) {
     if (threadIdx.x == 0) a.meta[u] = UnitMeta{0, 0, 0, 0, UM_DONE, 0};
     return;
   }
-  if (!GENERAL && kbits > 32) {
+  if (!GENERAL && kbits > 31) {
     if (threadIdx.x == 0) a.meta[u] = UnitMeta{0, 0, 0, 0, UM_WIDE, 0};
     return;
   }
   __syncthreads();
   if constexpr (GENERAL) {
-    if (kbits > 32) {
+    if (kbits > 31) {
       unit_body<WEIGHTED, uint64_t>(sm, a, u, cb, ce, n_u, g, kbits, pcb, tz, dense);
       return;
     }
@@ -1010,7 +1016,7 @@ __global__ void __launch_bounds__(UBLOCK) k_big_chunks(BigArgs a, ListBuf o) {
     if (threadIdx.x == 0) o.len[ch] = 0;
     return;
   }
-  if (!GENERAL && kbits > 32) {
+  if (!GENERAL && kbits > 31) {
     if (threadIdx.x == 0) o.len[ch] = WIDE_CHUNK;
     return;
   }

@@ -13,6 +13,22 @@ constexpr int WAVE = 64;
 __device__ inline int lane_id() { return (int)(threadIdx.x & (WAVE - 1)); }
 __device__ inline int wave_id() { return (int)(threadIdx.x / WAVE); }
 
+// Inclusive scan over the 64 lanes of a wave for 32-bit values with DPP moves
+// (no LDS traffic): row shifts by 1, 2, 4 and 8 scan each row of 16 lanes, then
+// row broadcasts of lane 15 (into rows 1 and 3) and lane 31 (into rows 2 and 3)
+// carry the row totals.  Every lane must be active.
+__device__ inline uint32_t wave_incl_scan_u32(uint32_t v) {
+  v += (uint32_t)__builtin_amdgcn_update_dpp(0, (int)v, 0x111, 0xF, 0xF, true);  // row_shr:1
+  v += (uint32_t)__builtin_amdgcn_update_dpp(0, (int)v, 0x112, 0xF, 0xF, true);  // row_shr:2
+  v += (uint32_t)__builtin_amdgcn_update_dpp(0, (int)v, 0x114, 0xF, 0xF, true);  // row_shr:4
+  v += (uint32_t)__builtin_amdgcn_update_dpp(0, (int)v, 0x118, 0xF, 0xF, true);  // row_shr:8
+  v += (uint32_t)__builtin_amdgcn_update_dpp(0, (int)v, 0x142, 0xA, 0xF, false); // row_bcast:15
+  v += (uint32_t)__builtin_amdgcn_update_dpp(0, (int)v, 0x143, 0xC, 0xF, false); // row_bcast:31
+  return v;
+}
+
+__device__ inline uint32_t wave_last_u32(uint32_t v) { return (uint32_t)__builtin_amdgcn_readlane((int)v, WAVE - 1); }
+
 template <class T>
 __device__ inline T wave_incl_scan(T v) {
   const int lane = lane_id();
@@ -64,7 +80,9 @@ __device__ inline T wave_or(T v) {
 template <int BLOCK, class T>
 __device__ inline T block_excl_scan(T v, T* s_tmp, T* total) {
   constexpr int NW = BLOCK / WAVE;
-  T inc = wave_incl_scan(v);
+  T inc;
+  if constexpr (sizeof(T) == 4) inc = (T)wave_incl_scan_u32((uint32_t)v);
+  else inc = wave_incl_scan(v);
   if (lane_id() == WAVE - 1) s_tmp[wave_id()] = inc;
   __syncthreads();
   if (threadIdx.x == 0) {
@@ -128,17 +146,22 @@ struct BlockRadix {
   // p % ITEMS of thread p / ITEMS; positions >= n hold no key.  `striped`
   // gives the validity test of the starting arrangement.  s_buf: BUF_WORDS,
   // s_cnt: CNT_WORDS, s_doff: DOFF_WORDS (separate regions).
-  template <int NV>
+  //
+  // FULL: every item of every thread holds a key (the caller pads empty slots
+  // with keys that sort last), so no slot needs a validity test.
+  template <int NV, bool FULL = false>
   __device__ static __forceinline__ void sort(uint32_t (&key)[ITEMS], uint32_t (&v0)[ITEMS], uint32_t (&v1)[ITEMS],
                                               int bits, int n, bool striped, uint32_t* s_buf, uint32_t* s_cnt,
                                               uint32_t* s_doff) {
     const int tid = (int)threadIdx.x;
+    if (FULL) n = T;
+#define HPA_VALID(i) (FULL || (striped ? (i) * BLOCK + tid : tid * ITEMS + (i)) < n)
     for (int shift = 0; shift < bits; shift += 4) {
       // 1. per-thread digit counts
       uint64_t h0 = 0, h1 = 0;
 #pragma unroll
       for (int i = 0; i < ITEMS; ++i)
-        if ((striped ? i * BLOCK + tid : tid * ITEMS + i) < n) inc8(h0, h1, (key[i] >> shift) & 15u);
+        if (HPA_VALID(i)) inc8(h0, h1, (key[i] >> shift) & 15u);
       // 2. widen to 16-bit pairs: column k holds digits 2k (low) and 2k+1 (high)
 #pragma unroll
       for (int k = 0; k < 8; ++k) {
@@ -152,9 +175,9 @@ struct BlockRadix {
 #pragma unroll
         for (int c0 = 0; c0 < BLOCK; c0 += WAVE) {
           const uint32_t a = s_cnt[k * BLOCK + c0 + lane_id()];
-          const uint32_t inc = wave_incl_scan(a);
+          const uint32_t inc = wave_incl_scan_u32(a);
           s_cnt[k * BLOCK + c0 + lane_id()] = run + inc - a;
-          run += __shfl(inc, WAVE - 1, WAVE);
+          run += wave_last_u32(inc);
         }
         if (lane_id() == 0) {
           s_doff[2 * k] = run & 0xFFFFu;
@@ -164,7 +187,7 @@ struct BlockRadix {
       __syncthreads();
       if (tid < WAVE) {
         const uint32_t a = lane_id() < 16 ? s_doff[lane_id()] : 0u;
-        const uint32_t inc = wave_incl_scan(a);
+        const uint32_t inc = wave_incl_scan_u32(a);
         if (lane_id() < 16) s_doff[lane_id()] = inc - a;
       }
       __syncthreads();
@@ -174,7 +197,7 @@ struct BlockRadix {
         // one plane: write each key as soon as its position is known
 #pragma unroll
         for (int i = 0; i < ITEMS; ++i) {
-          if ((striped ? i * BLOCK + tid : tid * ITEMS + i) < n) {
+          if (HPA_VALID(i)) {
             const uint32_t d = (key[i] >> shift) & 15u;
             const uint32_t pre = (s_cnt[(d >> 1) * BLOCK + tid] >> ((d & 1) * 16)) & 0xFFFFu;
             s_buf[pad((int)(s_doff[d] + pre + get8(r0, r1, d)))] = key[i];
@@ -183,14 +206,14 @@ struct BlockRadix {
         }
         __syncthreads();
 #pragma unroll
-        for (int i = 0; i < ITEMS; ++i) key[i] = tid * ITEMS + i < n ? s_buf[pad(tid * ITEMS + i)] : 0u;
+        for (int i = 0; i < ITEMS; ++i) key[i] = (FULL || tid * ITEMS + i < n) ? s_buf[pad(tid * ITEMS + i)] : 0u;
         __syncthreads();
       } else {
         uint32_t pos[ITEMS];
 #pragma unroll
         for (int i = 0; i < ITEMS; ++i) {
           pos[i] = 0;
-          if ((striped ? i * BLOCK + tid : tid * ITEMS + i) < n) {
+          if (HPA_VALID(i)) {
             const uint32_t d = (key[i] >> shift) & 15u;
             const uint32_t pre = (s_cnt[(d >> 1) * BLOCK + tid] >> ((d & 1) * 16)) & 0xFFFFu;
             pos[i] = s_doff[d] + pre + get8(r0, r1, d);
@@ -203,6 +226,7 @@ struct BlockRadix {
       }
       striped = false;
     }
+#undef HPA_VALID
   }
 
   // Move valid v[i] to position pos[i] and read the plane back blocked.
