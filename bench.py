@@ -29,7 +29,9 @@ if ROOT not in sys.path:
 
 HBM_PEAK_GBPS = 8000.0  # MI355X HBM3E, published
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "k_units32_medium_traffic.json")
-UNITS_SRC = os.path.join(ROOT, "paper_2109_06931_amd", "csrc", "attribute.hip")
+# the unit kernel's sources, in the order their hash is taken
+UNITS_SRCS = [os.path.join(ROOT, "paper_2109_06931_amd", "csrc", f)
+              for f in ("attribute.hip", "block_prims.h", "hpa_internal.h")]
 
 
 def _parse():
@@ -61,8 +63,11 @@ def _units_traffic():
     try:
         with open(TRAFFIC_FILE) as f:
             t = json.load(f)
-        with open(UNITS_SRC, "rb") as f:
-            sha = hashlib.sha256(f.read()).hexdigest()
+        h = hashlib.sha256()
+        for src in UNITS_SRCS:
+            with open(src, "rb") as f:
+                h.update(f.read())
+        sha = h.hexdigest()
     except (OSError, ValueError):
         return None
     if t.get("source_sha256") != sha:

@@ -42,6 +42,7 @@ constexpr int UITEMS = 16;
 constexpr int UT = UBLOCK * UITEMS;  // unit capacity (samples)
 constexpr int UHALF = UT / 2;        // contexts up to this size are packed together
 constexpr int MAXC = 64;             // contexts per unit
+constexpr int RUN_CAP = 1024;        // runs a sort workgroup copies to LDS for its gather
 using Sorter = BlockRadix<UBLOCK, UITEMS>;
 
 constexpr uint64_t M40 = (1ull << 40) - 1;
@@ -334,6 +335,7 @@ struct SortSmem {
   union {
     uint32_t cnt[Sorter::CNT_WORDS];  // radix counter columns during the sort
     uint16_t upos[UT + 2];            // then: sorted position of every unique key, closed by n_u
+    Run runs[RUN_CAP];                // before the sort: the runs the workgroup gathers through
   };
   uint32_t doff[Sorter::DOFF_WORDS];
   unsigned long long pcmin[MAXC];
@@ -363,17 +365,47 @@ struct Gathered {
   }
 };
 
+// Find the run of each of a thread's items and load the items.  A thread's
+// items ascend, so the run of its first item comes from a binary search over
+// the runs and the later ones from walking forward with the current run in
+// registers.  `runs` is either the LDS copy of the runs or the global list.
+template <bool WEIGHTED, class Load>
+__device__ __forceinline__ void gather_runs(const Run* runs, uint64_t r_lo, uint64_t r_hi, uint64_t s0, uint64_t n_u,
+                                            uint32_t cb, Load&& load) {
+  uint64_t r = r_lo;
+  if (n_u > threadIdx.x) {
+    const uint64_t f0 = s0 + threadIdx.x;
+    uint64_t hi = r_hi;
+    while (hi - r > 1) {
+      uint64_t mid = (r + hi) >> 1;
+      if (runs[mid].flat <= f0) r = mid;
+      else hi = mid;
+    }
+  }
+  Run cur = n_u > threadIdx.x ? runs[r] : Run{0, 0, 0, cb};
+#pragma unroll
+  for (int i = 0; i < UITEMS; ++i) {
+    if ((uint64_t)i * UBLOCK >= n_u) continue;
+    const uint64_t j = (uint64_t)i * UBLOCK + threadIdx.x;
+    const uint64_t flat = s0 + j;
+    if (j < n_u) {
+      while (flat >= cur.flat + cur.len) cur = runs[++r];
+      load(i, cur.start + (flat - cur.flat), cur.ctx - cb);
+    }
+  }
+}
+
 // Load the unit's samples: item i of thread t is sample j = i * UBLOCK + t
-// (flat position s0 + j in context-grouped order).  A thread's items ascend,
-// so run mode finds the run of its first item by binary search over the
-// unit's grouped runs and then walks forward with the current run cached in
-// registers; scattered mode reads flat positions, finding each item's context
-// in the LDS copy of the unit's context offsets.
+// (flat position s0 + j in context-grouped order).  Run mode reads through
+// the runs [r_lo, r_hi) that cover the unit, copied to LDS first when at most
+// RUN_CAP of them (s_runs; the workgroup's barrier is taken inside, so every
+// thread calls this); scattered mode reads flat positions, finding each item's
+// context in the LDS copy of the unit's context offsets.
 template <bool SCATTERED, bool WEIGHTED>
 __device__ inline void gather(Gathered<WEIGHTED>& g, uint64_t s0, uint64_t n_u, uint32_t cb, const Run* __restrict__ grp,
                               uint64_t r_lo, uint64_t r_hi, const uint64_t* __restrict__ sb_lds,
                               uint32_t n_cu, const uint64_t* __restrict__ pc, const uint8_t* __restrict__ stall,
-                              const uint32_t* __restrict__ weight, uint32_t* err) {
+                              const uint32_t* __restrict__ weight, uint32_t* err, Run* s_runs) {
   auto load = [&](int i, uint64_t src, uint32_t lc) {
     g.pc[i] = pc[src];
     uint8_t st = stall[src];
@@ -405,26 +437,14 @@ __device__ inline void gather(Gathered<WEIGHTED>& g, uint64_t s0, uint64_t n_u, 
       }
     }
   } else {
-    uint64_t r = r_lo;
-    if (n_u > threadIdx.x) {
-      const uint64_t f0 = s0 + threadIdx.x;
-      uint64_t hi = r_hi;
-      while (hi - r > 1) {
-        uint64_t mid = (r + hi) >> 1;
-        if (grp[mid].flat <= f0) r = mid;
-        else hi = mid;
-      }
-    }
-    Run cur = n_u > threadIdx.x ? grp[r] : Run{0, 0, 0, cb};
-#pragma unroll
-    for (int i = 0; i < UITEMS; ++i) {
-      if ((uint64_t)i * UBLOCK >= n_u) continue;
-      const uint64_t j = (uint64_t)i * UBLOCK + threadIdx.x;
-      const uint64_t flat = s0 + j;
-      if (j < n_u) {
-        while (flat >= cur.flat + cur.len) cur = grp[++r];
-        load(i, cur.start + (flat - cur.flat), cur.ctx - cb);
-      }
+    const uint64_t nr = r_hi - r_lo;
+    if (nr <= (uint64_t)RUN_CAP) {
+      // the walk reads every run several times from dependent addresses: LDS
+      for (uint32_t k = threadIdx.x; k < nr; k += UBLOCK) s_runs[k] = grp[r_lo + k];
+      __syncthreads();
+      gather_runs<WEIGHTED>(s_runs, 0, nr, s0, n_u, cb, load);
+    } else {
+      gather_runs<WEIGHTED>(grp, r_lo, r_hi, s0, n_u, cb, load);
     }
   }
 }
@@ -755,7 +775,7 @@ __global__ void __launch_bounds__(UBLOCK) k_units32(UnitArgs a) {
   __syncthreads();
   Gathered<WEIGHTED> g;
   gather<SCATTERED, WEIGHTED>(g, s0, n_u, cb, a.grouped, SCATTERED ? 0 : a.rbase[cb], SCATTERED ? 0 : a.rbase[ce],
-                              s_sb, ce - cb, a.pc, a.stall, a.weight, &a.info->err);
+                              s_sb, ce - cb, a.pc, a.stall, a.weight, &a.info->err, sm.runs);
   bool dense = false;
   if (a.dense) {
     densify(sm, g, n_u, t);
@@ -763,7 +783,7 @@ __global__ void __launch_bounds__(UBLOCK) k_units32(UnitArgs a) {
     dense = sm.far == 0;
     if (!dense)
       gather<SCATTERED, WEIGHTED>(g, s0, n_u, cb, a.grouped, SCATTERED ? 0 : a.rbase[cb],
-                                  SCATTERED ? 0 : a.rbase[ce], s_sb, ce - cb, a.pc, a.stall, a.weight, &a.info->err);
+                                  SCATTERED ? 0 : a.rbase[ce], s_sb, ce - cb, a.pc, a.stall, a.weight, &a.info->err, sm.runs);
   }
   // key width decides the register type of the sort
   int kbits, pcb;
@@ -841,7 +861,8 @@ __global__ void __launch_bounds__(256) k_ctx_offsets(const uint32_t* __restrict_
 }
 
 // Write pass: unpack every unit's staged keys into the outputs.
-constexpr int WBLOCK = 256;
+constexpr int WBLOCK = 512;
+constexpr int WBATCH = 4;
 __global__ void __launch_bounds__(WBLOCK) k_units_write(UnitArgs a, const uint64_t* __restrict__ unit_off,
                                                        MapDev map, OutDev out, int weighted) {
   __shared__ uint64_t s_lo[DENSE_MAX_WIN], s_hi[DENSE_MAX_WIN], s_d[DENSE_MAX_WIN + 1];
@@ -865,23 +886,46 @@ __global__ void __launch_bounds__(WBLOCK) k_units_write(UnitArgs a, const uint64
   const uint32_t cb = a.unit_begin[u];
   const uint64_t s0 = a.sbase[cb], o0 = unit_off[u];
   const uint64_t pmask = m.pcb >= 64 ? ~0ull : ((1ull << m.pcb) - 1);
-  for (uint32_t ui = threadIdx.x; ui < m.nU; ui += WBLOCK) {
-    uint64_t k = a.skey[s0 + ui];
-    if (wide) k |= (uint64_t)a.shi[s0 + ui] << 32;
-    const uint32_t lc = (uint32_t)(k >> (m.pcb + 4));
-    const uint64_t v = m.lo + (((k >> 4) & pmask) << m.tz);
-    const uint64_t o = o0 + ui;
-    out.ctx[o] = cb + lc;
-    out.stall[o] = (uint8_t)(k & 15);
-    out.count[o] = weighted ? a.scnt64[s0 + ui] : (unsigned long long)a.scnt[s0 + ui];
-    if (dense) {
-      out.pc[o] = from_dense(t, v);
-      out.scope[o] = t.scope_of[v];
-    } else {
-      out.pc[o] = v;
-      if (a.dense) {  // a unit with a pc off the dense grid: binary search
-        const uint32_t iv = find_interval(map.start, map.end, map.n_iv, v, 0, map.n_iv);
-        out.scope[o] = iv == NONE32 ? NONE32 : map.scope[iv];
+  const uint32_t* __restrict__ skey = a.skey + s0;
+  // the staging arrays a call does not use are null
+  const uint32_t* __restrict__ shi = a.shi ? a.shi + s0 : nullptr;
+  const uint32_t* __restrict__ scnt = a.scnt ? a.scnt + s0 : nullptr;
+  const unsigned long long* __restrict__ scnt64 = a.scnt64 ? a.scnt64 + s0 : nullptr;
+  // WBATCH keys per thread per step: all loads are issued before the
+  // dependent table lookups and the stores
+  for (uint32_t b0 = 0; b0 < m.nU; b0 += WBLOCK * WBATCH) {
+    uint64_t k[WBATCH];
+    unsigned long long c[WBATCH];
+#pragma unroll
+    for (int q = 0; q < WBATCH; ++q) {
+      const uint32_t ui = b0 + q * WBLOCK + threadIdx.x;
+      k[q] = 0;
+      c[q] = 0;
+      if (ui < m.nU) {
+        k[q] = skey[ui];
+        if (wide) k[q] |= (uint64_t)shi[ui] << 32;
+        c[q] = weighted ? scnt64[ui] : (unsigned long long)scnt[ui];
+      }
+    }
+#pragma unroll
+    for (int q = 0; q < WBATCH; ++q) {
+      const uint32_t ui = b0 + q * WBLOCK + threadIdx.x;
+      if (ui >= m.nU) continue;
+      const uint32_t lc = (uint32_t)(k[q] >> (m.pcb + 4));
+      const uint64_t v = m.lo + (((k[q] >> 4) & pmask) << m.tz);
+      const uint64_t o = o0 + ui;
+      out.ctx[o] = cb + lc;
+      out.stall[o] = (uint8_t)(k[q] & 15);
+      out.count[o] = c[q];
+      if (dense) {
+        out.pc[o] = from_dense(t, v);
+        out.scope[o] = t.scope_of[v];
+      } else {
+        out.pc[o] = v;
+        if (a.dense) {  // a unit with a pc off the dense grid: binary search
+          const uint32_t iv = find_interval(map.start, map.end, map.n_iv, v, 0, map.n_iv);
+          out.scope[o] = iv == NONE32 ? NONE32 : map.scope[iv];
+        }
       }
     }
   }
@@ -998,7 +1042,7 @@ __global__ void __launch_bounds__(UBLOCK) k_big_chunks(BigArgs a, ListBuf o) {
   __syncthreads();
   Gathered<WEIGHTED> g;
   gather<SCATTERED, WEIGHTED>(g, s0, n_u, c, a.grouped, SCATTERED ? 0 : a.rbase[c], SCATTERED ? 0 : a.rbase[c + 1],
-                              s_sb, 1, a.pc, a.stall, a.weight, &a.info->err);
+                              s_sb, 1, a.pc, a.stall, a.weight, &a.info->err, sm.runs);
   bool dense = false;
   if (a.dense) {
     densify(sm, g, n_u, t);
@@ -1006,7 +1050,7 @@ __global__ void __launch_bounds__(UBLOCK) k_big_chunks(BigArgs a, ListBuf o) {
     dense = sm.far == 0;
     if (!dense)
       gather<SCATTERED, WEIGHTED>(g, s0, n_u, c, a.grouped, SCATTERED ? 0 : a.rbase[c], SCATTERED ? 0 : a.rbase[c + 1],
-                                  s_sb, 1, a.pc, a.stall, a.weight, &a.info->err);
+                                  s_sb, 1, a.pc, a.stall, a.weight, &a.info->err, sm.runs);
   }
   int kbits, pcb;
   uint32_t tz;

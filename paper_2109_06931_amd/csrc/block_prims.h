@@ -129,6 +129,10 @@ struct BlockRadix {
   static_assert(ITEMS <= 255, "8-bit per-thread counters");
 
   __device__ static inline int pad(int i) { return i + (i >> 5); }
+  // pad(t * ITEMS + i) for the ITEMS slots of thread t: one base plus i, since
+  // a thread's slots never straddle a multiple of 32 (ITEMS divides 32)
+  static_assert(32 % ITEMS == 0, "a thread's slots must not straddle a padding boundary");
+  __device__ static inline int row_base(int t) { return t * ITEMS + ((t * ITEMS) >> 5); }
 
   // register counters: digit d is byte (d & 7) of h[d >> 3] (two 64-bit words,
   // indexed by shifts so that nothing becomes an indexed private array)
@@ -191,7 +195,11 @@ struct BlockRadix {
         if (lane_id() < 16) s_doff[lane_id()] = inc - a;
       }
       __syncthreads();
-      // 4. positions: digit offset + thread prefix + running count
+      // 4. positions: digit offset + thread prefix + running count.  The
+      // digits are extracted again rather than kept from step 1: holding 2 x
+      // ITEMS values across the scans costs more registers than the shifts.
+#pragma unroll
+      for (int i = 0; i < ITEMS; ++i) asm volatile("" : "+v"(key[i]));
       uint64_t r0 = 0, r1 = 0;
       if constexpr (NV == 0) {
         // one plane: write each key as soon as its position is known
@@ -206,7 +214,7 @@ struct BlockRadix {
         }
         __syncthreads();
 #pragma unroll
-        for (int i = 0; i < ITEMS; ++i) key[i] = (FULL || tid * ITEMS + i < n) ? s_buf[pad(tid * ITEMS + i)] : 0u;
+        for (int i = 0; i < ITEMS; ++i) key[i] = (FULL || tid * ITEMS + i < n) ? s_buf[row_base(tid) + i] : 0u;
         __syncthreads();
       } else {
         uint32_t pos[ITEMS];
@@ -238,7 +246,7 @@ struct BlockRadix {
       if ((striped ? i * BLOCK + tid : tid * ITEMS + i) < n) s_buf[pad((int)pos[i])] = v[i];
     __syncthreads();
 #pragma unroll
-    for (int i = 0; i < ITEMS; ++i) v[i] = tid * ITEMS + i < n ? s_buf[pad(tid * ITEMS + i)] : 0u;
+    for (int i = 0; i < ITEMS; ++i) v[i] = tid * ITEMS + i < n ? s_buf[row_base(tid) + i] : 0u;
     __syncthreads();
   }
 };

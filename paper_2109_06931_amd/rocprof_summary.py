@@ -4,12 +4,17 @@
         kernel table from *kernel_stats.csv: calls, average and total duration
     python -m paper_2109_06931_amd.rocprof_summary pmc DIR
         per-kernel average of every counter in *counter_collection.csv
+    python -m paper_2109_06931_amd.rocprof_summary bytes --fetch D1 --write D2 \\
+            --copy-fetch D3 --copy-write D4 --copy-bytes B
+        table of read and written bytes per dispatch for every kernel, scaled
+        as below
     python -m paper_2109_06931_amd.rocprof_summary traffic --fetch D1 --write D2 \\
-            --copy-fetch D3 --copy-write D4 --copy-bytes B --kernel NAME --source FILE --out JSON
+            --copy-fetch D3 --copy-write D4 --copy-bytes B --kernel NAME --source FILE [--source FILE ...] --out JSON
         HBM bytes per launch of kernel NAME: FETCH_SIZE and WRITE_SIZE (KiB per
         dispatch) scaled by what the same counters read for a plain copy of B
-        bytes; records the sha256 of the kernel's source so that readers can
-        tell when the figures no longer describe the code.
+        bytes; records the sha256 of the kernel's sources (concatenated in the
+        order given) so that readers can tell when the figures no longer
+        describe the code.
 """
 import argparse
 import csv
@@ -64,15 +69,43 @@ def _pick(table, kernel):
     return max(hits.values(), key=lambda v: v.get("dispatches", 0))
 
 
+def _scales(a):
+    cf = max(pmc_table(a.copy_fetch).values(), key=lambda v: v.get("FETCH_SIZE", 0))["FETCH_SIZE"]
+    cw = max(pmc_table(a.copy_write).values(), key=lambda v: v.get("WRITE_SIZE", 0))["WRITE_SIZE"]
+    return cf, cw, a.copy_bytes / (cf * 1024.0), a.copy_bytes / (cw * 1024.0)
+
+
+def bytes_table(a):
+    fetch, write = pmc_table(a.fetch), pmc_table(a.write)
+    _, _, sf, sw = _scales(a)
+    rows = []
+    for k in set(fetch) | set(write):
+        f = fetch.get(k, {}).get("FETCH_SIZE", 0.0)
+        w = write.get(k, {}).get("WRITE_SIZE", 0.0)
+        rows.append((f * 1024.0 * sf + w * 1024.0 * sw, k, f, w))
+    rows.sort(reverse=True)
+    lines = ["| kernel | FETCH_SIZE KiB/dispatch | WRITE_SIZE KiB/dispatch | read GB (scaled) | written GB (scaled) |",
+             "|---|---:|---:|---:|---:|"]
+    for _, k, f, w in rows:
+        if k.startswith("__amd_rocclr") or k.startswith("void at::"):
+            continue
+        lines.append(f"| `{_short(k)}` | {f:,.0f} | {w:,.0f} | {f * 1024 * sf / 1e9:.3f} | {w * 1024 * sw / 1e9:.3f} |")
+    return "\n".join(lines)
+
+
+def sources_sha256(files):
+    h = hashlib.sha256()
+    for f in files:
+        with open(f, "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()
+
+
 def traffic(a):
     f = _pick(pmc_table(a.fetch), a.kernel)["FETCH_SIZE"]
     w = _pick(pmc_table(a.write), a.kernel)["WRITE_SIZE"]
-    cf = max(pmc_table(a.copy_fetch).values(), key=lambda v: v.get("FETCH_SIZE", 0))["FETCH_SIZE"]
-    cw = max(pmc_table(a.copy_write).values(), key=lambda v: v.get("WRITE_SIZE", 0))["WRITE_SIZE"]
-    sf, sw = a.copy_bytes / (cf * 1024.0), a.copy_bytes / (cw * 1024.0)
-    with open(a.source, "rb") as fh:
-        sha = hashlib.sha256(fh.read()).hexdigest()
-    out = {"kernel": a.kernel, "source": os.path.relpath(a.source), "source_sha256": sha,
+    cf, cw, sf, sw = _scales(a)
+    out = {"kernel": a.kernel, "sources": [os.path.relpath(f) for f in a.source], "source_sha256": sources_sha256(a.source),
            "fetch_kib_per_launch": f, "write_kib_per_launch": w,
            "copy_bytes": a.copy_bytes, "copy_fetch_kib": cf, "copy_write_kib": cw,
            "fetch_scale": sf, "write_scale": sw,
@@ -91,8 +124,13 @@ def main(argv=None):
     p = sub.add_parser("pmc")
     p.add_argument("dir")
     t = sub.add_parser("traffic")
-    for k in ["fetch", "write", "copy-fetch", "copy-write", "kernel", "source", "out"]:
+    for k in ["fetch", "write", "copy-fetch", "copy-write", "kernel", "out"]:
         t.add_argument(f"--{k}", required=True)
+    t.add_argument("--source", action="append", required=True)
+    b = sub.add_parser("bytes")
+    for k in ["fetch", "write", "copy-fetch", "copy-write"]:
+        b.add_argument(f"--{k}", required=True)
+    b.add_argument("--copy-bytes", type=int, required=True)
     t.add_argument("--copy-bytes", type=int, required=True)
     a = ap.parse_args(argv)
     if a.cmd == "stats":
@@ -100,6 +138,8 @@ def main(argv=None):
     elif a.cmd == "pmc":
         for k, v in sorted(pmc_table(a.dir).items(), key=lambda kv: kv[0]):
             print(_short(k), json.dumps({c: round(x, 1) for c, x in v.items()}))
+    elif a.cmd == "bytes":
+        print(bytes_table(a))
     else:
         print(json.dumps(traffic(a), indent=1))
 

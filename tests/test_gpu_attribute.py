@@ -107,6 +107,10 @@ def test_attribute_tiny(hpa, hctx, seed):
     (3, dict(shuffled=True)),
     (4, dict(seg_mean=20000.0)),
     (5, dict(seg_mean=30.0)),
+    # runs of about 10 samples: still the run path, but a unit spans more runs
+    # than its workgroup copies to LDS, so it walks the global run list
+    (6, dict(seg_mean=10.0)),
+    (7, dict(seg_mean=10.0, weighted=True)),
 ])
 def test_attribute_small(hpa, hctx, seed, kw):
     w = small_config(seed, n_samples=300_000, **kw)
