@@ -406,17 +406,20 @@ __device__ inline void gather(Gathered<WEIGHTED>& g, uint64_t s0, uint64_t n_u, 
                               uint64_t r_lo, uint64_t r_hi, const uint64_t* __restrict__ sb_lds,
                               uint32_t n_cu, const uint64_t* __restrict__ pc, const uint8_t* __restrict__ stall,
                               const uint32_t* __restrict__ weight, uint32_t* err, Run* s_runs) {
+  // every load is issued before any loaded value is used (the stall test
+  // and the packing come after the loop), so a thread's loads overlap
+  uint32_t st[UITEMS], lcs[UITEMS];
   auto load = [&](int i, uint64_t src, uint32_t lc) {
     g.pc[i] = pc[src];
-    uint8_t st = stall[src];
-    if (st >= NS) { atomicOr(err, (uint32_t)ERR_STALL); st = 0; }
-    g.meta[i] = (uint32_t)st | (lc << 4);
+    st[i] = stall[src];
+    lcs[i] = lc;
     if constexpr (WEIGHTED) g.w[i] = weight[src];
   };
 #pragma unroll
   for (int i = 0; i < UITEMS; ++i) {
     g.pc[i] = 0;
-    g.meta[i] = 0;
+    st[i] = 0;
+    lcs[i] = 0;
     if constexpr (WEIGHTED) g.w[i] = 0;
   }
   if constexpr (SCATTERED) {
@@ -447,6 +450,13 @@ __device__ inline void gather(Gathered<WEIGHTED>& g, uint64_t s0, uint64_t n_u, 
       gather_runs<WEIGHTED>(grp, r_lo, r_hi, s0, n_u, cb, load);
     }
   }
+  bool bad = false;
+#pragma unroll
+  for (int i = 0; i < UITEMS; ++i) {
+    bad |= st[i] >= NS;
+    g.meta[i] = (st[i] < NS ? st[i] : 0u) | (lcs[i] << 4);
+  }
+  if (bad) atomicOr(err, (uint32_t)ERR_STALL);
 }
 
 // Stage the dense window tables in LDS (the caller synchronises before use)
@@ -607,7 +617,8 @@ __device__ inline uint32_t find_heads(SortSmem& sm, const K (&key)[UITEMS], uint
   const int tid = threadIdx.x;
   sm.last_lo[tid] = (uint32_t)key[UITEMS - 1];
   sm.last_hi[tid] = (uint32_t)((uint64_t)key[UITEMS - 1] >> 32);
-  for (uint32_t l = tid; l <= n_cu; l += UBLOCK) sm.ucnt[l] = 0;
+  // sm.ucnt first holds each context's first unique index (NONE32: no keys)
+  for (uint32_t l = tid; l <= n_cu; l += UBLOCK) sm.ucnt[l] = NONE32;
   __syncthreads();
   K prev = prev_last<K>(sm, tid);
   uint32_t heads = 0;
@@ -631,13 +642,33 @@ __device__ inline uint32_t find_heads(SortSmem& sm, const K (&key)[UITEMS], uint
     if (h) {
       sm.upos[u] = (uint16_t)p;
       if constexpr (sizeof(K) == 4) sm.buf[u] = (uint32_t)key[i];
-      atomicAdd(&sm.ucnt[(uint32_t)((uint64_t)key[i] >> (pcb + 4))], 1u);
+      // unique keys are ordered by local context: a head whose context
+      // differs from the previous key's starts that context's keys
+      const uint32_t lc = (uint32_t)((uint64_t)key[i] >> (pcb + 4));
+      if (p == 0 || lc != (uint32_t)((uint64_t)prev >> (pcb + 4))) sm.ucnt[lc] = u;
       ++u;
     }
     prev = key[i];
   }
   if (tid == 0) sm.upos[nU] = (uint16_t)n_u;
   __syncthreads();
+  // keys per context: the next non-empty context's first index (a suffix
+  // minimum over the lanes of wave 0, n_cu <= 64) minus this one's; thread l
+  // converts entry l, and only thread l reads it afterwards
+  static_assert(MAXC <= WAVE, "one lane per local context");
+  if (tid < WAVE) {
+    const uint32_t l = (uint32_t)tid;
+    const uint32_t st = l < n_cu ? sm.ucnt[l] : NONE32;
+    uint32_t suf = st;
+    for (uint32_t d = 1; d < (uint32_t)WAVE; d <<= 1) {
+      const uint32_t o = __shfl(suf, (int)min(l + d, (uint32_t)WAVE - 1), WAVE);
+      if (l + d < (uint32_t)WAVE) suf = min(suf, o);
+    }
+    uint32_t next = __shfl(suf, (int)min(l + 1, (uint32_t)WAVE - 1), WAVE);
+    if (l + 1 >= (uint32_t)WAVE) next = NONE32;
+    next = min(next, nU);
+    if (l < n_cu) sm.ucnt[l] = st == NONE32 ? 0u : next - st;
+  }
   return heads;
 }
 

@@ -111,10 +111,11 @@ __device__ inline T block_excl_scan(T v, T* s_tmp, T* total) {
 // thread t is valid when i * BLOCK + t < n ("striped"), afterwards when
 // t * ITEMS + i < n.
 //
-// A pass: each thread counts its digits in registers (four 8-bit counters per
-// 32-bit register, so ITEMS <= 255); the 16 counts, widened to 16-bit pairs,
-// go to LDS as 8 columns of one word per thread; every column is scanned over
-// the threads (wave scans), which gives each thread its exclusive prefix per
+// A pass: each thread counts its digits in registers (16 four-bit counters in
+// one 64-bit register; the thread's last item is kept aside, so a counter
+// never exceeds ITEMS - 1 <= 15); the 16 counts, widened to 16-bit pairs, go
+// to LDS as 8 columns of one word per thread; every column is scanned over the
+// threads (wave scans), which gives each thread its exclusive prefix per
 // digit, and the digit totals are scanned into digit offsets; each item's new
 // position is digit offset + thread prefix + running count, and the key is
 // written there in the exchange plane and read back blocked.
@@ -126,24 +127,13 @@ struct BlockRadix {
   static constexpr int CNT_WORDS = 8 * BLOCK;   // 8 columns of 16-bit digit pairs
   static constexpr int DOFF_WORDS = 16;
   static_assert(T < 65536, "16-bit counters");
-  static_assert(ITEMS <= 255, "8-bit per-thread counters");
+  static_assert(ITEMS >= 2 && ITEMS <= 16, "4-bit per-thread counters hold ITEMS - 1");
 
   __device__ static inline int pad(int i) { return i + (i >> 5); }
   // pad(t * ITEMS + i) for the ITEMS slots of thread t: one base plus i, since
   // a thread's slots never straddle a multiple of 32 (ITEMS divides 32)
   static_assert(32 % ITEMS == 0, "a thread's slots must not straddle a padding boundary");
   __device__ static inline int row_base(int t) { return t * ITEMS + ((t * ITEMS) >> 5); }
-
-  // register counters: digit d is byte (d & 7) of h[d >> 3] (two 64-bit words,
-  // indexed by shifts so that nothing becomes an indexed private array)
-  __device__ static inline uint32_t get8(uint64_t h0, uint64_t h1, uint32_t d) {
-    return (uint32_t)(((d & 8) ? h1 : h0) >> ((d & 7) * 8)) & 0xFFu;
-  }
-  __device__ static inline void inc8(uint64_t& h0, uint64_t& h1, uint32_t d) {
-    const uint64_t one = 1ull << ((d & 7) * 8);
-    h0 += (d & 8) ? 0ull : one;
-    h1 += (d & 8) ? one : 0ull;
-  }
 
   // Sort the first n 32-bit keys on bits [0, bits); the NV payload arrays
   // (v0, then v1) move with their keys.  Afterwards position p is item
@@ -161,16 +151,20 @@ struct BlockRadix {
     if (FULL) n = T;
 #define HPA_VALID(i) (FULL || (striped ? (i) * BLOCK + tid : tid * ITEMS + (i)) < n)
     for (int shift = 0; shift < bits; shift += 4) {
-      // 1. per-thread digit counts
-      uint64_t h0 = 0, h1 = 0;
+      // 1. per-thread digit counts of items 0 .. ITEMS - 2; the last item's
+      //    digit (16: none) is added when the columns are formed
+      uint64_t h = 0;
 #pragma unroll
-      for (int i = 0; i < ITEMS; ++i)
-        if (HPA_VALID(i)) inc8(h0, h1, (key[i] >> shift) & 15u);
+      for (int i = 0; i < ITEMS - 1; ++i)
+        if (HPA_VALID(i)) h += 1ull << (((key[i] >> shift) & 15u) * 4);
+      const uint32_t dl = HPA_VALID(ITEMS - 1) ? (key[ITEMS - 1] >> shift) & 15u : 16u;
       // 2. widen to 16-bit pairs: column k holds digits 2k (low) and 2k+1 (high)
 #pragma unroll
       for (int k = 0; k < 8; ++k) {
-        const uint32_t w = (uint32_t)(((k & 4) ? h1 : h0) >> (16 * (k & 3)));
-        s_cnt[k * BLOCK + tid] = (w & 0xFFu) | ((w & 0xFF00u) << 8);
+        const uint32_t w = (uint32_t)(h >> (8 * k));
+        uint32_t col = (w & 0xFu) | ((w & 0xF0u) << 12);
+        if ((dl >> 1) == (uint32_t)k) col += 1u << ((dl & 1u) * 16);
+        s_cnt[k * BLOCK + tid] = col;
       }
       __syncthreads();
       // 3. exclusive scan of every column over the threads; digit totals
@@ -200,18 +194,19 @@ struct BlockRadix {
       // ITEMS values across the scans costs more registers than the shifts.
 #pragma unroll
       for (int i = 0; i < ITEMS; ++i) asm volatile("" : "+v"(key[i]));
-      uint64_t r0 = 0, r1 = 0;
+      uint64_t r = 0;
+      auto position = [&](int i) -> uint32_t {
+        const uint32_t d = (key[i] >> shift) & 15u;
+        const uint32_t pre = (s_cnt[(d >> 1) * BLOCK + tid] >> ((d & 1) * 16)) & 0xFFFFu;
+        const uint32_t p = s_doff[d] + pre + ((uint32_t)(r >> (d * 4)) & 15u);
+        if (i < ITEMS - 1) r += 1ull << (d * 4);
+        return p;
+      };
       if constexpr (NV == 0) {
         // one plane: write each key as soon as its position is known
 #pragma unroll
-        for (int i = 0; i < ITEMS; ++i) {
-          if (HPA_VALID(i)) {
-            const uint32_t d = (key[i] >> shift) & 15u;
-            const uint32_t pre = (s_cnt[(d >> 1) * BLOCK + tid] >> ((d & 1) * 16)) & 0xFFFFu;
-            s_buf[pad((int)(s_doff[d] + pre + get8(r0, r1, d)))] = key[i];
-            inc8(r0, r1, d);
-          }
-        }
+        for (int i = 0; i < ITEMS; ++i)
+          if (HPA_VALID(i)) s_buf[pad((int)position(i))] = key[i];
         __syncthreads();
 #pragma unroll
         for (int i = 0; i < ITEMS; ++i) key[i] = (FULL || tid * ITEMS + i < n) ? s_buf[row_base(tid) + i] : 0u;
@@ -219,15 +214,7 @@ struct BlockRadix {
       } else {
         uint32_t pos[ITEMS];
 #pragma unroll
-        for (int i = 0; i < ITEMS; ++i) {
-          pos[i] = 0;
-          if (HPA_VALID(i)) {
-            const uint32_t d = (key[i] >> shift) & 15u;
-            const uint32_t pre = (s_cnt[(d >> 1) * BLOCK + tid] >> ((d & 1) * 16)) & 0xFFFFu;
-            pos[i] = s_doff[d] + pre + get8(r0, r1, d);
-            inc8(r0, r1, d);
-          }
-        }
+        for (int i = 0; i < ITEMS; ++i) pos[i] = HPA_VALID(i) ? position(i) : 0u;
         exchange_u32(v0, pos, s_buf, n, striped);
         if constexpr (NV == 2) exchange_u32(v1, pos, s_buf, n, striped);
         exchange_u32(key, pos, s_buf, n, striped);
