@@ -46,7 +46,7 @@ constexpr int RUN_CAP = 1024;        // runs a sort workgroup copies to LDS for 
 using Sorter = BlockRadix<UBLOCK, UITEMS>;
 
 constexpr uint64_t M40 = (1ull << 40) - 1;
-constexpr int ERR_CTX = 1, ERR_STALL = 2, ERR_WIDE = 4;
+constexpr int ERR_CTX = 1, ERR_STALL = 2, ERR_WIDE = 4, ERR_SPLIT = 8;
 constexpr uint64_t WIDE_CHUNK = ~0ull;  // chunk list length: left for the general chunk kernel
 
 struct Run {
@@ -65,6 +65,11 @@ struct PlanInfo {
   uint32_t n_big;
   uint32_t max_chunks;
   uint32_t err;
+  uint32_t n_bigall;   // contexts over T samples
+  uint32_t n_split;    // of those, split into parts by coordinate range
+  uint32_t n_virtual;  // contexts after the split (each part counts as one)
+  uint32_t n_parts;    // parts of the split contexts
+  unsigned long long split_samples;
 };
 
 __device__ inline int bits_for(uint64_t v) { return v ? 64 - __clzll(v) : 0; }
@@ -175,20 +180,26 @@ k_scan_ctx(const uint32_t* __restrict__ ctx, uint64_t n, uint32_t n_ctx, unsigne
 }
 
 // ----------------------------------------------------------------------------
-// plan: one workgroup walks the contexts in order
+// plan: one workgroup walks the contexts in order.  A unit is a run of
+// contexts packed together; unit_big holds the big-context index of a unit of
+// one context over T samples, UNIT_PLAIN for a unit read through the run
+// list, and UNIT_PART for a unit of parts of a split context (grp, when
+// given, names the split context a part belongs to, NONE32 for the others;
+// units never mix groups).
 // ----------------------------------------------------------------------------
 constexpr int PLAN_BLOCK = 1024;
 constexpr int PLAN_ITEMS = 8;
+constexpr int32_t UNIT_PLAIN = -1, UNIT_PART = -2;
 
 enum : uint8_t { KIND_S = 0, KIND_M = 1, KIND_B = 2 };
 
 __device__ inline uint8_t ctx_kind(uint64_t n) { return n <= (uint64_t)UHALF ? KIND_S : (n <= (uint64_t)UT ? KIND_M : KIND_B); }
 
 __global__ void __launch_bounds__(PLAN_BLOCK)
-k_plan(const unsigned long long* __restrict__ hist, uint32_t n_ctx, uint64_t* __restrict__ sbase,
-       uint64_t* __restrict__ rbase, uint32_t* __restrict__ unit_begin, int32_t* __restrict__ unit_big,
-       uint32_t* __restrict__ big_ctx, uint64_t* __restrict__ big_sbase, uint64_t* __restrict__ big_chunk,
-       PlanInfo* __restrict__ info) {
+k_plan(const unsigned long long* __restrict__ hist, uint32_t n_ctx, const uint32_t* __restrict__ grp,
+       uint64_t* __restrict__ sbase, uint64_t* __restrict__ rbase, uint32_t* __restrict__ unit_begin,
+       int32_t* __restrict__ unit_big, uint32_t* __restrict__ big_ctx, uint64_t* __restrict__ big_sbase,
+       uint64_t* __restrict__ big_chunk, PlanInfo* __restrict__ info) {
   __shared__ unsigned long long s_tmp[PLAN_BLOCK / WAVE + 1];
   __shared__ uint32_t s_max;
   const int tid = threadIdx.x;
@@ -235,7 +246,8 @@ k_plan(const unsigned long long* __restrict__ hist, uint32_t n_ctx, uint64_t* __
           uint8_t k = ctx_kind(nn[i]);
           uint8_t kp = c > 0 ? ctx_kind(n_prev) : KIND_S;
           uint64_t ps_prev = ps_c - (c > 0 && kp == KIND_S ? n_prev : 0);
-          st = c == 0 || k != KIND_S || kp != KIND_S || (c % MAXC) == 0 || (ps_c / UHALF) != (ps_prev / UHALF);
+          st = c == 0 || k != KIND_S || kp != KIND_S || (c % MAXC) == 0 || (ps_c / UHALF) != (ps_prev / UHALF) ||
+               (grp && grp[c] != grp[c - 1]);
           if (k == KIND_S) ps_c += nn[i];
           n_prev = nn[i];
         }
@@ -257,7 +269,7 @@ k_plan(const unsigned long long* __restrict__ hist, uint32_t n_ctx, uint64_t* __
         const uint8_t k = ctx_kind(nn[i]);
         if (starts[i]) {
           unit_begin[u] = c;
-          unit_big[u] = k == KIND_B ? (int32_t)bg : -1;
+          unit_big[u] = k == KIND_B ? (int32_t)bg : (grp && grp[c] != NONE32 ? UNIT_PART : UNIT_PLAIN);
           ++u;
         }
         if (k == KIND_B) {
@@ -295,17 +307,303 @@ k_plan(const unsigned long long* __restrict__ hist, uint32_t n_ctx, uint64_t* __
 
 // ----------------------------------------------------------------------------
 // group_runs: runs ordered by context; one 64-bit atomic gives both the run's
-// slot and its sample offset within the context
+// slot and its sample offset within the context.  With split contexts, vsolo
+// maps a context to its virtual id (NONE32 for a split context, whose samples
+// are scattered into parts instead), and the grouped run carries that id.
 // ----------------------------------------------------------------------------
-__global__ void k_group_runs(const Run* __restrict__ runs, uint64_t n_runs, const uint64_t* __restrict__ sbase,
-                             const uint64_t* __restrict__ rbase, unsigned long long* __restrict__ cur,
-                             Run* __restrict__ grouped) {
+__global__ void k_group_runs(const Run* __restrict__ runs, uint64_t n_runs, const uint32_t* __restrict__ vsolo,
+                             const uint64_t* __restrict__ sbase, const uint64_t* __restrict__ rbase,
+                             unsigned long long* __restrict__ cur, Run* __restrict__ grouped) {
   for (uint64_t r = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; r < n_runs; r += (uint64_t)gridDim.x * blockDim.x) {
     Run x = runs[r];
+    if (vsolo) {
+      const uint32_t v = vsolo[x.ctx];
+      if (v == NONE32) continue;
+      x.ctx = v;
+    }
     unsigned long long old = atomicAdd(&cur[x.ctx], (1ull << 40) | (unsigned long long)x.len);
     uint64_t k = old >> 40, soff = old & M40;
     x.flat = sbase[x.ctx] + soff;
     grouped[rbase[x.ctx] + k] = x;
+  }
+}
+
+// ----------------------------------------------------------------------------
+// Split of big contexts by coordinate range
+//
+// A context with more than T samples is cut into parts of at most T samples
+// along its dense coordinates: a histogram of its samples over NB coordinate
+// buckets (bucket = D >> bshift), buckets packed in order into parts by the
+// plan's packing rule, and its samples scattered into part order.  The parts
+// of a context cover increasing coordinate ranges, so sorting each part on its
+// own and concatenating the results gives the context's keys in order; the
+// parts then pass through the unit passes as contexts of their own (virtual
+// contexts).  A context with a pc outside the dense coordinates, or with one
+// bucket over T samples, keeps the chunk path.
+// ----------------------------------------------------------------------------
+constexpr int NB = 1024;  // coordinate buckets per big context
+constexpr int SPLIT_BLOCK = 256;
+constexpr int SPLIT_ITEMS = 8;
+constexpr int SPLIT_ROUND = SPLIT_BLOCK * SPLIT_ITEMS;  // samples per workgroup round
+constexpr uint32_t SPLIT_NO = 0xFFFFFFFFu;               // no parts: the context keeps the chunk path
+
+// Contexts over T samples get an index (in no particular order).
+__global__ void k_big_index(const unsigned long long* __restrict__ hist, uint32_t n_ctx, int32_t* __restrict__ big_of,
+                            PlanInfo* __restrict__ info) {
+  for (uint32_t c = blockIdx.x * blockDim.x + threadIdx.x; c < n_ctx; c += gridDim.x * blockDim.x)
+    big_of[c] = (hist[c] & M40) > (uint64_t)UT ? (int32_t)atomicAdd(&info->n_bigall, 1u) : -1;
+}
+
+__device__ inline void stage_windows(uint64_t* lo, uint64_t* hi, uint64_t* d, const DenseDev& t, int nthreads) {
+  for (uint32_t i = threadIdx.x; i < t.n_win; i += nthreads) {
+    lo[i] = t.lo[i];
+    hi[i] = t.hi[i];
+  }
+  if (t.n_win)
+    for (uint32_t i = threadIdx.x; i <= t.n_win; i += nthreads) d[i] = t.d[i];
+}
+
+// Bucket histogram of every big context, one run at a time per workgroup (a
+// run belongs to one context); a pc without a dense coordinate flags its
+// context.
+__global__ void __launch_bounds__(SPLIT_BLOCK)
+k_big_hist(const Run* __restrict__ runs, uint64_t n_runs, const int32_t* __restrict__ big_of,
+           const uint64_t* __restrict__ pc, DenseDev dd, uint32_t bshift, uint32_t* __restrict__ bhist,
+           uint32_t* __restrict__ bflag) {
+  __shared__ uint32_t s_h[NB];
+  __shared__ uint64_t s_lo[DENSE_MAX_WIN], s_hi[DENSE_MAX_WIN], s_d[DENSE_MAX_WIN + 1];
+  stage_windows(s_lo, s_hi, s_d, dd, SPLIT_BLOCK);
+  const DenseDev t{s_lo, s_hi, s_d, dd.scope_of, dd.n_win, dd.tz};
+  for (uint64_t r = blockIdx.x; r < n_runs; r += gridDim.x) {
+    const Run x = runs[r];
+    const int32_t b = big_of[x.ctx];
+    if (b < 0) continue;
+    for (int k = threadIdx.x; k < NB; k += SPLIT_BLOCK) s_h[k] = 0;
+    __syncthreads();
+    bool far = false;
+    for (uint32_t o = 0; o < x.len; o += SPLIT_ROUND) {
+      uint64_t v[SPLIT_ITEMS];
+#pragma unroll
+      for (int i = 0; i < SPLIT_ITEMS; ++i) {
+        const uint32_t j = o + i * SPLIT_BLOCK + threadIdx.x;
+        v[i] = j < x.len ? pc[x.start + j] : 0;
+      }
+#pragma unroll
+      for (int i = 0; i < SPLIT_ITEMS; ++i) {
+        const uint32_t j = o + i * SPLIT_BLOCK + threadIdx.x;
+        uint64_t D;
+        if (j >= x.len) continue;
+        if (to_dense(t, v[i], D)) atomicAdd(&s_h[(uint32_t)(D >> bshift)], 1u);
+        else far = true;
+      }
+    }
+    if (far) atomicOr(&bflag[b], 1u);
+    __syncthreads();
+    for (int k = threadIdx.x; k < NB; k += SPLIT_BLOCK)
+      if (s_h[k]) atomicAdd(&bhist[(uint64_t)b * NB + k], s_h[k]);
+    __syncthreads();
+  }
+}
+
+// Parts of every big context, one wave each: bucket k starts a part when it is
+// the first, when it or the bucket before holds over T/2 samples, or when the
+// running count of the other (light) buckets crosses a multiple of T/2 between
+// the bucket before and this one.  A part then holds one heavy bucket (at most
+// T samples) or light buckets whose running counts start within one T/2 band,
+// fewer than T samples.  part_of gets each bucket's part, psum (zeroed) each
+// part's samples, n_parts the count (SPLIT_NO: keep the chunk path).
+__global__ void __launch_bounds__(256)
+k_big_parts(const uint32_t* __restrict__ bhist, const uint32_t* __restrict__ bflag, uint32_t n_big,
+            uint32_t* __restrict__ part_of, uint32_t* __restrict__ psum, uint32_t* __restrict__ n_parts) {
+  constexpr int PER = NB / WAVE;
+  const uint32_t b = blockIdx.x * (256 / WAVE) + wave_id();
+  if (b >= n_big) return;
+  const uint32_t l = lane_id();
+  const uint32_t* h = bhist + (uint64_t)b * NB + l * PER;
+  uint32_t cnt[PER];
+  uint32_t light = 0;
+  bool over = false;
+#pragma unroll
+  for (int i = 0; i < PER; ++i) {
+    cnt[i] = h[i];
+    over |= cnt[i] > (uint32_t)UT;
+    light += cnt[i] <= (uint32_t)UHALF ? cnt[i] : 0u;
+  }
+  const uint32_t light_incl = wave_incl_scan(light);
+  if (wave_or((uint32_t)over) || bflag[b]) {
+    if (l == 0) n_parts[b] = SPLIT_NO;
+    return;
+  }
+  // the bucket before this lane's first: its exclusive light count and weight
+  uint32_t prevL = __shfl_up(light_incl - (cnt[PER - 1] <= (uint32_t)UHALF ? cnt[PER - 1] : 0u), 1, WAVE);
+  bool prevH = __shfl_up(cnt[PER - 1] > (uint32_t)UHALF ? 1 : 0, 1, WAVE) != 0;
+  uint32_t L = light_incl - light;
+  uint32_t starts = 0;
+  uint32_t st[PER];
+#pragma unroll
+  for (int i = 0; i < PER; ++i) {
+    const bool heavy = cnt[i] > (uint32_t)UHALF;
+    const bool first = l == 0 && i == 0;
+    st[i] = first || heavy || prevH || (L / UHALF) != (prevL / UHALF);
+    starts += st[i];
+    prevL = L;
+    prevH = heavy;
+    L += heavy ? 0u : cnt[i];
+  }
+  const uint32_t s_incl = wave_incl_scan(starts);
+  uint32_t part = s_incl - starts;  // starts before this lane
+#pragma unroll
+  for (int i = 0; i < PER; ++i) {
+    part += st[i];
+    const uint64_t k = (uint64_t)b * NB + l * PER + i;
+    part_of[k] = part - 1;
+    if (cnt[i]) atomicAdd(&psum[(uint64_t)b * NB + part - 1], cnt[i]);
+  }
+  if (l == WAVE - 1) n_parts[b] = s_incl;
+}
+
+// Virtual contexts, one workgroup: every context stays one, except a split
+// context, which becomes its parts.  Writes the virtual histogram (count, and
+// runs for contexts read through the run list; parts have none), the real
+// context of every virtual one, its group (the split context, or NONE32), the
+// first virtual id of every context (vbase, closed by the total) and vsolo
+// (the virtual id of an unsplit context, NONE32 for a split one).
+__global__ void __launch_bounds__(PLAN_BLOCK)
+k_virtual(const unsigned long long* __restrict__ hist, uint32_t n_ctx, const int32_t* __restrict__ big_of,
+          const uint32_t* __restrict__ n_parts, const uint32_t* __restrict__ psum,
+          unsigned long long* __restrict__ vhist, uint32_t* __restrict__ vreal, uint32_t* __restrict__ vgrp,
+          uint32_t* __restrict__ vbase, uint32_t* __restrict__ vsolo, PlanInfo* __restrict__ info) {
+  __shared__ uint32_t s_tmp[PLAN_BLOCK / WAVE + 1];
+  uint32_t carry = 0, n_split = 0, n_part = 0;
+  unsigned long long split_samples = 0;
+  for (uint32_t b0 = 0; b0 < n_ctx; b0 += PLAN_BLOCK * PLAN_ITEMS) {
+    const uint32_t c0 = b0 + threadIdx.x * PLAN_ITEMS;
+    uint32_t nv[PLAN_ITEMS], local = 0;
+#pragma unroll
+    for (int i = 0; i < PLAN_ITEMS; ++i) {
+      const uint32_t c = c0 + i;
+      nv[i] = 0;
+      if (c < n_ctx) {
+        const int32_t b = big_of[c];
+        nv[i] = (b >= 0 && n_parts[b] != SPLIT_NO) ? n_parts[b] : 1u;
+      }
+      local += nv[i];
+    }
+    uint32_t tot;
+    uint32_t v = carry + block_excl_scan<PLAN_BLOCK>(local, s_tmp, &tot);
+#pragma unroll
+    for (int i = 0; i < PLAN_ITEMS; ++i) {
+      const uint32_t c = c0 + i;
+      if (c >= n_ctx) continue;
+      vbase[c] = v;
+      const int32_t b = big_of[c];
+      if (b >= 0 && n_parts[b] != SPLIT_NO) {
+        vsolo[c] = NONE32;
+        for (uint32_t p = 0; p < nv[i]; ++p) {
+          vhist[v + p] = psum[(uint64_t)b * NB + p];
+          vreal[v + p] = c;
+          vgrp[v + p] = c;
+        }
+        ++n_split;
+        n_part += nv[i];
+        split_samples += hist[c] & M40;
+      } else {
+        vsolo[c] = v;
+        vhist[v] = hist[c];
+        vreal[v] = c;
+        vgrp[v] = NONE32;
+      }
+      v += nv[i];
+    }
+    carry += tot;
+  }
+  atomicAdd(&info->n_split, n_split);
+  atomicAdd(&info->n_parts, n_part);
+  atomicAdd(&info->split_samples, split_samples);
+  if (threadIdx.x == 0) {
+    vbase[n_ctx] = carry;
+    info->n_virtual = carry;
+  }
+}
+
+// Scatter the samples of split contexts into part order (flat positions of
+// the virtual contexts), one run per workgroup at a time: per round, each
+// item's part and its rank among the round's items of that part (LDS
+// counters), one global reservation per part, then the writes.  A
+// reservation past the part's end (which the histogram rules out) is
+// reported and its items dropped.
+__global__ void __launch_bounds__(SPLIT_BLOCK)
+k_big_scatter(const Run* __restrict__ runs, uint64_t n_runs, const int32_t* __restrict__ big_of,
+              const uint32_t* __restrict__ n_parts, const uint32_t* __restrict__ part_of,
+              const uint32_t* __restrict__ vbase, const uint64_t* __restrict__ sbase,
+              unsigned long long* __restrict__ vcur, const uint64_t* __restrict__ pc,
+              const uint8_t* __restrict__ stall, const uint32_t* __restrict__ weight, DenseDev dd, uint32_t bshift,
+              uint64_t* __restrict__ tpc, uint8_t* __restrict__ tst, uint32_t* __restrict__ tw,
+              uint32_t* __restrict__ err) {
+  __shared__ uint32_t s_cnt[NB];
+  __shared__ unsigned long long s_base[NB];
+  __shared__ uint64_t s_lo[DENSE_MAX_WIN], s_hi[DENSE_MAX_WIN], s_d[DENSE_MAX_WIN + 1];
+  stage_windows(s_lo, s_hi, s_d, dd, SPLIT_BLOCK);
+  const DenseDev t{s_lo, s_hi, s_d, dd.scope_of, dd.n_win, dd.tz};
+  for (uint64_t r = blockIdx.x; r < n_runs; r += gridDim.x) {
+    const Run x = runs[r];
+    const int32_t b = big_of[x.ctx];
+    if (b < 0) continue;
+    const uint32_t np = n_parts[b];
+    if (np == SPLIT_NO) continue;
+    const uint32_t vb = vbase[x.ctx];
+    for (uint32_t o = 0; o < x.len; o += SPLIT_ROUND) {
+      for (uint32_t k = threadIdx.x; k < np; k += SPLIT_BLOCK) s_cnt[k] = 0;
+      __syncthreads();
+      uint64_t v[SPLIT_ITEMS];
+      uint32_t part[SPLIT_ITEMS], rank[SPLIT_ITEMS];
+#pragma unroll
+      for (int i = 0; i < SPLIT_ITEMS; ++i) {
+        const uint32_t j = o + i * SPLIT_BLOCK + threadIdx.x;
+        v[i] = j < x.len ? pc[x.start + j] : 0;
+      }
+#pragma unroll
+      for (int i = 0; i < SPLIT_ITEMS; ++i) {
+        const uint32_t j = o + i * SPLIT_BLOCK + threadIdx.x;
+        part[i] = NONE32;
+        rank[i] = 0;
+        uint64_t D;
+        if (j >= x.len) continue;
+        // the histogram found a coordinate for every pc of a split context,
+        // in a bucket of some part
+        const uint32_t p = to_dense(t, v[i], D) ? part_of[(uint64_t)b * NB + (uint32_t)(D >> bshift)] : NONE32;
+        if (p < np) {
+          part[i] = p;
+          rank[i] = atomicAdd(&s_cnt[p], 1u);
+        } else {
+          atomicOr(err, (uint32_t)ERR_SPLIT);
+        }
+      }
+      __syncthreads();
+      for (uint32_t k = threadIdx.x; k < np; k += SPLIT_BLOCK) {
+        const uint32_t c = s_cnt[k];
+        if (!c) continue;
+        const unsigned long long at = sbase[vb + k] + atomicAdd(&vcur[vb + k], (unsigned long long)c);
+        if (at + c > sbase[vb + k + 1]) {
+          atomicOr(err, (uint32_t)ERR_SPLIT);
+          s_base[k] = ~0ull;
+        } else {
+          s_base[k] = at;
+        }
+      }
+      __syncthreads();
+#pragma unroll
+      for (int i = 0; i < SPLIT_ITEMS; ++i) {
+        if (part[i] == NONE32) continue;
+        const unsigned long long at = s_base[part[i]];
+        if (at == ~0ull) continue;
+        const uint64_t src = x.start + o + i * SPLIT_BLOCK + threadIdx.x;
+        tpc[at + rank[i]] = v[i];
+        tst[at + rank[i]] = stall[src];
+        if (tw) tw[at + rank[i]] = weight[src];
+      }
+      __syncthreads();
+    }
   }
 }
 
@@ -743,6 +1041,8 @@ struct UnitArgs {
   uint32_t* shi;               // high word (units with keys wider than 32 bits)
   uint32_t* scnt;              // count (unweighted)
   unsigned long long* scnt64;  // count (weighted)
+  int32_t kind;                // the unit class a sort launch handles (UNIT_PLAIN or UNIT_PART)
+  const uint32_t* vreal;       // real context of every virtual one (null: no split contexts)
 };
 
 // Stage the unit's unique keys, counts and decoding parameters.
@@ -796,7 +1096,8 @@ __global__ void __launch_bounds__(UBLOCK) k_units32(UnitArgs a) {
   __shared__ SortSmem sm;
   __shared__ uint64_t s_sb[MAXC + 1];
   const uint32_t u = blockIdx.x;
-  if (a.unit_big[u] >= 0) return;  // a big context: its keys come from the chunk path
+  // units of the other class, or a big context (its keys come from the chunk path)
+  if (a.unit_big[u] != a.kind) return;
   if (GENERAL && a.meta[u].flags != UM_WIDE) return;
   const uint32_t cb = a.unit_begin[u], ce = a.unit_begin[u + 1];
   const uint64_t s0 = a.sbase[cb];
@@ -867,11 +1168,15 @@ __global__ void __launch_bounds__(1024) k_unit_offsets(const UnitMeta* __restric
   }
 }
 
-// Context offsets: one wave per unit scans its per-context key counts.
+// Context offsets: one wave per unit scans its per-context key counts.  With
+// split contexts the unit's contexts are virtual: a real context's offset is
+// that of its first virtual context.
 __global__ void __launch_bounds__(256) k_ctx_offsets(const uint32_t* __restrict__ unit_begin,
                                                      const int32_t* __restrict__ unit_big,
                                                      const uint32_t* __restrict__ ucnt,
                                                      const uint64_t* __restrict__ unit_off, uint32_t n_units,
+                                                     const uint32_t* __restrict__ vreal,
+                                                     const uint32_t* __restrict__ vbase,
                                                      uint64_t* __restrict__ ctx_off, uint64_t* __restrict__ big_out) {
   const uint32_t u = blockIdx.x * (256 / WAVE) + wave_id();
   if (u >= n_units) return;
@@ -880,7 +1185,7 @@ __global__ void __launch_bounds__(256) k_ctx_offsets(const uint32_t* __restrict_
   const int32_t big = unit_big[u];
   if (big >= 0) {  // one context
     if (lane_id() == 0) {
-      ctx_off[cb] = off;
+      ctx_off[vreal ? vreal[cb] : cb] = off;
       big_out[big] = off;
     }
     return;
@@ -888,7 +1193,11 @@ __global__ void __launch_bounds__(256) k_ctx_offsets(const uint32_t* __restrict_
   const uint32_t l = lane_id();
   const uint32_t v = l < ce - cb ? ucnt[(uint64_t)u * MAXC + l] : 0u;
   const uint32_t inc = wave_incl_scan(v);
-  if (l < ce - cb) ctx_off[cb + l] = off + inc - v;
+  if (l < ce - cb) {
+    const uint32_t vc = cb + l;
+    const uint32_t c = vreal ? vreal[vc] : vc;
+    if (!vreal || vbase[c] == vc) ctx_off[c] = off + inc - v;
+  }
 }
 
 // Write pass: unpack every unit's staged keys into the outputs.
@@ -945,7 +1254,7 @@ __global__ void __launch_bounds__(WBLOCK) k_units_write(UnitArgs a, const uint64
       const uint32_t lc = (uint32_t)(k[q] >> (m.pcb + 4));
       const uint64_t v = m.lo + (((k[q] >> 4) & pmask) << m.tz);
       const uint64_t o = o0 + ui;
-      out.ctx[o] = cb + lc;
+      out.ctx[o] = a.vreal ? a.vreal[cb + lc] : cb + lc;
       out.stall[o] = (uint8_t)(k[q] & 15);
       out.count[o] = c[q];
       if (dense) {
@@ -980,6 +1289,7 @@ struct BigArgs {
   PlanInfo* info;
   DenseDev dd;
   int dense;
+  const uint32_t* vreal;  // real context of every virtual one (null: no split contexts)
 };
 
 struct ListBuf {
@@ -1209,7 +1519,7 @@ __global__ void __launch_bounds__(256) k_big_write(BigArgs a, ListBuf fin, const
       unsigned long long cnt = fin.cnt[base + e];
       for (uint64_t f = e + 1; f < len && fin.pc[base + f] == p && fin.stall[base + f] == s; ++f) cnt += fin.cnt[base + f];
       uint64_t o = big_out[b] + slot0 + done + ex;
-      out.ctx[o] = c;
+      out.ctx[o] = a.vreal ? a.vreal[c] : c;
       out.pc[o] = p;
       out.stall[o] = s;
       out.count[o] = cnt;
@@ -1258,7 +1568,7 @@ extern "C" hpa_status hpa_attribute(hpa_ctx* ctx, const hpa_structure_map* map, 
     }
     StageTimer tm(ctx, s);
     // --- scan ctx, plan ---
-    tm.begin("scan_plan");
+    tm.begin("scan_ctx");
     const uint64_t run_cap = std::min<uint64_t>(std::max<uint64_t>(n / 8, 1024), 1ull << 24);
     DBuf d_info(ctx, sizeof(PlanInfo), s);
     DBuf d_hist(ctx, (uint64_t)C * 8, s);
@@ -1272,30 +1582,86 @@ extern "C" hpa_status hpa_attribute(hpa_ctx* ctx, const hpa_structure_map* map, 
                                              run_cap, d_info.as<PlanInfo>());
       HPA_HIP(hipGetLastError());
     }
-    // the run/scatter decision needs the run count: read it with the plan
-    DBuf d_sbase(ctx, ((uint64_t)C + 1) * 8, s);
-    DBuf d_rbase(ctx, ((uint64_t)C + 1) * 8, s);
-    DBuf d_ubeg(ctx, ((uint64_t)C + 1) * 4, s);
-    DBuf d_ubig(ctx, ((uint64_t)C + 1) * 4, s);
-    DBuf d_bctx(ctx, ((uint64_t)C + 1) * 4, s);
-    DBuf d_bsb(ctx, ((uint64_t)C + 1) * 8, s);
-    DBuf d_bch(ctx, ((uint64_t)C + 1) * 8, s);
-    k_plan<<<1, PLAN_BLOCK, 0, s>>>(d_hist.as<unsigned long long>(), C, d_sbase.as<uint64_t>(),
-                                    d_rbase.as<uint64_t>(), d_ubeg.as<uint32_t>(), d_ubig.as<int32_t>(),
-                                    d_bctx.as<uint32_t>(), d_bsb.as<uint64_t>(), d_bch.as<uint64_t>(),
-                                    d_info.as<PlanInfo>());
+    // the run/scatter decision needs the run count, the split the number of
+    // contexts over T samples
+    DBuf d_bigof(ctx, (uint64_t)C * 4, s);
+    k_big_index<<<grid_for(C, 256, ctx->n_cu * 8), 256, 0, s>>>(d_hist.as<unsigned long long>(), C,
+                                                                  d_bigof.as<int32_t>(), d_info.as<PlanInfo>());
     HPA_HIP(hipGetLastError());
-    tm.end(n, 0);
     PlanInfo info;
     HPA_HIP(hipMemcpyAsync(&info, d_info.p, sizeof(info), hipMemcpyDeviceToHost, s));
     HPA_HIP(hipStreamSynchronize(s));
     if (info.err & ERR_CTX) fail(HPA_E_INVAL, "a sample has ctx >= n_ctx");
     const bool scattered = info.n_runs > run_cap;
-    // --- order samples by context ---
-    DBuf d_cur(ctx, (uint64_t)C * 8, s);
-    HPA_HIP(hipMemsetAsync(d_cur.p, 0, (uint64_t)C * 8, s));
-    DBuf d_grp, d_spc, d_sst, d_sw;
+    tm.end(n, 0);
     const bool weighted = smp->weight != nullptr;
+    // --- split of big contexts by coordinate range (run list and dense map only) ---
+    const bool split = !scattered && map->dense && info.n_bigall > 0;
+    uint32_t CV = C;  // contexts after the split
+    DBuf d_vhist, d_vreal, d_vgrp, d_vbase, d_vsolo, d_bhist, d_bflag, d_partof, d_psum, d_nparts;
+    uint32_t bshift = 0;
+    const DenseDev dd{map->win_lo.as<uint64_t>(), map->win_hi.as<uint64_t>(), map->win_d.as<uint64_t>(),
+                      map->scope_of.as<uint32_t>(), map->n_win, map->dense_tz};
+    if (split) {
+      tm.begin("split_plan");
+      const uint32_t NBIG = info.n_bigall;
+      // every coordinate D < n_dense has its bucket D >> bshift below NB
+      while (((map->n_dense - 1) >> bshift) >= (uint64_t)NB) ++bshift;
+      d_bhist = DBuf(ctx, (uint64_t)NBIG * NB * 4, s);
+      d_bflag = DBuf(ctx, (uint64_t)NBIG * 4, s);
+      d_partof = DBuf(ctx, (uint64_t)NBIG * NB * 4, s);
+      d_psum = DBuf(ctx, (uint64_t)NBIG * NB * 4, s);
+      d_nparts = DBuf(ctx, (uint64_t)NBIG * 4, s);
+      HPA_HIP(hipMemsetAsync(d_bhist.p, 0, d_bhist.bytes, s));
+      HPA_HIP(hipMemsetAsync(d_bflag.p, 0, d_bflag.bytes, s));
+      HPA_HIP(hipMemsetAsync(d_psum.p, 0, d_psum.bytes, s));
+      k_big_hist<<<(unsigned)std::min<uint64_t>(std::max<uint64_t>(info.n_runs, 1), (uint64_t)ctx->n_cu * 8),
+                   SPLIT_BLOCK, 0, s>>>(d_runs.as<Run>(), info.n_runs, d_bigof.as<int32_t>(), smp->pc, dd, bshift,
+                                        d_bhist.as<uint32_t>(), d_bflag.as<uint32_t>());
+      k_big_parts<<<(NBIG + 3) / 4, 256, 0, s>>>(d_bhist.as<uint32_t>(), d_bflag.as<uint32_t>(), NBIG,
+                                                d_partof.as<uint32_t>(), d_psum.as<uint32_t>(),
+                                                d_nparts.as<uint32_t>());
+      // at most NB parts per big context
+      const uint64_t cv_cap = (uint64_t)C + (uint64_t)NBIG * (NB - 1);
+      d_vhist = DBuf(ctx, cv_cap * 8, s);
+      d_vreal = DBuf(ctx, cv_cap * 4, s);
+      d_vgrp = DBuf(ctx, cv_cap * 4, s);
+      d_vbase = DBuf(ctx, ((uint64_t)C + 1) * 4, s);
+      d_vsolo = DBuf(ctx, (uint64_t)C * 4, s);
+      k_virtual<<<1, PLAN_BLOCK, 0, s>>>(d_hist.as<unsigned long long>(), C, d_bigof.as<int32_t>(),
+                                         d_nparts.as<uint32_t>(), d_psum.as<uint32_t>(),
+                                         d_vhist.as<unsigned long long>(), d_vreal.as<uint32_t>(),
+                                         d_vgrp.as<uint32_t>(), d_vbase.as<uint32_t>(), d_vsolo.as<uint32_t>(),
+                                         d_info.as<PlanInfo>());
+      HPA_HIP(hipGetLastError());
+      HPA_HIP(hipMemcpyAsync(&info, d_info.p, sizeof(info), hipMemcpyDeviceToHost, s));
+      HPA_HIP(hipStreamSynchronize(s));
+      CV = info.n_virtual;
+      tm.end(info.split_samples, info.n_parts);
+    }
+    // --- plan over the (virtual) contexts ---
+    tm.begin("plan");
+    DBuf d_sbase(ctx, ((uint64_t)CV + 1) * 8, s);
+    DBuf d_rbase(ctx, ((uint64_t)CV + 1) * 8, s);
+    DBuf d_ubeg(ctx, ((uint64_t)CV + 1) * 4, s);
+    DBuf d_ubig(ctx, ((uint64_t)CV + 1) * 4, s);
+    DBuf d_bctx(ctx, ((uint64_t)CV + 1) * 4, s);
+    DBuf d_bsb(ctx, ((uint64_t)CV + 1) * 8, s);
+    DBuf d_bch(ctx, ((uint64_t)CV + 1) * 8, s);
+    k_plan<<<1, PLAN_BLOCK, 0, s>>>(split ? d_vhist.as<unsigned long long>() : d_hist.as<unsigned long long>(), CV,
+                                    split ? d_vgrp.as<uint32_t>() : nullptr, d_sbase.as<uint64_t>(),
+                                    d_rbase.as<uint64_t>(), d_ubeg.as<uint32_t>(), d_ubig.as<int32_t>(),
+                                    d_bctx.as<uint32_t>(), d_bsb.as<uint64_t>(), d_bch.as<uint64_t>(),
+                                    d_info.as<PlanInfo>());
+    HPA_HIP(hipGetLastError());
+    HPA_HIP(hipMemcpyAsync(&info, d_info.p, sizeof(info), hipMemcpyDeviceToHost, s));
+    HPA_HIP(hipStreamSynchronize(s));
+    tm.end(CV, info.n_units);
+    const uint32_t* vreal = split ? d_vreal.as<uint32_t>() : nullptr;
+    // --- order samples by context ---
+    DBuf d_cur(ctx, (uint64_t)CV * 8, s);
+    HPA_HIP(hipMemsetAsync(d_cur.p, 0, (uint64_t)CV * 8, s));
+    DBuf d_grp, d_spc, d_sst, d_sw, d_tpc, d_tst, d_tw;
     const uint64_t* src_pc = smp->pc;
     const uint8_t* src_st = smp->stall;
     const uint32_t* src_w = smp->weight;
@@ -1303,9 +1669,22 @@ extern "C" hpa_status hpa_attribute(hpa_ctx* ctx, const hpa_structure_map* map, 
     if (!scattered) {
       d_grp = DBuf(ctx, std::max<uint64_t>(info.n_runs, 1) * sizeof(Run), s);
       k_group_runs<<<grid_for(info.n_runs, 256, ctx->n_cu * 8), 256, 0, s>>>(
-          d_runs.as<Run>(), info.n_runs, d_sbase.as<uint64_t>(), d_rbase.as<uint64_t>(),
-          d_cur.as<unsigned long long>(), d_grp.as<Run>());
+          d_runs.as<Run>(), info.n_runs, split ? d_vsolo.as<uint32_t>() : nullptr, d_sbase.as<uint64_t>(),
+          d_rbase.as<uint64_t>(), d_cur.as<unsigned long long>(), d_grp.as<Run>());
       HPA_HIP(hipGetLastError());
+      if (split) {
+        // the samples of split contexts into part order, at the parts' flat positions
+        d_tpc = DBuf(ctx, n * 8, s);
+        d_tst = DBuf(ctx, n, s);
+        if (weighted) d_tw = DBuf(ctx, n * 4, s);
+        k_big_scatter<<<(unsigned)std::min<uint64_t>(std::max<uint64_t>(info.n_runs, 1), (uint64_t)ctx->n_cu * 8),
+                        SPLIT_BLOCK, 0, s>>>(
+            d_runs.as<Run>(), info.n_runs, d_bigof.as<int32_t>(), d_nparts.as<uint32_t>(), d_partof.as<uint32_t>(),
+            d_vbase.as<uint32_t>(), d_sbase.as<uint64_t>(), d_cur.as<unsigned long long>(), smp->pc, smp->stall,
+            smp->weight, dd, bshift, d_tpc.as<uint64_t>(), d_tst.as<uint8_t>(),
+            weighted ? d_tw.as<uint32_t>() : nullptr, &d_info.as<PlanInfo>()->err);
+        HPA_HIP(hipGetLastError());
+      }
     } else {
       d_spc = DBuf(ctx, n * 8, s);
       d_sst = DBuf(ctx, n, s);
@@ -1330,10 +1709,9 @@ extern "C" hpa_status hpa_attribute(hpa_ctx* ctx, const hpa_structure_map* map, 
     BigArgs ba{src_pc, src_st, src_w, d_sbase.as<uint64_t>(), d_rbase.as<uint64_t>(), d_grp.as<Run>(),
                d_bctx.as<uint32_t>(), d_bsb.as<uint64_t>(), d_bch.as<uint64_t>(), info.n_big, info.n_chunks,
                d_info.as<PlanInfo>()};
-    const DenseDev dd{map->win_lo.as<uint64_t>(), map->win_hi.as<uint64_t>(), map->win_d.as<uint64_t>(),
-                      map->scope_of.as<uint32_t>(), map->n_win, map->dense_tz};
     ba.dd = dd;
     ba.dense = map->dense ? 1 : 0;
+    ba.vreal = vreal;
     if (info.n_big) {
       tm.begin("big_sort");
       const uint64_t bs = info.big_samples;
@@ -1393,19 +1771,29 @@ extern "C" hpa_status hpa_attribute(hpa_ctx* ctx, const hpa_structure_map* map, 
                 d_ubeg.as<uint32_t>(), d_ubig.as<int32_t>(), d_info.as<PlanInfo>(), NU, C, dd,
                 map->dense ? 1 : 0, d_meta.as<UnitMeta>(), d_ucnt.as<uint32_t>(), d_skey.as<uint32_t>(),
                 d_shi.as<uint32_t>(), weighted ? nullptr : d_scnt.as<uint32_t>(),
-                weighted ? d_scnt.as<unsigned long long>() : nullptr};
+                weighted ? d_scnt.as<unsigned long long>() : nullptr, UNIT_PLAIN, vreal};
     tm.begin("units");
-#define HPA_UNITS(W, S)                                  \
-  do {                                                   \
-    k_units32<W, S, false><<<NU, UBLOCK, 0, s>>>(ua);    \
-    k_units32<W, S, true><<<NU, UBLOCK, 0, s>>>(ua);     \
+#define HPA_UNITS(W, S, A)                                \
+  do {                                                    \
+    k_units32<W, S, false><<<NU, UBLOCK, 0, s>>>(A);      \
+    k_units32<W, S, true><<<NU, UBLOCK, 0, s>>>(A);       \
   } while (0)
     if (weighted) {
-      if (scattered) HPA_UNITS(true, true);
-      else HPA_UNITS(true, false);
+      if (scattered) HPA_UNITS(true, true, ua);
+      else HPA_UNITS(true, false, ua);
     } else {
-      if (scattered) HPA_UNITS(false, true);
-      else HPA_UNITS(false, false);
+      if (scattered) HPA_UNITS(false, true, ua);
+      else HPA_UNITS(false, false, ua);
+    }
+    if (split) {
+      // units of parts read the scattered copies at their flat positions
+      UnitArgs pa = ua;
+      pa.pc = d_tpc.as<uint64_t>();
+      pa.stall = d_tst.as<uint8_t>();
+      pa.weight = weighted ? d_tw.as<uint32_t>() : nullptr;
+      pa.kind = UNIT_PART;
+      if (weighted) HPA_UNITS(true, true, pa);
+      else HPA_UNITS(false, true, pa);
     }
 #undef HPA_UNITS
     HPA_HIP(hipGetLastError());
@@ -1414,8 +1802,9 @@ extern "C" hpa_status hpa_attribute(hpa_ctx* ctx, const hpa_structure_map* map, 
     k_unit_offsets<<<1, 1024, 0, s>>>(d_meta.as<UnitMeta>(), d_ubig.as<int32_t>(), d_bigU.as<uint64_t>(), NU, C,
                                       d_uoff.as<uint64_t>(), A->ctx_offsets.as<uint64_t>(), d_info.as<PlanInfo>());
     k_ctx_offsets<<<(NU + 3) / 4, 256, 0, s>>>(d_ubeg.as<uint32_t>(), d_ubig.as<int32_t>(), d_ucnt.as<uint32_t>(),
-                                              d_uoff.as<uint64_t>(), NU, A->ctx_offsets.as<uint64_t>(),
-                                              d_bigout.as<uint64_t>());
+                                              d_uoff.as<uint64_t>(), NU, vreal,
+                                              split ? d_vbase.as<uint32_t>() : nullptr,
+                                              A->ctx_offsets.as<uint64_t>(), d_bigout.as<uint64_t>());
     k_units_write<<<NU, WBLOCK, 0, s>>>(ua, d_uoff.as<uint64_t>(), md, od, weighted ? 1 : 0);
     HPA_HIP(hipGetLastError());
     tm.end();
@@ -1436,6 +1825,7 @@ extern "C" hpa_status hpa_attribute(hpa_ctx* ctx, const hpa_structure_map* map, 
     HPA_HIP(hipMemcpyAsync(&info, d_info.p, sizeof(info), hipMemcpyDeviceToHost, s));
     HPA_HIP(hipStreamSynchronize(s));
     if (info.err & ERR_STALL) fail(HPA_E_INVAL, "a sample has stall >= 16");
+    if (info.err & ERR_SPLIT) fail(HPA_E_DEVICE, "internal error: a split context's samples missed their parts");
     if (info.err & ERR_WIDE) fail(HPA_E_UNSUPPORTED, "the PCs of one context span more than 2^56 bytes");
     A->n_keys = info.total_keys;
     if (tm.on()) {

@@ -14,24 +14,62 @@ void set_last_error(const std::string& msg) { g_last_error = msg; }
 
 void fail(hpa_status s, const std::string& msg) { throw Error{s, msg}; }
 
-void* dalloc(hpa_ctx* ctx, size_t bytes, hipStream_t s) {
+namespace {
+
+// Release every cached block to HIP (blocks may still be in use by work in
+// flight, so the device is drained first).
+void drop_cache(hpa_ctx* ctx) {
+  if (ctx->cache.empty()) return;
+  (void)hipDeviceSynchronize();
+  for (auto& kv : ctx->cache) (void)hipFreeAsync(kv.second.p, nullptr);
+  (void)hipDeviceSynchronize();
+  ctx->cache.clear();
+}
+
+}  // namespace
+
+void* dalloc(hpa_ctx* ctx, size_t bytes, hipStream_t s, size_t* cap) {
   void* p = nullptr;
   if (ctx->custom) {
     p = ctx->alloc.alloc(bytes, s, ctx->alloc.user);
     if (!p) fail(HPA_E_NOMEM, "allocator returned NULL for " + std::to_string(bytes) + " bytes");
+    *cap = bytes;
     return p;
   }
-  hipError_t e = hipMallocAsync(&p, bytes, s);
+  // a cached block released on this stream, at most twice the request (plus
+  // 1 MiB) so that small requests do not pin large blocks
+  std::lock_guard<std::mutex> lk(ctx->cache_mu);
+  const size_t limit = bytes * 2 + (1u << 20);
+  for (auto it = ctx->cache.lower_bound(bytes); it != ctx->cache.end() && it->first <= limit; ++it) {
+    if (it->second.stream != s) continue;
+    p = it->second.p;
+    *cap = it->first;
+    ctx->cache.erase(it);
+    return p;
+  }
+  // new blocks are rounded up to 1 MiB so that similar sizes share them
+  const size_t want = bytes > (1u << 20) ? (bytes + (1u << 20) - 1) & ~(size_t)((1u << 20) - 1) : bytes;
+  hipError_t e = hipMallocAsync(&p, want, s);
+  if (e == hipErrorOutOfMemory && !ctx->cache.empty()) {
+    (void)hipGetLastError();
+    drop_cache(ctx);
+    e = hipMallocAsync(&p, want, s);
+  }
   if (e == hipErrorOutOfMemory || (e == hipSuccess && !p))
     fail(HPA_E_NOMEM, "device allocation of " + std::to_string(bytes) + " bytes failed");
   if (e != hipSuccess) fail(HPA_E_DEVICE, std::string("hipMallocAsync: ") + hipGetErrorString(e));
+  *cap = want;
   return p;
 }
 
-void dfree(hpa_ctx* ctx, void* p, hipStream_t s) {
+void dfree(hpa_ctx* ctx, void* p, size_t cap, hipStream_t s) {
   if (!p) return;
-  if (ctx->custom) ctx->alloc.free(p, s, ctx->alloc.user);
-  else (void)hipFreeAsync(p, s);
+  if (ctx->custom) {
+    ctx->alloc.free(p, s, ctx->alloc.user);
+    return;
+  }
+  std::lock_guard<std::mutex> lk(ctx->cache_mu);
+  ctx->cache.emplace(cap, hpa_ctx::Cached{p, s});
 }
 
 }  // namespace hpa
@@ -62,6 +100,16 @@ extern "C" hpa_status hpa_ctx_create(int device, const hpa_allocator* alloc, hpa
     }
     *out = c;
   });
+}
+
+hpa_ctx::~hpa_ctx() {
+  if (custom) return;
+  int prev = 0;
+  if (hipGetDevice(&prev) != hipSuccess) prev = device;
+  (void)hipSetDevice(device);
+  std::lock_guard<std::mutex> lk(cache_mu);
+  drop_cache(this);
+  (void)hipSetDevice(prev);
 }
 
 extern "C" void hpa_ctx_destroy(hpa_ctx* ctx) { delete ctx; }

@@ -6,6 +6,8 @@
 #include <algorithm>
 #include <cstdint>
 #include <cstring>
+#include <map>
+#include <mutex>
 #include <string>
 #include <utility>
 #include <vector>
@@ -60,35 +62,50 @@ struct hpa_ctx {
   int n_cu = 256;
   bool timing = false;
   std::vector<hpa_stage_time> stages;  // accumulated stage timings
+  // Device blocks released by the library's buffers, by size, with the
+  // stream they were released on.  A later allocation on the same stream
+  // reuses one (stream order makes that safe); the blocks go back to HIP when
+  // the context is destroyed, or when an allocation would otherwise fail.
+  struct Cached {
+    void* p;
+    hipStream_t stream;
+  };
+  std::mutex cache_mu;
+  std::multimap<size_t, Cached> cache;
+  ~hpa_ctx();
 };
 
 namespace hpa {
 
-void* dalloc(hpa_ctx* ctx, size_t bytes, hipStream_t s);
-void dfree(hpa_ctx* ctx, void* p, hipStream_t s);
+// dalloc returns a block of at least `bytes` and its capacity in *cap; dfree
+// takes the block back with that capacity.
+void* dalloc(hpa_ctx* ctx, size_t bytes, hipStream_t s, size_t* cap);
+void dfree(hpa_ctx* ctx, void* p, size_t cap, hipStream_t s);
 
 // Stream-ordered device buffer owned by a scope or a handle.
 struct DBuf {
   hpa_ctx* ctx = nullptr;
   hipStream_t stream = nullptr;
   void* p = nullptr;
-  size_t bytes = 0;
+  size_t bytes = 0;  // requested size
+  size_t cap = 0;    // size of the block
   DBuf() = default;
-  DBuf(hpa_ctx* c, size_t n, hipStream_t s) : ctx(c), stream(s), bytes(n) { p = n ? dalloc(c, n, s) : nullptr; }
+  DBuf(hpa_ctx* c, size_t n, hipStream_t s) : ctx(c), stream(s), bytes(n) { p = n ? dalloc(c, n, s, &cap) : nullptr; }
   DBuf(const DBuf&) = delete;
   DBuf& operator=(const DBuf&) = delete;
   DBuf(DBuf&& o) noexcept { *this = std::move(o); }
   DBuf& operator=(DBuf&& o) noexcept {
     release();
-    ctx = o.ctx; stream = o.stream; p = o.p; bytes = o.bytes;
-    o.p = nullptr; o.bytes = 0;
+    ctx = o.ctx; stream = o.stream; p = o.p; bytes = o.bytes; cap = o.cap;
+    o.p = nullptr; o.bytes = 0; o.cap = 0;
     return *this;
   }
   ~DBuf() { release(); }
   void release() {
-    if (p) dfree(ctx, p, stream);
+    if (p) dfree(ctx, p, cap, stream);
     p = nullptr;
     bytes = 0;
+    cap = 0;
   }
   template <class T>
   T* as() const { return static_cast<T*>(p); }

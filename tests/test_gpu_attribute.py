@@ -118,6 +118,34 @@ def test_attribute_small(hpa, hctx, seed, kw):
     assert_attribution_equal(a.numpy(), oa, f"small{seed}{kw}")
 
 
+@pytest.mark.parametrize("seed,kw,fallback", [
+    # contexts of ~37k samples: most are cut into parts by coordinate range,
+    # a few keep the chunk path (one coordinate bucket over 16,384 samples)
+    (8, dict(n_ctx=8), True),
+    (9, dict(n_ctx=12, weighted=True), None),
+    (11, dict(n_ctx=20, seg_mean=300.0), None),
+    # every context too concentrated to split: the chunk path only
+    (10, dict(n_ctx=6, n_samples=600_000), True),
+])
+def test_attribute_split_big_contexts(hpa, hctx, seed, kw, fallback):
+    kw = dict(kw)
+    w = small_config(seed, n_samples=kw.pop("n_samples", 300_000), **kw)
+    hctx.set_timing(True)
+    try:
+        m, om, a, oa = _run(hpa, hctx, w)
+        stages = hctx.timing()
+    finally:
+        hctx.set_timing(False)
+    assert_attribution_equal(a.numpy(), oa, f"split{seed}{kw}")
+    split_in = stages.get("split_plan", {}).get("items_in", 0)
+    if seed == 10:
+        assert split_in == 0
+    else:
+        assert split_in > 0, "no context was split"
+    if fallback:
+        assert stages.get("big_sort", {}).get("items_in", 0) > 0, "no context kept the chunk path"
+
+
 def test_attribute_config1(hpa, hctx):
     w = config1()
     m, om, a, oa = _run(hpa, hctx, w)
