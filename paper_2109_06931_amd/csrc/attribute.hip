@@ -98,70 +98,51 @@ __device__ inline void scan_tile_heads(const uint32_t* __restrict__ ctx, uint64_
   }
 }
 
+// One pass over the context array: every tile's run heads, one reservation
+// in the run list per tile (runs are grouped by context later, so their order
+// here is free), the runs and the per-context histogram.  A run never crosses
+// a tile boundary.
 __global__ void __launch_bounds__(SCAN_BLOCK)
 k_scan_ctx(const uint32_t* __restrict__ ctx, uint64_t n, uint32_t n_ctx, unsigned long long* __restrict__ hist,
            Run* __restrict__ runs, uint64_t run_cap, PlanInfo* __restrict__ info) {
+  constexpr int NWS = SCAN_BLOCK / WAVE;
+  static_assert(SCAN_ITEMS * NWS == WAVE, "one lane per (item, wave) head count");
   __shared__ uint32_t s_ctx[SCAN_TILE];
   __shared__ uint32_t s_head[SCAN_TILE];
-  __shared__ uint32_t s_wcnt[SCAN_ITEMS][SCAN_BLOCK / WAVE];
+  __shared__ uint32_t s_wcnt[SCAN_ITEMS * NWS];
   __shared__ unsigned long long s_base;
   __shared__ uint32_t s_R;
   const int tid = threadIdx.x;
   const uint64_t n_tiles = (n + SCAN_TILE - 1) / SCAN_TILE;
-  const uint64_t per = (n_tiles + gridDim.x - 1) / gridDim.x;
-  const uint64_t tb = (uint64_t)blockIdx.x * per, te = min(n_tiles, tb + per);
-  if (tb >= te) return;
-  // 1. count the heads of the range
-  unsigned long long mine = 0;
-  for (uint64_t tile = tb; tile < te; ++tile) {
+  for (uint64_t tile = blockIdx.x; tile < n_tiles; tile += gridDim.x) {
     const uint64_t t0 = tile * SCAN_TILE;
     const int cnt = (int)min((uint64_t)SCAN_TILE, n - t0);
     uint64_t mask[SCAN_ITEMS];
     scan_tile_heads(ctx, t0, cnt, s_ctx, mask);
     if (lane_id() == 0)
 #pragma unroll
-      for (int i = 0; i < SCAN_ITEMS; ++i) mine += (unsigned long long)__popcll(mask[i]);
+      for (int i = 0; i < SCAN_ITEMS; ++i) s_wcnt[i * NWS + wave_id()] = (uint32_t)__popcll(mask[i]);
     __syncthreads();
-  }
-  if (lane_id() == 0) s_wcnt[0][wave_id()] = (uint32_t)mine;
-  __syncthreads();
-  if (tid == 0) {
-    unsigned long long tot = 0;
-    for (int w = 0; w < SCAN_BLOCK / WAVE; ++w) tot += s_wcnt[0][w];
-    s_base = atomicAdd(&info->n_runs, tot);
-  }
-  __syncthreads();
-  unsigned long long base = s_base;
-  // 2. write the runs
-  for (uint64_t tile = tb; tile < te; ++tile) {
-    const uint64_t t0 = tile * SCAN_TILE;
-    const int cnt = (int)min((uint64_t)SCAN_TILE, n - t0);
-    uint64_t mask[SCAN_ITEMS];
-    scan_tile_heads(ctx, t0, cnt, s_ctx, mask);
     // rank among the tile's heads = prefix over (item, wave, lane)
-    if (lane_id() == 0)
-#pragma unroll
-      for (int i = 0; i < SCAN_ITEMS; ++i) s_wcnt[i][wave_id()] = (uint32_t)__popcll(mask[i]);
-    __syncthreads();
-    if (tid == 0) {
-      uint32_t run = 0;
-      for (int i = 0; i < SCAN_ITEMS; ++i)
-        for (int w = 0; w < SCAN_BLOCK / WAVE; ++w) {
-          const uint32_t t = s_wcnt[i][w];
-          s_wcnt[i][w] = run;
-          run += t;
-        }
-      s_R = run;
+    if (tid < WAVE) {
+      const uint32_t a = s_wcnt[tid];
+      const uint32_t inc = wave_incl_scan_u32(a);
+      s_wcnt[tid] = inc - a;
+      if (tid == WAVE - 1) {
+        s_R = inc;
+        s_base = atomicAdd(&info->n_runs, (unsigned long long)inc);
+      }
     }
     __syncthreads();
 #pragma unroll
     for (int i = 0; i < SCAN_ITEMS; ++i) {
       const int j = i * SCAN_BLOCK + tid;
       const uint64_t below = mask[i] & ((1ull << lane_id()) - 1);
-      if ((mask[i] >> lane_id()) & 1) s_head[s_wcnt[i][wave_id()] + (uint32_t)__popcll(below)] = (uint32_t)j;
+      if ((mask[i] >> lane_id()) & 1) s_head[s_wcnt[i * NWS + wave_id()] + (uint32_t)__popcll(below)] = (uint32_t)j;
     }
     __syncthreads();
     const uint32_t R = s_R;
+    const unsigned long long base = s_base;
     for (uint32_t k = tid; k < R; k += SCAN_BLOCK) {
       const uint32_t p = s_head[k];
       const uint32_t len = (k + 1 < R ? s_head[k + 1] : (uint32_t)cnt) - p;
@@ -174,7 +155,6 @@ k_scan_ctx(const uint32_t* __restrict__ ctx, uint64_t n, uint32_t n_ctx, unsigne
       const uint64_t g = base + k;
       if (g < run_cap) runs[g] = Run{t0 + p, 0, len, c};
     }
-    base += R;
     __syncthreads();
   }
 }
@@ -195,113 +175,150 @@ enum : uint8_t { KIND_S = 0, KIND_M = 1, KIND_B = 2 };
 
 __device__ inline uint8_t ctx_kind(uint64_t n) { return n <= (uint64_t)UHALF ? KIND_S : (n <= (uint64_t)UT ? KIND_M : KIND_B); }
 
-__global__ void __launch_bounds__(PLAN_BLOCK)
-k_plan(const unsigned long long* __restrict__ hist, uint32_t n_ctx, const uint32_t* __restrict__ grp,
-       uint64_t* __restrict__ sbase, uint64_t* __restrict__ rbase, uint32_t* __restrict__ unit_begin,
-       int32_t* __restrict__ unit_big, uint32_t* __restrict__ big_ctx, uint64_t* __restrict__ big_sbase,
-       uint64_t* __restrict__ big_chunk, PlanInfo* __restrict__ info) {
-  __shared__ unsigned long long s_tmp[PLAN_BLOCK / WAVE + 1];
-  __shared__ uint32_t s_max;
-  const int tid = threadIdx.x;
-  if (tid == 0) s_max = 0;
-  // running totals carried across blocks of contexts
-  unsigned long long c_s = 0, c_r = 0, c_ps = 0, c_unit = 0, c_big = 0, c_chunk = 0, c_bs = 0;
-  uint32_t maxch = 0;
-  for (uint32_t b0 = 0; b0 < n_ctx; b0 += PLAN_BLOCK * PLAN_ITEMS) {
-    const uint32_t c0 = b0 + (uint32_t)tid * PLAN_ITEMS;
-    uint64_t nn[PLAN_ITEMS], rr[PLAN_ITEMS];
-    unsigned long long ls = 0, lr = 0, lps = 0, lbig = 0, lch = 0, lbs = 0;
-#pragma unroll
-    for (int i = 0; i < PLAN_ITEMS; ++i) {
-      uint32_t c = c0 + i;
-      unsigned long long h = c < n_ctx ? hist[c] : 0ull;
-      nn[i] = h & M40;
-      rr[i] = h >> 40;
-      ls += nn[i];
-      lr += rr[i];
-      uint8_t k = ctx_kind(nn[i]);
-      if (k == KIND_S) lps += nn[i];
-      if (k == KIND_B) { lbig += 1; lch += (nn[i] + UT - 1) / UT; lbs += nn[i]; }
-    }
-    const uint64_t n_before = (c0 > 0 && c0 - 1 < n_ctx) ? (hist[c0 - 1] & M40) : 0;
-    unsigned long long t;
-    const unsigned long long ps = block_excl_scan<PLAN_BLOCK>(ls, s_tmp, &t); const unsigned long long ps_tot = t;
-    const unsigned long long pr = block_excl_scan<PLAN_BLOCK>(lr, s_tmp, &t); const unsigned long long pr_tot = t;
-    const unsigned long long pp = block_excl_scan<PLAN_BLOCK>(lps, s_tmp, &t); const unsigned long long pp_tot = t;
-    const unsigned long long pb = block_excl_scan<PLAN_BLOCK>(lbig, s_tmp, &t); const unsigned long long pb_tot = t;
-    const unsigned long long pc = block_excl_scan<PLAN_BLOCK>(lch, s_tmp, &t); const unsigned long long pc_tot = t;
-    const unsigned long long pbs = block_excl_scan<PLAN_BLOCK>(lbs, s_tmp, &t); const unsigned long long pbs_tot = t;
-    // unit starts: a new unit at every context that is not packable, after one,
-    // every MAXC contexts, and where the packable prefix crosses a multiple of UHALF
-    uint8_t starts[PLAN_ITEMS];
-    unsigned long long lunits = 0;
-    {
-      uint64_t ps_c = c_ps + pp;  // packable samples before context c
-      uint64_t n_prev = n_before;
-#pragma unroll
-      for (int i = 0; i < PLAN_ITEMS; ++i) {
-        uint32_t c = c0 + i;
-        bool st = false;
-        if (c < n_ctx) {
-          uint8_t k = ctx_kind(nn[i]);
-          uint8_t kp = c > 0 ? ctx_kind(n_prev) : KIND_S;
-          uint64_t ps_prev = ps_c - (c > 0 && kp == KIND_S ? n_prev : 0);
-          st = c == 0 || k != KIND_S || kp != KIND_S || (c % MAXC) == 0 || (ps_c / UHALF) != (ps_prev / UHALF) ||
-               (grp && grp[c] != grp[c - 1]);
-          if (k == KIND_S) ps_c += nn[i];
-          n_prev = nn[i];
-        }
-        starts[i] = st;
-        lunits += st;
-      }
-    }
-    const unsigned long long pu = block_excl_scan<PLAN_BLOCK>(lunits, s_tmp, &t);
-    const unsigned long long pu_tot = t;
-    {
-      unsigned long long sv = c_s + ps, r = c_r + pr, u = c_unit + pu, bg = c_big + pb, ch = c_chunk + pc,
-                         bs = c_bs + pbs;
-#pragma unroll
-      for (int i = 0; i < PLAN_ITEMS; ++i) {
-        uint32_t c = c0 + i;
-        if (c >= n_ctx) continue;
-        sbase[c] = sv;
-        rbase[c] = r;
-        const uint8_t k = ctx_kind(nn[i]);
-        if (starts[i]) {
-          unit_begin[u] = c;
-          unit_big[u] = k == KIND_B ? (int32_t)bg : (grp && grp[c] != NONE32 ? UNIT_PART : UNIT_PLAIN);
-          ++u;
-        }
-        if (k == KIND_B) {
-          uint64_t nk = (nn[i] + UT - 1) / UT;
-          big_ctx[bg] = c;
-          big_sbase[bg] = bs;
-          big_chunk[bg] = ch;
-          maxch = max(maxch, (uint32_t)nk);
-          ++bg;
-          ch += nk;
-          bs += nn[i];
-        }
-        sv += nn[i];
-        r += rr[i];
-      }
-    }
-    c_s += ps_tot; c_r += pr_tot; c_ps += pp_tot; c_big += pb_tot; c_chunk += pc_tot; c_unit += pu_tot;
-    c_bs += pbs_tot;
+// The plan runs as five launches over tiles of PLAN_BLOCK contexts, one per
+// thread: tile sums of the per-context quantities; their exclusive scan (one
+// workgroup); per context the bases and the big-context lists, plus the unit
+// start flags and their count per tile; the scan of those counts; the unit
+// list.  A unit starts at context c when c is the first context, when c or
+// c - 1 is not packable (over T/2 samples), every MAXC contexts, where the
+// running count of packable samples crosses a multiple of T/2 between c - 1
+// and c, and where the group changes.
+struct PlanVals {
+  unsigned long long n, r, ps, big, ch, bs;  // samples, runs, packable samples, big contexts, chunks, big samples
+};
+
+__device__ inline PlanVals plan_vals(const unsigned long long* hist, uint32_t n_ctx, uint32_t c) {
+  PlanVals v{0, 0, 0, 0, 0, 0};
+  if (c >= n_ctx) return v;
+  const unsigned long long h = hist[c];
+  v.n = h & M40;
+  v.r = h >> 40;
+  const uint8_t k = ctx_kind(v.n);
+  if (k == KIND_S) v.ps = v.n;
+  if (k == KIND_B) {
+    v.big = 1;
+    v.ch = (v.n + UT - 1) / UT;
+    v.bs = v.n;
   }
-  atomicMax(&s_max, maxch);
+  return v;
+}
+
+constexpr int PLAN_NV = 6;
+
+__global__ void __launch_bounds__(PLAN_BLOCK) k_plan_sums(const unsigned long long* __restrict__ hist, uint32_t n_ctx,
+                                                          unsigned long long* __restrict__ tile_sum,
+                                                          PlanInfo* __restrict__ info) {
+  __shared__ unsigned long long s_red[PLAN_NV][PLAN_BLOCK / WAVE];
+  const uint32_t c = blockIdx.x * PLAN_BLOCK + threadIdx.x;
+  const PlanVals v = plan_vals(hist, n_ctx, c);
+  const unsigned long long x[PLAN_NV] = {v.n, v.r, v.ps, v.big, v.ch, v.bs};
+#pragma unroll
+  for (int k = 0; k < PLAN_NV; ++k) {
+    const unsigned long long t = wave_sum(x[k]);
+    if (lane_id() == 0) s_red[k][wave_id()] = t;
+  }
+  if (v.big) atomicMax(&info->max_chunks, (uint32_t)v.ch);
   __syncthreads();
-  if (tid == 0) {
-    sbase[n_ctx] = c_s;
-    rbase[n_ctx] = c_r;
-    unit_begin[c_unit] = n_ctx;
-    big_chunk[c_big] = c_chunk;
-    big_sbase[c_big] = c_bs;
-    info->n_units = (uint32_t)c_unit;
-    info->n_big = (uint32_t)c_big;
-    info->n_chunks = c_chunk;
-    info->big_samples = c_bs;
-    info->max_chunks = s_max;
+  if (threadIdx.x < PLAN_NV) {
+    unsigned long long t = 0;
+    for (int w = 0; w < PLAN_BLOCK / WAVE; ++w) t += s_red[threadIdx.x][w];
+    tile_sum[(uint64_t)blockIdx.x * PLAN_NV + threadIdx.x] = t;
+  }
+}
+
+// Exclusive scan over the tiles of every quantity (in place); the totals
+// close the base arrays and go to the plan summary.
+__global__ void __launch_bounds__(1024) k_plan_tile_scan(unsigned long long* __restrict__ tile_sum, uint32_t n_tiles,
+                                                         uint32_t n_ctx, uint64_t* __restrict__ sbase,
+                                                         uint64_t* __restrict__ rbase,
+                                                         uint64_t* __restrict__ big_sbase,
+                                                         uint64_t* __restrict__ big_chunk,
+                                                         PlanInfo* __restrict__ info) {
+  __shared__ unsigned long long s_tmp[1024 / WAVE + 1];
+  unsigned long long carry[PLAN_NV] = {0, 0, 0, 0, 0, 0};
+  for (uint32_t b0 = 0; b0 < n_tiles; b0 += 1024) {
+    const uint32_t i = b0 + threadIdx.x;
+#pragma unroll
+    for (int k = 0; k < PLAN_NV; ++k) {
+      const unsigned long long x = i < n_tiles ? tile_sum[(uint64_t)i * PLAN_NV + k] : 0ull;
+      unsigned long long tot;
+      const unsigned long long ex = block_excl_scan<1024>(x, s_tmp, &tot);
+      if (i < n_tiles) tile_sum[(uint64_t)i * PLAN_NV + k] = carry[k] + ex;
+      carry[k] += tot;
+    }
+  }
+  if (threadIdx.x == 0) {
+    sbase[n_ctx] = carry[0];
+    rbase[n_ctx] = carry[1];
+    big_chunk[carry[3]] = carry[4];
+    big_sbase[carry[3]] = carry[5];
+    info->n_big = (uint32_t)carry[3];
+    info->n_chunks = carry[4];
+    info->big_samples = carry[5];
+  }
+}
+
+__global__ void __launch_bounds__(PLAN_BLOCK)
+k_plan_starts(const unsigned long long* __restrict__ hist, uint32_t n_ctx, const uint32_t* __restrict__ grp,
+              const unsigned long long* __restrict__ tile_off, uint64_t* __restrict__ sbase,
+              uint64_t* __restrict__ rbase, uint32_t* __restrict__ big_ctx, uint64_t* __restrict__ big_sbase,
+              uint64_t* __restrict__ big_chunk, uint8_t* __restrict__ start, uint32_t* __restrict__ tile_starts) {
+  __shared__ unsigned long long s_tmp[PLAN_BLOCK / WAVE + 1];
+  __shared__ uint32_t s_tmp32[PLAN_BLOCK / WAVE + 1];
+  const uint32_t c = blockIdx.x * PLAN_BLOCK + threadIdx.x;
+  const PlanVals v = plan_vals(hist, n_ctx, c);
+  const unsigned long long* off = tile_off + (uint64_t)blockIdx.x * PLAN_NV;
+  unsigned long long t;
+  const unsigned long long sb = off[0] + block_excl_scan<PLAN_BLOCK>(v.n, s_tmp, &t);
+  const unsigned long long rb = off[1] + block_excl_scan<PLAN_BLOCK>(v.r, s_tmp, &t);
+  const unsigned long long ps = off[2] + block_excl_scan<PLAN_BLOCK>(v.ps, s_tmp, &t);
+  const unsigned long long bg = off[3] + block_excl_scan<PLAN_BLOCK>(v.big, s_tmp, &t);
+  const unsigned long long ch = off[4] + block_excl_scan<PLAN_BLOCK>(v.ch, s_tmp, &t);
+  const unsigned long long bs = off[5] + block_excl_scan<PLAN_BLOCK>(v.bs, s_tmp, &t);
+  uint32_t st = 0;
+  if (c < n_ctx) {
+    sbase[c] = sb;
+    rbase[c] = rb;
+    const uint8_t k = ctx_kind(v.n);
+    if (k == KIND_B) {
+      big_ctx[bg] = c;
+      big_sbase[bg] = bs;
+      big_chunk[bg] = ch;
+    }
+    // the context before: its kind and the packable count before it
+    const uint64_t n_prev = c > 0 ? (hist[c - 1] & M40) : 0;
+    const uint8_t kp = c > 0 ? ctx_kind(n_prev) : KIND_S;
+    const uint64_t ps_prev = ps - (c > 0 && kp == KIND_S ? n_prev : 0);
+    st = c == 0 || k != KIND_S || kp != KIND_S || (c % MAXC) == 0 || (ps / UHALF) != (ps_prev / UHALF) ||
+         (grp && grp[c] != grp[c - 1]);
+    start[c] = (uint8_t)st;
+  }
+  uint32_t tot;
+  block_excl_scan<PLAN_BLOCK>(st, s_tmp32, &tot);
+  if (threadIdx.x == 0) tile_starts[blockIdx.x] = tot;
+}
+
+__global__ void __launch_bounds__(PLAN_BLOCK)
+k_plan_units(const unsigned long long* __restrict__ hist, uint32_t n_ctx, const uint32_t* __restrict__ grp,
+             const unsigned long long* __restrict__ tile_off, const uint8_t* __restrict__ start,
+             const uint32_t* __restrict__ tile_starts, uint32_t* __restrict__ unit_begin,
+             int32_t* __restrict__ unit_big, PlanInfo* __restrict__ info) {
+  __shared__ unsigned long long s_tmp[PLAN_BLOCK / WAVE + 1];
+  __shared__ uint32_t s_tmp32[PLAN_BLOCK / WAVE + 1];
+  const uint32_t c = blockIdx.x * PLAN_BLOCK + threadIdx.x;
+  const PlanVals v = plan_vals(hist, n_ctx, c);
+  unsigned long long t;
+  const unsigned long long bg = tile_off[(uint64_t)blockIdx.x * PLAN_NV + 3] + block_excl_scan<PLAN_BLOCK>(v.big, s_tmp, &t);
+  const uint32_t st = c < n_ctx ? start[c] : 0u;
+  uint32_t tot;
+  const uint32_t u = tile_starts[blockIdx.x] + block_excl_scan<PLAN_BLOCK>(st, s_tmp32, &tot);
+  if (st) {
+    unit_begin[u] = c;
+    unit_big[u] = ctx_kind(v.n) == KIND_B ? (int32_t)bg : (grp && grp[c] != NONE32 ? UNIT_PART : UNIT_PLAIN);
+  }
+  if (c == n_ctx - 1) {
+    unit_begin[u + st] = n_ctx;
+    info->n_units = u + st;
   }
 }
 
@@ -462,67 +479,81 @@ k_big_parts(const uint32_t* __restrict__ bhist, const uint32_t* __restrict__ bfl
   if (l == WAVE - 1) n_parts[b] = s_incl;
 }
 
-// Virtual contexts, one workgroup: every context stays one, except a split
-// context, which becomes its parts.  Writes the virtual histogram (count, and
-// runs for contexts read through the run list; parts have none), the real
-// context of every virtual one, its group (the split context, or NONE32), the
-// first virtual id of every context (vbase, closed by the total) and vsolo
-// (the virtual id of an unsplit context, NONE32 for a split one).
-__global__ void __launch_bounds__(PLAN_BLOCK)
-k_virtual(const unsigned long long* __restrict__ hist, uint32_t n_ctx, const int32_t* __restrict__ big_of,
-          const uint32_t* __restrict__ n_parts, const uint32_t* __restrict__ psum,
-          unsigned long long* __restrict__ vhist, uint32_t* __restrict__ vreal, uint32_t* __restrict__ vgrp,
-          uint32_t* __restrict__ vbase, uint32_t* __restrict__ vsolo, PlanInfo* __restrict__ info) {
-  __shared__ uint32_t s_tmp[PLAN_BLOCK / WAVE + 1];
-  uint32_t carry = 0, n_split = 0, n_part = 0;
-  unsigned long long split_samples = 0;
-  for (uint32_t b0 = 0; b0 < n_ctx; b0 += PLAN_BLOCK * PLAN_ITEMS) {
-    const uint32_t c0 = b0 + threadIdx.x * PLAN_ITEMS;
-    uint32_t nv[PLAN_ITEMS], local = 0;
-#pragma unroll
-    for (int i = 0; i < PLAN_ITEMS; ++i) {
-      const uint32_t c = c0 + i;
-      nv[i] = 0;
-      if (c < n_ctx) {
-        const int32_t b = big_of[c];
-        nv[i] = (b >= 0 && n_parts[b] != SPLIT_NO) ? n_parts[b] : 1u;
-      }
-      local += nv[i];
-    }
+// Virtual contexts: every context stays one, except a split context, which
+// becomes its parts.  Three launches over tiles of VT contexts: the number of
+// virtual contexts per tile, an exclusive scan of those (one workgroup), then
+// the writes: the virtual histogram (count, and runs for contexts read through
+// the run list; parts have none), the real context of every virtual one, its
+// group (the split context, or NONE32), the first virtual id of every context
+// (vbase, closed by the total) and vsolo (the virtual id of an unsplit
+// context, NONE32 for a split one).
+constexpr int VT = 1024;
+
+__device__ inline uint32_t n_virtual_of(const int32_t* big_of, const uint32_t* n_parts, uint32_t c) {
+  const int32_t b = big_of[c];
+  return (b >= 0 && n_parts[b] != SPLIT_NO) ? n_parts[b] : 1u;
+}
+
+__global__ void __launch_bounds__(VT) k_virtual_count(uint32_t n_ctx, const int32_t* __restrict__ big_of,
+                                                      const uint32_t* __restrict__ n_parts,
+                                                      uint32_t* __restrict__ tile_sum) {
+  __shared__ uint32_t s_tmp[VT / WAVE + 1];
+  const uint32_t c = blockIdx.x * VT + threadIdx.x;
+  const uint32_t nv = c < n_ctx ? n_virtual_of(big_of, n_parts, c) : 0u;
+  uint32_t tot;
+  block_excl_scan<VT>(nv, s_tmp, &tot);
+  if (threadIdx.x == 0) tile_sum[blockIdx.x] = tot;
+}
+
+// Exclusive scan of n per-tile values in place (one workgroup); the total goes
+// to *total.
+__global__ void __launch_bounds__(1024) k_tile_scan(uint32_t* __restrict__ v, uint32_t n, uint32_t* __restrict__ total) {
+  __shared__ uint32_t s_tmp[1024 / WAVE + 1];
+  uint32_t carry = 0;
+  for (uint32_t b0 = 0; b0 < n; b0 += 1024) {
+    const uint32_t i = b0 + threadIdx.x;
+    const uint32_t x = i < n ? v[i] : 0u;
     uint32_t tot;
-    uint32_t v = carry + block_excl_scan<PLAN_BLOCK>(local, s_tmp, &tot);
-#pragma unroll
-    for (int i = 0; i < PLAN_ITEMS; ++i) {
-      const uint32_t c = c0 + i;
-      if (c >= n_ctx) continue;
-      vbase[c] = v;
-      const int32_t b = big_of[c];
-      if (b >= 0 && n_parts[b] != SPLIT_NO) {
-        vsolo[c] = NONE32;
-        for (uint32_t p = 0; p < nv[i]; ++p) {
-          vhist[v + p] = psum[(uint64_t)b * NB + p];
-          vreal[v + p] = c;
-          vgrp[v + p] = c;
-        }
-        ++n_split;
-        n_part += nv[i];
-        split_samples += hist[c] & M40;
-      } else {
-        vsolo[c] = v;
-        vhist[v] = hist[c];
-        vreal[v] = c;
-        vgrp[v] = NONE32;
-      }
-      v += nv[i];
-    }
+    const uint32_t ex = block_excl_scan<1024>(x, s_tmp, &tot);
+    if (i < n) v[i] = carry + ex;
     carry += tot;
   }
-  atomicAdd(&info->n_split, n_split);
-  atomicAdd(&info->n_parts, n_part);
-  atomicAdd(&info->split_samples, split_samples);
-  if (threadIdx.x == 0) {
-    vbase[n_ctx] = carry;
-    info->n_virtual = carry;
+  if (threadIdx.x == 0) *total = carry;
+}
+
+__global__ void __launch_bounds__(VT)
+k_virtual_write(const unsigned long long* __restrict__ hist, uint32_t n_ctx, const int32_t* __restrict__ big_of,
+                const uint32_t* __restrict__ n_parts, const uint32_t* __restrict__ psum,
+                const uint32_t* __restrict__ tile_off, unsigned long long* __restrict__ vhist,
+                uint32_t* __restrict__ vreal, uint32_t* __restrict__ vgrp, uint32_t* __restrict__ vbase,
+                uint32_t* __restrict__ vsolo, PlanInfo* __restrict__ info) {
+  __shared__ uint32_t s_tmp[VT / WAVE + 1];
+  const uint32_t c = blockIdx.x * VT + threadIdx.x;
+  const uint32_t nv = c < n_ctx ? n_virtual_of(big_of, n_parts, c) : 0u;
+  uint32_t tot;
+  const uint32_t v = tile_off[blockIdx.x] + block_excl_scan<VT>(nv, s_tmp, &tot);
+  if (c >= n_ctx) return;
+  vbase[c] = v;
+  if (c == n_ctx - 1) {
+    vbase[n_ctx] = v + nv;
+    info->n_virtual = v + nv;
+  }
+  const int32_t b = big_of[c];
+  if (b >= 0 && n_parts[b] != SPLIT_NO) {
+    vsolo[c] = NONE32;
+    for (uint32_t p = 0; p < nv; ++p) {
+      vhist[v + p] = psum[(uint64_t)b * NB + p];
+      vreal[v + p] = c;
+      vgrp[v + p] = c;
+    }
+    atomicAdd(&info->n_split, 1u);
+    atomicAdd(&info->n_parts, nv);
+    atomicAdd(&info->split_samples, hist[c] & M40);
+  } else {
+    vsolo[c] = v;
+    vhist[v] = hist[c];
+    vreal[v] = c;
+    vgrp[v] = NONE32;
   }
 }
 
@@ -1628,11 +1659,16 @@ extern "C" hpa_status hpa_attribute(hpa_ctx* ctx, const hpa_structure_map* map, 
       d_vgrp = DBuf(ctx, cv_cap * 4, s);
       d_vbase = DBuf(ctx, ((uint64_t)C + 1) * 4, s);
       d_vsolo = DBuf(ctx, (uint64_t)C * 4, s);
-      k_virtual<<<1, PLAN_BLOCK, 0, s>>>(d_hist.as<unsigned long long>(), C, d_bigof.as<int32_t>(),
-                                         d_nparts.as<uint32_t>(), d_psum.as<uint32_t>(),
-                                         d_vhist.as<unsigned long long>(), d_vreal.as<uint32_t>(),
-                                         d_vgrp.as<uint32_t>(), d_vbase.as<uint32_t>(), d_vsolo.as<uint32_t>(),
-                                         d_info.as<PlanInfo>());
+      const uint32_t vtiles = (C + VT - 1) / VT;
+      DBuf d_vtile(ctx, ((uint64_t)vtiles + 1) * 4, s);
+      k_virtual_count<<<vtiles, VT, 0, s>>>(C, d_bigof.as<int32_t>(), d_nparts.as<uint32_t>(),
+                                           d_vtile.as<uint32_t>());
+      k_tile_scan<<<1, 1024, 0, s>>>(d_vtile.as<uint32_t>(), vtiles, d_vtile.as<uint32_t>() + vtiles);
+      k_virtual_write<<<vtiles, VT, 0, s>>>(d_hist.as<unsigned long long>(), C, d_bigof.as<int32_t>(),
+                                           d_nparts.as<uint32_t>(), d_psum.as<uint32_t>(), d_vtile.as<uint32_t>(),
+                                           d_vhist.as<unsigned long long>(), d_vreal.as<uint32_t>(),
+                                           d_vgrp.as<uint32_t>(), d_vbase.as<uint32_t>(), d_vsolo.as<uint32_t>(),
+                                           d_info.as<PlanInfo>());
       HPA_HIP(hipGetLastError());
       HPA_HIP(hipMemcpyAsync(&info, d_info.p, sizeof(info), hipMemcpyDeviceToHost, s));
       HPA_HIP(hipStreamSynchronize(s));
@@ -1648,12 +1684,26 @@ extern "C" hpa_status hpa_attribute(hpa_ctx* ctx, const hpa_structure_map* map, 
     DBuf d_bctx(ctx, ((uint64_t)CV + 1) * 4, s);
     DBuf d_bsb(ctx, ((uint64_t)CV + 1) * 8, s);
     DBuf d_bch(ctx, ((uint64_t)CV + 1) * 8, s);
-    k_plan<<<1, PLAN_BLOCK, 0, s>>>(split ? d_vhist.as<unsigned long long>() : d_hist.as<unsigned long long>(), CV,
-                                    split ? d_vgrp.as<uint32_t>() : nullptr, d_sbase.as<uint64_t>(),
-                                    d_rbase.as<uint64_t>(), d_ubeg.as<uint32_t>(), d_ubig.as<int32_t>(),
-                                    d_bctx.as<uint32_t>(), d_bsb.as<uint64_t>(), d_bch.as<uint64_t>(),
-                                    d_info.as<PlanInfo>());
-    HPA_HIP(hipGetLastError());
+    {
+      const unsigned long long* vh = split ? d_vhist.as<unsigned long long>() : d_hist.as<unsigned long long>();
+      const uint32_t* vg = split ? d_vgrp.as<uint32_t>() : nullptr;
+      const uint32_t ptiles = (CV + PLAN_BLOCK - 1) / PLAN_BLOCK;
+      DBuf d_psums(ctx, (uint64_t)ptiles * PLAN_NV * 8, s);
+      DBuf d_pstart(ctx, (uint64_t)CV, s);
+      DBuf d_pts(ctx, ((uint64_t)ptiles + 1) * 4, s);
+      k_plan_sums<<<ptiles, PLAN_BLOCK, 0, s>>>(vh, CV, d_psums.as<unsigned long long>(), d_info.as<PlanInfo>());
+      k_plan_tile_scan<<<1, 1024, 0, s>>>(d_psums.as<unsigned long long>(), ptiles, CV, d_sbase.as<uint64_t>(),
+                                          d_rbase.as<uint64_t>(), d_bsb.as<uint64_t>(), d_bch.as<uint64_t>(),
+                                          d_info.as<PlanInfo>());
+      k_plan_starts<<<ptiles, PLAN_BLOCK, 0, s>>>(vh, CV, vg, d_psums.as<unsigned long long>(), d_sbase.as<uint64_t>(),
+                                                 d_rbase.as<uint64_t>(), d_bctx.as<uint32_t>(), d_bsb.as<uint64_t>(),
+                                                 d_bch.as<uint64_t>(), d_pstart.as<uint8_t>(), d_pts.as<uint32_t>());
+      k_tile_scan<<<1, 1024, 0, s>>>(d_pts.as<uint32_t>(), ptiles, d_pts.as<uint32_t>() + ptiles);
+      k_plan_units<<<ptiles, PLAN_BLOCK, 0, s>>>(vh, CV, vg, d_psums.as<unsigned long long>(), d_pstart.as<uint8_t>(),
+                                                d_pts.as<uint32_t>(), d_ubeg.as<uint32_t>(), d_ubig.as<int32_t>(),
+                                                d_info.as<PlanInfo>());
+      HPA_HIP(hipGetLastError());
+    }
     HPA_HIP(hipMemcpyAsync(&info, d_info.p, sizeof(info), hipMemcpyDeviceToHost, s));
     HPA_HIP(hipStreamSynchronize(s));
     tm.end(CV, info.n_units);
