@@ -833,16 +833,17 @@ __device__ inline uint32_t scope_of_pc(const DenseDev& t, bool dense, const uint
 // smallest, stall) and sort them.  Keys of at most 32 bits take one 32-bit
 // sort; wider keys take two chained 32-bit sorts (low word first, the high
 // word carried along, then the high word), which is the same LSD order.
-template <bool WEIGHTED, class K>
-__device__ inline void sort_reduce(SortSmem& sm, Gathered<WEIGHTED>& g, uint64_t n_u, uint32_t n_cu, K (&key)[UITEMS],
-                                   uint32_t (&val)[UITEMS], int kbits, int pcb, uint32_t tz) {
-  uint32_t lo[UITEMS], hi[UITEMS];
+template <bool WEIGHTED, class K, int IT = UITEMS>
+__device__ inline void sort_reduce(SortSmem& sm, Gathered<WEIGHTED>& g, uint64_t n_u, uint32_t n_cu, K (&key)[IT],
+                                   uint32_t (&val)[IT], int kbits, int pcb, uint32_t tz) {
+  using S = BlockRadix<UBLOCK, IT>;
+  uint32_t lo[IT], hi[IT];
   // 32-bit keys (kbits <= 31): an empty slot holds 1 << kbits, above every
   // real key, so sorting kbits + 1 bits leaves the real keys first and the
   // sort needs no per-slot test
   const uint64_t empty = sizeof(K) == 4 ? (1ull << kbits) : 0ull;
 #pragma unroll
-  for (int i = 0; i < UITEMS; ++i) {
+  for (int i = 0; i < IT; ++i) {
     const uint64_t j = (uint64_t)i * UBLOCK + threadIdx.x;
     uint64_t k = empty;
     if (j < n_u) {
@@ -855,20 +856,20 @@ __device__ inline void sort_reduce(SortSmem& sm, Gathered<WEIGHTED>& g, uint64_t
   }
   if constexpr (sizeof(K) == 4) {
     if constexpr (WEIGHTED)
-      Sorter::template sort<1, true>(lo, val, hi, kbits + 1, (int)n_u, true, sm.buf, sm.cnt, sm.doff);
-    else Sorter::template sort<0, true>(lo, val, hi, kbits + 1, (int)n_u, true, sm.buf, sm.cnt, sm.doff);
+      S::template sort<1, true>(lo, val, hi, kbits + 1, (int)n_u, true, sm.buf, sm.cnt, sm.doff);
+    else S::template sort<0, true>(lo, val, hi, kbits + 1, (int)n_u, true, sm.buf, sm.cnt, sm.doff);
 #pragma unroll
-    for (int i = 0; i < UITEMS; ++i) key[i] = (K)lo[i];
+    for (int i = 0; i < IT; ++i) key[i] = (K)lo[i];
   } else {
     if constexpr (WEIGHTED) {
-      Sorter::template sort<2>(lo, hi, val, 32, (int)n_u, true, sm.buf, sm.cnt, sm.doff);
-      Sorter::template sort<2>(hi, lo, val, kbits - 32, (int)n_u, false, sm.buf, sm.cnt, sm.doff);
+      S::template sort<2>(lo, hi, val, 32, (int)n_u, true, sm.buf, sm.cnt, sm.doff);
+      S::template sort<2>(hi, lo, val, kbits - 32, (int)n_u, false, sm.buf, sm.cnt, sm.doff);
     } else {
-      Sorter::template sort<1>(lo, hi, val, 32, (int)n_u, true, sm.buf, sm.cnt, sm.doff);
-      Sorter::template sort<1>(hi, lo, val, kbits - 32, (int)n_u, false, sm.buf, sm.cnt, sm.doff);
+      S::template sort<1>(lo, hi, val, 32, (int)n_u, true, sm.buf, sm.cnt, sm.doff);
+      S::template sort<1>(hi, lo, val, kbits - 32, (int)n_u, false, sm.buf, sm.cnt, sm.doff);
     }
 #pragma unroll
-    for (int i = 0; i < UITEMS; ++i) key[i] = (K)(((uint64_t)hi[i] << 32) | lo[i]);
+    for (int i = 0; i < IT; ++i) key[i] = (K)(((uint64_t)hi[i] << 32) | lo[i]);
   }
 }
 
@@ -940,20 +941,20 @@ __device__ inline K prev_last(const SortSmem& sm, int tid) {
   return tid == 0 ? (K)0 : (K)(((uint64_t)sm.last_hi[tid - 1] << 32) | sm.last_lo[tid - 1]);
 }
 
-template <class K>
-__device__ inline uint32_t find_heads(SortSmem& sm, const K (&key)[UITEMS], uint64_t n_u, uint32_t n_cu, int pcb,
+template <class K, int IT = UITEMS>
+__device__ inline uint32_t find_heads(SortSmem& sm, const K (&key)[IT], uint64_t n_u, uint32_t n_cu, int pcb,
                                       uint32_t& first_uidx, uint32_t& nU) {
   const int tid = threadIdx.x;
-  sm.last_lo[tid] = (uint32_t)key[UITEMS - 1];
-  sm.last_hi[tid] = (uint32_t)((uint64_t)key[UITEMS - 1] >> 32);
+  sm.last_lo[tid] = (uint32_t)key[IT - 1];
+  sm.last_hi[tid] = (uint32_t)((uint64_t)key[IT - 1] >> 32);
   // sm.ucnt first holds each context's first unique index (NONE32: no keys)
   for (uint32_t l = tid; l <= n_cu; l += UBLOCK) sm.ucnt[l] = NONE32;
   __syncthreads();
   K prev = prev_last<K>(sm, tid);
   uint32_t heads = 0;
 #pragma unroll
-  for (int i = 0; i < UITEMS; ++i) {
-    uint32_t p = (uint32_t)tid * UITEMS + i;
+  for (int i = 0; i < IT; ++i) {
+    uint32_t p = (uint32_t)tid * IT + i;
     bool h = p < n_u && (p == 0 || key[i] != prev);
     heads += h;
     prev = key[i];
@@ -965,8 +966,8 @@ __device__ inline uint32_t find_heads(SortSmem& sm, const K (&key)[UITEMS], uint
   prev = prev_last<K>(sm, tid);
   uint32_t u = first_uidx;
 #pragma unroll
-  for (int i = 0; i < UITEMS; ++i) {
-    uint32_t p = (uint32_t)tid * UITEMS + i;
+  for (int i = 0; i < IT; ++i) {
+    uint32_t p = (uint32_t)tid * IT + i;
     bool h = p < n_u && (p == 0 || key[i] != prev);
     if (h) {
       sm.upos[u] = (uint16_t)p;
@@ -1003,8 +1004,8 @@ __device__ inline uint32_t find_heads(SortSmem& sm, const K (&key)[UITEMS], uint
 
 // Weighted counts: every head writes the weight of its run inside its thread;
 // runs continuing from the previous thread are added with one atomic each.
-template <class K>
-__device__ inline void weighted_counts(const SortSmem& sm, const K (&key)[UITEMS], const uint32_t (&val)[UITEMS],
+template <class K, int IT = UITEMS>
+__device__ inline void weighted_counts(const SortSmem& sm, const K (&key)[IT], const uint32_t (&val)[IT],
                                        uint64_t n_u, uint32_t first_uidx, unsigned long long* count) {
   const int tid = threadIdx.x;
   K prev = prev_last<K>(sm, tid);
@@ -1012,8 +1013,8 @@ __device__ inline void weighted_counts(const SortSmem& sm, const K (&key)[UITEMS
   bool seen = false;
   uint32_t u = first_uidx;
 #pragma unroll
-  for (int i = 0; i < UITEMS; ++i) {
-    uint32_t p = (uint32_t)tid * UITEMS + i;
+  for (int i = 0; i < IT; ++i) {
+    uint32_t p = (uint32_t)tid * IT + i;
     if (p < n_u) {
       bool h = p == 0 || key[i] != prev;
       if (h) {
@@ -1077,16 +1078,16 @@ struct UnitArgs {
 };
 
 // Stage the unit's unique keys, counts and decoding parameters.
-template <bool WEIGHTED, class K>
+template <bool WEIGHTED, class K, int IT = UITEMS>
 __device__ __forceinline__ void unit_body(SortSmem& sm, const UnitArgs& a, uint32_t u, uint32_t cb, uint32_t ce,
                                           uint64_t n_u, Gathered<WEIGHTED>& g, int kbits, int pcb, uint32_t tz,
                                           bool dense) {
   const uint32_t n_cu = ce - cb;
-  K key[UITEMS];
-  uint32_t val[UITEMS];
-  sort_reduce<WEIGHTED, K>(sm, g, n_u, n_cu, key, val, kbits, pcb, tz);
+  K key[IT];
+  uint32_t val[IT];
+  sort_reduce<WEIGHTED, K, IT>(sm, g, n_u, n_cu, key, val, kbits, pcb, tz);
   uint32_t first, nU;
-  find_heads<K>(sm, key, n_u, n_cu, pcb, first, nU);
+  find_heads<K, IT>(sm, key, n_u, n_cu, pcb, first, nU);
   const uint64_t s0 = a.sbase[cb];
   for (uint32_t l = threadIdx.x; l < n_cu; l += UBLOCK) a.ucnt[(uint64_t)u * MAXC + l] = sm.ucnt[l];
   if (threadIdx.x == 0)
@@ -1105,8 +1106,8 @@ __device__ __forceinline__ void unit_body(SortSmem& sm, const UnitArgs& a, uint3
     K prev = prev_last<K>(sm, threadIdx.x);
     uint32_t ui = first;
 #pragma unroll
-    for (int i = 0; i < UITEMS; ++i) {
-      const uint32_t p = threadIdx.x * UITEMS + i;
+    for (int i = 0; i < IT; ++i) {
+      const uint32_t p = threadIdx.x * IT + i;
       const bool h = p < n_u && (p == 0 || key[i] != prev);
       prev = key[i];
       if (!h) continue;
@@ -1116,7 +1117,7 @@ __device__ __forceinline__ void unit_body(SortSmem& sm, const UnitArgs& a, uint3
       ++ui;
     }
   }
-  if constexpr (WEIGHTED) weighted_counts<K>(sm, key, val, n_u, first, a.scnt64 + s0);
+  if constexpr (WEIGHTED) weighted_counts<K, IT>(sm, key, val, n_u, first, a.scnt64 + s0);
 }
 
 // Sort pass.  GENERAL = false handles keys of at most 32 bits (registers sized
@@ -1168,7 +1169,11 @@ __global__ void __launch_bounds__(UBLOCK) k_units32(UnitArgs a) {
       return;
     }
   }
-  unit_body<WEIGHTED, uint32_t>(sm, a, u, cb, ce, n_u, g, kbits, pcb, tz, dense);
+  // items per thread sized to the unit: a sort pass costs in proportion to
+  // the slots it sorts, padding included
+  if (n_u <= 4u * UBLOCK) unit_body<WEIGHTED, uint32_t, 4>(sm, a, u, cb, ce, n_u, g, kbits, pcb, tz, dense);
+  else if (n_u <= 8u * UBLOCK) unit_body<WEIGHTED, uint32_t, 8>(sm, a, u, cb, ce, n_u, g, kbits, pcb, tz, dense);
+  else unit_body<WEIGHTED, uint32_t, UITEMS>(sm, a, u, cb, ce, n_u, g, kbits, pcb, tz, dense);
 }
 
 // Output offsets: exclusive scan of the units' key counts (a big context's
