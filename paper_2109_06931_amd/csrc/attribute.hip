@@ -734,7 +734,8 @@ template <bool SCATTERED, bool WEIGHTED>
 __device__ inline void gather(Gathered<WEIGHTED>& g, uint64_t s0, uint64_t n_u, uint32_t cb, const Run* __restrict__ grp,
                               uint64_t r_lo, uint64_t r_hi, const uint64_t* __restrict__ sb_lds,
                               uint32_t n_cu, const uint64_t* __restrict__ pc, const uint8_t* __restrict__ stall,
-                              const uint32_t* __restrict__ weight, uint32_t* err, Run* s_runs) {
+                              const uint32_t* __restrict__ weight, uint32_t* err, Run* s_runs,
+                              bool runs_staged = false) {
   // every load is issued before any loaded value is used (the stall test
   // and the packing come after the loop), so a thread's loads overlap
   uint32_t st[UITEMS], lcs[UITEMS];
@@ -772,8 +773,11 @@ __device__ inline void gather(Gathered<WEIGHTED>& g, uint64_t s0, uint64_t n_u, 
     const uint64_t nr = r_hi - r_lo;
     if (nr <= (uint64_t)RUN_CAP) {
       // the walk reads every run several times from dependent addresses: LDS
-      for (uint32_t k = threadIdx.x; k < nr; k += UBLOCK) s_runs[k] = grp[r_lo + k];
-      __syncthreads();
+      // (runs_staged: the caller copied them and synchronised already)
+      if (!runs_staged) {
+        for (uint32_t k = threadIdx.x; k < nr; k += UBLOCK) s_runs[k] = grp[r_lo + k];
+        __syncthreads();
+      }
       gather_runs<WEIGHTED>(s_runs, 0, nr, s0, n_u, cb, load);
     } else {
       gather_runs<WEIGHTED>(grp, r_lo, r_hi, s0, n_u, cb, load);
@@ -1053,6 +1057,25 @@ struct UnitMeta {
 };
 constexpr uint32_t UM_DONE = 1, UM_WIDE = 2, UM_DENSE = 4;
 
+// Everything a unit's workgroup needs first, in one record, so that its
+// start is one load rather than a chain of dependent ones.
+struct UnitDesc {
+  uint64_t s0, s1;  // flat sample range
+  uint64_t r0, r1;  // grouped run range
+  uint32_t cb, ce;  // (virtual) context range
+  int32_t big;      // unit_big
+  uint32_t pad;
+};
+
+__global__ void k_unit_desc(const uint32_t* __restrict__ unit_begin, const int32_t* __restrict__ unit_big,
+                            const uint64_t* __restrict__ sbase, const uint64_t* __restrict__ rbase, uint32_t n_units,
+                            UnitDesc* __restrict__ desc) {
+  for (uint32_t u = blockIdx.x * blockDim.x + threadIdx.x; u < n_units; u += gridDim.x * blockDim.x) {
+    const uint32_t cb = unit_begin[u], ce = unit_begin[u + 1];
+    desc[u] = UnitDesc{sbase[cb], sbase[ce], rbase[cb], rbase[ce], cb, ce, unit_big[u], 0u};
+  }
+}
+
 struct UnitArgs {
   const uint64_t* pc;
   const uint8_t* stall;
@@ -1075,6 +1098,7 @@ struct UnitArgs {
   unsigned long long* scnt64;  // count (weighted)
   int32_t kind;                // the unit class a sort launch handles (UNIT_PLAIN or UNIT_PART)
   const uint32_t* vreal;       // real context of every virtual one (null: no split contexts)
+  const UnitDesc* desc;        // per unit
 };
 
 // Stage the unit's unique keys, counts and decoding parameters.
@@ -1128,26 +1152,32 @@ __global__ void __launch_bounds__(UBLOCK) k_units32(UnitArgs a) {
   __shared__ SortSmem sm;
   __shared__ uint64_t s_sb[MAXC + 1];
   const uint32_t u = blockIdx.x;
+  const UnitDesc d = a.desc[u];
   // units of the other class, or a big context (its keys come from the chunk path)
-  if (a.unit_big[u] != a.kind) return;
+  if (d.big != a.kind) return;
   if (GENERAL && a.meta[u].flags != UM_WIDE) return;
-  const uint32_t cb = a.unit_begin[u], ce = a.unit_begin[u + 1];
-  const uint64_t s0 = a.sbase[cb];
-  const uint64_t n_u = a.sbase[ce] - s0;
+  const uint32_t cb = d.cb, ce = d.ce;
+  const uint64_t s0 = d.s0;
+  const uint64_t n_u = d.s1 - s0;
+  // context bases, window tables and (when they fit) the runs, behind one barrier
   for (uint32_t l = threadIdx.x; l <= ce - cb; l += UBLOCK) s_sb[l] = a.sbase[cb + l];
   const DenseDev t = stage_dense(sm, a.dd);  // LDS view (empty when the map has no dense coordinates)
+  const uint64_t r0 = SCATTERED ? 0 : d.r0, r1 = SCATTERED ? 0 : d.r1;
+  const bool staged = !SCATTERED && r1 - r0 <= (uint64_t)RUN_CAP;
+  if (staged)
+    for (uint32_t k = threadIdx.x; k < r1 - r0; k += UBLOCK) sm.runs[k] = a.grouped[r0 + k];
   __syncthreads();
   Gathered<WEIGHTED> g;
-  gather<SCATTERED, WEIGHTED>(g, s0, n_u, cb, a.grouped, SCATTERED ? 0 : a.rbase[cb], SCATTERED ? 0 : a.rbase[ce],
-                              s_sb, ce - cb, a.pc, a.stall, a.weight, &a.info->err, sm.runs);
+  gather<SCATTERED, WEIGHTED>(g, s0, n_u, cb, a.grouped, r0, r1, s_sb, ce - cb, a.pc, a.stall, a.weight,
+                              &a.info->err, sm.runs, staged);
   bool dense = false;
   if (a.dense) {
     densify(sm, g, n_u, t);
     __syncthreads();
     dense = sm.far == 0;
-    if (!dense)
-      gather<SCATTERED, WEIGHTED>(g, s0, n_u, cb, a.grouped, SCATTERED ? 0 : a.rbase[cb],
-                                  SCATTERED ? 0 : a.rbase[ce], s_sb, ce - cb, a.pc, a.stall, a.weight, &a.info->err, sm.runs);
+    if (!dense)  // the runs are still in LDS: the sort has not touched them
+      gather<SCATTERED, WEIGHTED>(g, s0, n_u, cb, a.grouped, r0, r1, s_sb, ce - cb, a.pc, a.stall, a.weight,
+                                  &a.info->err, sm.runs, staged);
   }
   // key width decides the register type of the sort
   int kbits, pcb;
@@ -1243,7 +1273,8 @@ __global__ void __launch_bounds__(WBLOCK) k_units_write(UnitArgs a, const uint64
                                                        MapDev map, OutDev out, int weighted) {
   __shared__ uint64_t s_lo[DENSE_MAX_WIN], s_hi[DENSE_MAX_WIN], s_d[DENSE_MAX_WIN + 1];
   const uint32_t u = blockIdx.x;
-  if (a.unit_big[u] >= 0) return;
+  const UnitDesc du = a.desc[u];
+  if (du.big >= 0) return;
   const UnitMeta m = a.meta[u];
   if (m.nU == 0) return;
   const bool dense = (m.flags & UM_DENSE) != 0, wide = (m.flags & UM_WIDE) != 0;
@@ -1259,8 +1290,8 @@ __global__ void __launch_bounds__(WBLOCK) k_units_write(UnitArgs a, const uint64
     t.d = s_d;
   }
   __syncthreads();
-  const uint32_t cb = a.unit_begin[u];
-  const uint64_t s0 = a.sbase[cb], o0 = unit_off[u];
+  const uint32_t cb = du.cb;
+  const uint64_t s0 = du.s0, o0 = unit_off[u];
   const uint64_t pmask = m.pcb >= 64 ? ~0ull : ((1ull << m.pcb) - 1);
   const uint32_t* __restrict__ skey = a.skey + s0;
   // the staging arrays a call does not use are null
@@ -1813,6 +1844,10 @@ extern "C" hpa_status hpa_attribute(hpa_ctx* ctx, const hpa_structure_map* map, 
     }
     // --- unit passes: sort (narrow, then the wide units), offsets, write ---
     const uint32_t NU = info.n_units;
+    DBuf d_udesc(ctx, std::max<uint64_t>(NU, 1) * sizeof(UnitDesc), s);
+    k_unit_desc<<<grid_for(NU, 256, ctx->n_cu * 8), 256, 0, s>>>(d_ubeg.as<uint32_t>(), d_ubig.as<int32_t>(),
+                                                                  d_sbase.as<uint64_t>(), d_rbase.as<uint64_t>(), NU,
+                                                                  d_udesc.as<UnitDesc>());
     DBuf d_meta(ctx, std::max<uint64_t>(NU, 1) * sizeof(UnitMeta), s);
     DBuf d_ucnt(ctx, std::max<uint64_t>(NU, 1) * MAXC * 4, s);
     DBuf d_uoff(ctx, ((uint64_t)NU + 1) * 8, s);
@@ -1826,7 +1861,7 @@ extern "C" hpa_status hpa_attribute(hpa_ctx* ctx, const hpa_structure_map* map, 
                 d_ubeg.as<uint32_t>(), d_ubig.as<int32_t>(), d_info.as<PlanInfo>(), NU, C, dd,
                 map->dense ? 1 : 0, d_meta.as<UnitMeta>(), d_ucnt.as<uint32_t>(), d_skey.as<uint32_t>(),
                 d_shi.as<uint32_t>(), weighted ? nullptr : d_scnt.as<uint32_t>(),
-                weighted ? d_scnt.as<unsigned long long>() : nullptr, UNIT_PLAIN, vreal};
+                weighted ? d_scnt.as<unsigned long long>() : nullptr, UNIT_PLAIN, vreal, d_udesc.as<UnitDesc>()};
     tm.begin("units");
 #define HPA_UNITS(W, S, A)                                \
   do {                                                    \

@@ -113,11 +113,11 @@ __device__ inline T block_excl_scan(T v, T* s_tmp, T* total) {
 //
 // A pass: each thread counts its digits in registers (16 four-bit counters in
 // one 64-bit register; the thread's last item is kept aside, so a counter
-// never exceeds ITEMS - 1 <= 15); the 16 counts, widened to 16-bit pairs, go
-// to LDS as 8 columns of one word per thread; every column is scanned over the
-// threads (wave scans), which gives each thread its exclusive prefix per
-// digit, and the digit totals are scanned into digit offsets; each item's new
-// position is digit offset + thread prefix + running count, and the key is
+// never exceeds ITEMS - 1 <= 15); the 16 counts, widened to 16-bit pairs in 8
+// columns, are scanned over each wave's lanes in registers; the wave
+// totals, scanned over the waves and offset by the scanned digit totals, give
+// each thread its own table of where its keys of each digit start; each
+// item's new position is that start plus the running count, and the key is
 // written there in the exchange plane and read back blocked.
 template <int BLOCK, int ITEMS>
 struct BlockRadix {
@@ -125,7 +125,7 @@ struct BlockRadix {
   static constexpr int NW = BLOCK / WAVE;
   static constexpr int BUF_WORDS = T + T / 32;  // exchange plane, padded every 32 words
   static constexpr int CNT_WORDS = 8 * BLOCK;   // 8 columns of 16-bit digit pairs
-  static constexpr int DOFF_WORDS = 16;
+  static constexpr int DOFF_WORDS = 8 * NW;     // per wave: the 8 column totals, then their offsets
   static_assert(T < 65536, "16-bit counters");
   static_assert(ITEMS >= 2 && ITEMS <= 16, "4-bit per-thread counters hold ITEMS - 1");
 
@@ -158,37 +158,48 @@ struct BlockRadix {
       for (int i = 0; i < ITEMS - 1; ++i)
         if (HPA_VALID(i)) h += 1ull << (((key[i] >> shift) & 15u) * 4);
       const uint32_t dl = HPA_VALID(ITEMS - 1) ? (key[ITEMS - 1] >> shift) & 15u : 16u;
-      // 2. widen to 16-bit pairs: column k holds digits 2k (low) and 2k+1 (high)
+      // 2. widen to 16-bit pairs (column k holds digits 2k low and 2k+1
+      //    high) and scan every column over the wave's lanes in registers;
+      //    the wave totals go to LDS
+      uint32_t ex[8];
 #pragma unroll
       for (int k = 0; k < 8; ++k) {
         const uint32_t w = (uint32_t)(h >> (8 * k));
         uint32_t col = (w & 0xFu) | ((w & 0xF0u) << 12);
         if ((dl >> 1) == (uint32_t)k) col += 1u << ((dl & 1u) * 16);
-        s_cnt[k * BLOCK + tid] = col;
+        const uint32_t inc = wave_incl_scan_u32(col);
+        ex[k] = inc - col;
+        if (lane_id() == WAVE - 1) s_doff[wave_id() * 8 + k] = inc;
       }
       __syncthreads();
-      // 3. exclusive scan of every column over the threads; digit totals
-      for (int k = wave_id(); k < 8; k += NW) {
-        uint32_t run = 0;
-#pragma unroll
-        for (int c0 = 0; c0 < BLOCK; c0 += WAVE) {
-          const uint32_t a = s_cnt[k * BLOCK + c0 + lane_id()];
-          const uint32_t inc = wave_incl_scan_u32(a);
-          s_cnt[k * BLOCK + c0 + lane_id()] = run + inc - a;
-          run += wave_last_u32(inc);
-        }
-        if (lane_id() == 0) {
-          s_doff[2 * k] = run & 0xFFFFu;
-          s_doff[2 * k + 1] = run >> 16;
-        }
-      }
-      __syncthreads();
+      // 3. wave 0, lane k < 8 takes column k: the exclusive prefix over the
+      //    waves, plus the offsets of digits 2k and 2k+1 (an exclusive scan of
+      //    the 16 digit totals, as pairs over lanes 0..7), back in place.
+      //    Halves never carry: every count is below T < 65536.
       if (tid < WAVE) {
-        const uint32_t a = lane_id() < 16 ? s_doff[lane_id()] : 0u;
-        const uint32_t inc = wave_incl_scan_u32(a);
-        if (lane_id() < 16) s_doff[lane_id()] = inc - a;
+        const int k = lane_id();
+        uint32_t tot = 0;
+        if (k < 8)
+#pragma unroll
+          for (int w = 0; w < NW; ++w) tot += s_doff[w * 8 + k];
+        const uint32_t pair = k < 8 ? (tot & 0xFFFFu) + (tot >> 16) : 0u;
+        const uint32_t lo = wave_incl_scan_u32(pair) - pair;
+        const uint32_t base = lo | ((lo + (tot & 0xFFFFu)) << 16);
+        if (k < 8) {
+          uint32_t run = base;
+#pragma unroll
+          for (int w = 0; w < NW; ++w) {
+            const uint32_t t = s_doff[w * 8 + k];
+            s_doff[w * 8 + k] = run;
+            run += t;
+          }
+        }
       }
       __syncthreads();
+      // every thread's own column table: digit offset + wave prefix + lane
+      // prefix (read back only by the same thread)
+#pragma unroll
+      for (int k = 0; k < 8; ++k) s_cnt[k * BLOCK + tid] = s_doff[wave_id() * 8 + k] + ex[k];
       // 4. positions: digit offset + thread prefix + running count.  The
       // digits are extracted again rather than kept from step 1: holding 2 x
       // ITEMS values across the scans costs more registers than the shifts.
@@ -198,7 +209,7 @@ struct BlockRadix {
       auto position = [&](int i) -> uint32_t {
         const uint32_t d = (key[i] >> shift) & 15u;
         const uint32_t pre = (s_cnt[(d >> 1) * BLOCK + tid] >> ((d & 1) * 16)) & 0xFFFFu;
-        const uint32_t p = s_doff[d] + pre + ((uint32_t)(r >> (d * 4)) & 15u);
+        const uint32_t p = pre + ((uint32_t)(r >> (d * 4)) & 15u);
         if (i < ITEMS - 1) r += 1ull << (d * 4);
         return p;
       };
