@@ -11,8 +11,8 @@ built once before the timed region, as it is per set of binaries.  Inputs are
 resident in device memory when the timed region starts.
 
 Prints one JSON line.  `roofline` is for the dominant kernel (the unit sort and
-reduce kernel), timed with hipEvents on the call's stream through the library's
-stage timer; `cpu_baseline` times the CPU oracle on a bounded prefix of the
+reduce kernel, its launch over the units read through the run list), timed
+with hipEvents on the call's stream through the library's stage timer; `cpu_baseline` times the CPU oracle on a bounded prefix of the
 same samples.  `--copy-calibration BYTES` instead runs a plain device copy of
 that size (the scale for hardware byte counters) and exits.
 """
@@ -158,14 +158,16 @@ def main():
 
     M = m.n_intervals
     b_alg = 13.0 + 25.0 * U / N + 16.0 * M / N
-    # the unit sort kernel reads its samples (13 B each by the record layout);
-    # its packed output is staging for the write pass, so it is not counted
-    u = stages.get("units", {})
+    # the unit sort kernel (its launch over the units read through the run
+    # list) reads its samples (13 B each by the record layout); its packed
+    # output is staging for the write pass, so it is not counted
+    u = stages.get("units_plain", {})
     u_ms = u.get("ms", 0.0) / max(u.get("calls", 1), 1)
     u_bytes = 13.0 * u.get("items_in", 0) / max(u.get("calls", 1), 1)
     achieved = u_bytes / (u_ms * 1e-3) / 1e9 if u_ms > 0 else 0.0
     traffic = _units_traffic()
-    roofline = {"bound": "hbm", "kernel": "k_units32", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBPS,
+    roofline = {"bound": "hbm", "kernel": "k_units32<false, false, false>", "achieved": round(achieved, 1),
+                "peak": HBM_PEAK_GBPS,
                 "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBPS, 4),
                 "traffic": None if traffic is None else round(traffic),
                 "launch_ms": round(u_ms, 3), "algorithmic_bytes": round(u_bytes)}

@@ -1862,18 +1862,22 @@ extern "C" hpa_status hpa_attribute(hpa_ctx* ctx, const hpa_structure_map* map, 
                 map->dense ? 1 : 0, d_meta.as<UnitMeta>(), d_ucnt.as<uint32_t>(), d_skey.as<uint32_t>(),
                 d_shi.as<uint32_t>(), weighted ? nullptr : d_scnt.as<uint32_t>(),
                 weighted ? d_scnt.as<unsigned long long>() : nullptr, UNIT_PLAIN, vreal, d_udesc.as<UnitDesc>()};
-    tm.begin("units");
-#define HPA_UNITS(W, S, A)                                \
+    // the narrow launch over plain units is timed on its own: it is the
+    // dominant kernel; the launches for wide keys and for parts follow
+#define HPA_UNITS(W, S, A, NAME)                          \
   do {                                                    \
+    if (NAME) tm.begin(NAME);                             \
     k_units32<W, S, false><<<NU, UBLOCK, 0, s>>>(A);      \
+    if (NAME) tm.end();                                   \
+    if (NAME) tm.begin("units_other");                    \
     k_units32<W, S, true><<<NU, UBLOCK, 0, s>>>(A);       \
   } while (0)
     if (weighted) {
-      if (scattered) HPA_UNITS(true, true, ua);
-      else HPA_UNITS(true, false, ua);
+      if (scattered) HPA_UNITS(true, true, ua, "units_plain");
+      else HPA_UNITS(true, false, ua, "units_plain");
     } else {
-      if (scattered) HPA_UNITS(false, true, ua);
-      else HPA_UNITS(false, false, ua);
+      if (scattered) HPA_UNITS(false, true, ua, "units_plain");
+      else HPA_UNITS(false, false, ua, "units_plain");
     }
     if (split) {
       // units of parts read the scattered copies at their flat positions
@@ -1882,8 +1886,8 @@ extern "C" hpa_status hpa_attribute(hpa_ctx* ctx, const hpa_structure_map* map, 
       pa.stall = d_tst.as<uint8_t>();
       pa.weight = weighted ? d_tw.as<uint32_t>() : nullptr;
       pa.kind = UNIT_PART;
-      if (weighted) HPA_UNITS(true, true, pa);
-      else HPA_UNITS(false, true, pa);
+      if (weighted) HPA_UNITS(true, true, pa, (const char*)nullptr);
+      else HPA_UNITS(false, true, pa, (const char*)nullptr);
     }
 #undef HPA_UNITS
     HPA_HIP(hipGetLastError());
@@ -1926,7 +1930,8 @@ extern "C" hpa_status hpa_attribute(hpa_ctx* ctx, const hpa_structure_map* map, 
       }
       uint64_t big_keys = 0;
       for (uint64_t v : bu) big_keys += v;
-      tm.items("units", n - info.big_samples, info.total_keys - big_keys);
+      tm.items("units_plain", n - info.big_samples - info.split_samples, 0);
+      tm.items("units_other", info.split_samples, 0);
       tm.items("unit_write", info.total_keys - big_keys, info.total_keys - big_keys);
       tm.items("big_write", 0, big_keys);
       if (!map->dense) tm.items("scope_labels", info.total_keys, info.total_keys);
