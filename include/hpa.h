@@ -84,9 +84,12 @@ const char* hpa_last_error(void);
 
 /* Device-memory allocator.  alloc returns device memory usable on `stream`
  * (NULL on failure -> HPA_E_NOMEM); free releases it in stream order.  When
- * no allocator is given the library uses hipMallocAsync / hipFreeAsync on the
- * device's default memory pool, whose release threshold it raises so that
- * repeated calls reuse memory. */
+ * no allocator is given the library allocates with hipMallocAsync on the
+ * device's default memory pool and keeps the blocks it releases (including
+ * those of freed output handles) in a cache owned by the context, by size and
+ * stream: a later allocation on the same stream reuses a cached block of at
+ * most twice its size.  Cached blocks return to HIP when the context is
+ * destroyed, or when an allocation would otherwise run out of memory. */
 typedef struct {
   void* (*alloc)(size_t bytes, hipStream_t stream, void* user);
   void (*free)(void* ptr, hipStream_t stream, void* user);
@@ -99,6 +102,8 @@ typedef struct hpa_ctx hpa_ctx;
  * the struct is copied.  Errors: HPA_E_INVAL (bad device or out == NULL),
  * HPA_E_DEVICE. */
 hpa_status hpa_ctx_create(int device, const hpa_allocator* alloc, hpa_ctx** out);
+/* Destroy a context: waits for the device, then returns the cached blocks to
+ * HIP.  Handles made with the context must be freed first. */
 void hpa_ctx_destroy(hpa_ctx* ctx);
 
 /* Stage timing, for profiling the library's own calls (not part of the
