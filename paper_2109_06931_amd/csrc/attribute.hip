@@ -70,6 +70,8 @@ struct PlanInfo {
   uint32_t n_virtual;  // contexts after the split (each part counts as one)
   uint32_t n_parts;    // parts of the split contexts
   unsigned long long split_samples;
+  uint32_t n_merged;   // units after merging adjacent pairs
+  uint32_t pad_;
 };
 
 __device__ inline int bits_for(uint64_t v) { return v ? 64 - __clzll(v) : 0; }
@@ -319,6 +321,61 @@ k_plan_units(const unsigned long long* __restrict__ hist, uint32_t n_ctx, const 
   if (c == n_ctx - 1) {
     unit_begin[u + st] = n_ctx;
     info->n_units = u + st;
+  }
+}
+
+// Unit pairs (2m, 2m + 1) merge when both are read the same way (plain units,
+// or parts of one split context) and together hold at most T samples and MAXC
+// contexts: the band rule above leaves units about half full on average, and
+// a sort costs in proportion to its slots.  Three launches over tiles of
+// PLAN_BLOCK units (the count n_units comes from the plan on the device): the
+// kept units per tile, their scan, and the new unit list.
+__device__ inline bool merge_pair(const uint32_t* unit_begin, const int32_t* unit_big, const uint64_t* sbase,
+                                  const uint32_t* grp, uint32_t nu, uint32_t a) {
+  if (a + 1 >= nu) return false;
+  const int32_t ba = unit_big[a], bb = unit_big[a + 1];
+  if (ba >= 0 || ba != bb) return false;
+  const uint32_t c0 = unit_begin[a], c1 = unit_begin[a + 1], c2 = unit_begin[a + 2];
+  if (grp && grp[c0] != grp[c1]) return false;
+  return c2 - c0 <= (uint32_t)MAXC && sbase[c2] - sbase[c0] <= (uint64_t)UT;
+}
+
+__device__ inline uint32_t unit_kept(const uint32_t* unit_begin, const int32_t* unit_big, const uint64_t* sbase,
+                                     const uint32_t* grp, uint32_t nu, uint32_t u) {
+  if (u >= nu) return 0u;
+  return (u & 1u) && merge_pair(unit_begin, unit_big, sbase, grp, nu, u - 1) ? 0u : 1u;
+}
+
+__global__ void __launch_bounds__(PLAN_BLOCK)
+k_merge_count(const uint32_t* __restrict__ unit_begin, const int32_t* __restrict__ unit_big,
+              const uint64_t* __restrict__ sbase, const uint32_t* __restrict__ grp, const PlanInfo* __restrict__ info,
+              uint32_t* __restrict__ tile_sum) {
+  __shared__ uint32_t s_tmp[PLAN_BLOCK / WAVE + 1];
+  const uint32_t nu = info->n_units;
+  const uint32_t u = blockIdx.x * PLAN_BLOCK + threadIdx.x;
+  uint32_t tot;
+  block_excl_scan<PLAN_BLOCK>(unit_kept(unit_begin, unit_big, sbase, grp, nu, u), s_tmp, &tot);
+  if (threadIdx.x == 0) tile_sum[blockIdx.x] = tot;
+}
+
+__global__ void __launch_bounds__(PLAN_BLOCK)
+k_merge_write(const uint32_t* __restrict__ unit_begin, const int32_t* __restrict__ unit_big,
+              const uint64_t* __restrict__ sbase, const uint32_t* __restrict__ grp, uint32_t n_ctx,
+              const uint32_t* __restrict__ tile_off, uint32_t* __restrict__ out_begin, int32_t* __restrict__ out_big,
+              PlanInfo* __restrict__ info) {
+  __shared__ uint32_t s_tmp[PLAN_BLOCK / WAVE + 1];
+  const uint32_t nu = info->n_units;
+  const uint32_t u = blockIdx.x * PLAN_BLOCK + threadIdx.x;
+  const uint32_t keep = unit_kept(unit_begin, unit_big, sbase, grp, nu, u);
+  uint32_t tot;
+  const uint32_t v = tile_off[blockIdx.x] + block_excl_scan<PLAN_BLOCK>(keep, s_tmp, &tot);
+  if (keep) {
+    out_begin[v] = unit_begin[u];
+    out_big[v] = unit_big[u];
+  }
+  if (u == nu - 1) {
+    out_begin[v + keep] = n_ctx;
+    info->n_merged = v + keep;
   }
 }
 
@@ -1738,7 +1795,18 @@ extern "C" hpa_status hpa_attribute(hpa_ctx* ctx, const hpa_structure_map* map, 
       k_plan_units<<<ptiles, PLAN_BLOCK, 0, s>>>(vh, CV, vg, d_psums.as<unsigned long long>(), d_pstart.as<uint8_t>(),
                                                 d_pts.as<uint32_t>(), d_ubeg.as<uint32_t>(), d_ubig.as<int32_t>(),
                                                 d_info.as<PlanInfo>());
+      // merge adjacent unit pairs (at most CV units: tiles over CV)
+      DBuf d_ubeg2(ctx, ((uint64_t)CV + 1) * 4, s);
+      DBuf d_ubig2(ctx, ((uint64_t)CV + 1) * 4, s);
+      k_merge_count<<<ptiles, PLAN_BLOCK, 0, s>>>(d_ubeg.as<uint32_t>(), d_ubig.as<int32_t>(), d_sbase.as<uint64_t>(), vg,
+                                                 d_info.as<PlanInfo>(), d_pts.as<uint32_t>());
+      k_tile_scan<<<1, 1024, 0, s>>>(d_pts.as<uint32_t>(), ptiles, d_pts.as<uint32_t>() + ptiles);
+      k_merge_write<<<ptiles, PLAN_BLOCK, 0, s>>>(d_ubeg.as<uint32_t>(), d_ubig.as<int32_t>(), d_sbase.as<uint64_t>(), vg,
+                                                 CV, d_pts.as<uint32_t>(), d_ubeg2.as<uint32_t>(),
+                                                 d_ubig2.as<int32_t>(), d_info.as<PlanInfo>());
       HPA_HIP(hipGetLastError());
+      std::swap(d_ubeg, d_ubeg2);
+      std::swap(d_ubig, d_ubig2);
     }
     HPA_HIP(hipMemcpyAsync(&info, d_info.p, sizeof(info), hipMemcpyDeviceToHost, s));
     HPA_HIP(hipStreamSynchronize(s));
@@ -1843,7 +1911,7 @@ extern "C" hpa_status hpa_attribute(hpa_ctx* ctx, const hpa_structure_map* map, 
       tm.end(info.big_samples, 0);
     }
     // --- unit passes: sort (narrow, then the wide units), offsets, write ---
-    const uint32_t NU = info.n_units;
+    const uint32_t NU = info.n_merged;
     DBuf d_udesc(ctx, std::max<uint64_t>(NU, 1) * sizeof(UnitDesc), s);
     k_unit_desc<<<grid_for(NU, 256, ctx->n_cu * 8), 256, 0, s>>>(d_ubeg.as<uint32_t>(), d_ubig.as<int32_t>(),
                                                                   d_sbase.as<uint64_t>(), d_rbase.as<uint64_t>(), NU,
