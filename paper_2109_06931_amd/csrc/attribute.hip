@@ -330,6 +330,9 @@ k_plan_units(const unsigned long long* __restrict__ hist, uint32_t n_ctx, const 
 // a sort costs in proportion to its slots.  Three launches over tiles of
 // PLAN_BLOCK units (the count n_units comes from the plan on the device): the
 // kept units per tile, their scan, and the new unit list.
+// Between merge rounds: the merged count becomes the unit count.
+__global__ void k_set_units(PlanInfo* __restrict__ info) { info->n_units = info->n_merged; }
+
 __device__ inline bool merge_pair(const uint32_t* unit_begin, const int32_t* unit_big, const uint64_t* sbase,
                                   const uint32_t* grp, uint32_t nu, uint32_t a) {
   if (a + 1 >= nu) return false;
@@ -1701,7 +1704,9 @@ extern "C" hpa_status hpa_attribute(hpa_ctx* ctx, const hpa_structure_map* map, 
     HPA_HIP(hipMemsetAsync(d_hist.p, 0, (uint64_t)C * 8, s));
     {
       uint64_t tiles = (n + SCAN_TILE - 1) / SCAN_TILE;
-      unsigned grid = (unsigned)std::min<uint64_t>(tiles, (uint64_t)ctx->n_cu * 8);
+      // as many workgroups as are resident at once (four per CU at its
+      // 33 KB of LDS), each looping over tiles
+      unsigned grid = (unsigned)std::min<uint64_t>(tiles, (uint64_t)ctx->n_cu * 4);
       k_scan_ctx<<<grid, SCAN_BLOCK, 0, s>>>(smp->ctx, n, C, d_hist.as<unsigned long long>(), d_runs.as<Run>(),
                                              run_cap, d_info.as<PlanInfo>());
       HPA_HIP(hipGetLastError());
@@ -1795,18 +1800,24 @@ extern "C" hpa_status hpa_attribute(hpa_ctx* ctx, const hpa_structure_map* map, 
       k_plan_units<<<ptiles, PLAN_BLOCK, 0, s>>>(vh, CV, vg, d_psums.as<unsigned long long>(), d_pstart.as<uint8_t>(),
                                                 d_pts.as<uint32_t>(), d_ubeg.as<uint32_t>(), d_ubig.as<int32_t>(),
                                                 d_info.as<PlanInfo>());
-      // merge adjacent unit pairs (at most CV units: tiles over CV)
+      // merge adjacent unit pairs, twice (at most CV units: tiles over CV);
+      // each round reads the unit count the previous one left in n_units
       DBuf d_ubeg2(ctx, ((uint64_t)CV + 1) * 4, s);
       DBuf d_ubig2(ctx, ((uint64_t)CV + 1) * 4, s);
-      k_merge_count<<<ptiles, PLAN_BLOCK, 0, s>>>(d_ubeg.as<uint32_t>(), d_ubig.as<int32_t>(), d_sbase.as<uint64_t>(), vg,
-                                                 d_info.as<PlanInfo>(), d_pts.as<uint32_t>());
-      k_tile_scan<<<1, 1024, 0, s>>>(d_pts.as<uint32_t>(), ptiles, d_pts.as<uint32_t>() + ptiles);
-      k_merge_write<<<ptiles, PLAN_BLOCK, 0, s>>>(d_ubeg.as<uint32_t>(), d_ubig.as<int32_t>(), d_sbase.as<uint64_t>(), vg,
-                                                 CV, d_pts.as<uint32_t>(), d_ubeg2.as<uint32_t>(),
-                                                 d_ubig2.as<int32_t>(), d_info.as<PlanInfo>());
-      HPA_HIP(hipGetLastError());
-      std::swap(d_ubeg, d_ubeg2);
-      std::swap(d_ubig, d_ubig2);
+      for (int round = 0; round < 2; ++round) {
+        if (round) {
+          k_set_units<<<1, 1, 0, s>>>(d_info.as<PlanInfo>());
+        }
+        k_merge_count<<<ptiles, PLAN_BLOCK, 0, s>>>(d_ubeg.as<uint32_t>(), d_ubig.as<int32_t>(), d_sbase.as<uint64_t>(),
+                                                   vg, d_info.as<PlanInfo>(), d_pts.as<uint32_t>());
+        k_tile_scan<<<1, 1024, 0, s>>>(d_pts.as<uint32_t>(), ptiles, d_pts.as<uint32_t>() + ptiles);
+        k_merge_write<<<ptiles, PLAN_BLOCK, 0, s>>>(d_ubeg.as<uint32_t>(), d_ubig.as<int32_t>(), d_sbase.as<uint64_t>(),
+                                                   vg, CV, d_pts.as<uint32_t>(), d_ubeg2.as<uint32_t>(),
+                                                   d_ubig2.as<int32_t>(), d_info.as<PlanInfo>());
+        HPA_HIP(hipGetLastError());
+        std::swap(d_ubeg, d_ubeg2);
+        std::swap(d_ubig, d_ubig2);
+      }
     }
     HPA_HIP(hipMemcpyAsync(&info, d_info.p, sizeof(info), hipMemcpyDeviceToHost, s));
     HPA_HIP(hipStreamSynchronize(s));
