@@ -264,3 +264,16 @@ def test_attribute_map_without_dense_coordinates(hpa, hctx):
     w.weight = None
     m, om, a, oa = _run(hpa, hctx, w)
     assert_attribution_equal(a.numpy(), oa, "no dense map")
+
+
+def test_attribute_reuses_cached_blocks(hpa):
+    # one context, calls of different sizes in a row: the library reuses the
+    # blocks of earlier calls, which still hold their data, so any buffer read
+    # before it is written would show up here as a wrong result
+    ctx = hpa.Context(0)
+    big = small_config(8, n_samples=300_000, n_ctx=8)
+    small = small_config(2, n_samples=60_000)
+    for name, w in [("big", big), ("small", small), ("big again", big), ("small again", small)]:
+        m, om, a, oa = _run(hpa, ctx, w)
+        assert_attribution_equal(a.numpy(), oa, f"cached blocks: {name}")
+        del a, m
