@@ -9,18 +9,24 @@
 //
 //   scan_ctx    read ctx[] once (4 B/sample): run boundaries, per-context
 //               sample and run counts (one 64-bit atomic per run), run list.
-//   plan        one workgroup: prefix sums over contexts, packing of contexts
-//               into work units of <= T samples, list of contexts > T samples.
+//   split       contexts over T samples: a histogram over coordinate buckets,
+//               parts of at most T samples by coordinate range, which stand
+//               in for the context as virtual contexts.
+//   plan        parallel tile scans over the (virtual) contexts: bases,
+//               packing into work units of <= T samples, adjacent unit pairs
+//               merged when they fit, contexts that stay over T samples.
 //   group_runs  order the run list by context (atomic cursors; a run learns
-//               its offset inside its context from the same atomic).
+//               its offset inside its context from the same atomic); the
+//               samples of split contexts are copied into part order.
 //   units       one workgroup per unit: gather the unit's samples from its
 //               runs (pc 8 B + stall 1 B, read once), map pcs to dense
 //               coordinates, pack keys, LSD radix sort in LDS, run-length
 //               reduce, stage the packed unique keys at the unit's first sample
 //               position; then a scan gives the output offsets and a write
 //               pass unpacks the keys (pc, scope label from the dense table).
-//   big path    contexts over T samples: chunk sort, pairwise merge rounds,
-//               duplicate combine, written where the unit pass placed them.
+//   chunk path  contexts over T samples that cannot be split: chunk sort,
+//               pairwise merge rounds, duplicate combine, written where the
+//               unit pass placed them.
 //
 // When runs are short (shuffled input) the run list would cost more than the
 // samples themselves; the samples are then scattered into context order first.
@@ -162,7 +168,7 @@ k_scan_ctx(const uint32_t* __restrict__ ctx, uint64_t n, uint32_t n_ctx, unsigne
 }
 
 // ----------------------------------------------------------------------------
-// plan: one workgroup walks the contexts in order.  A unit is a run of
+// plan: contexts are packed into units in order.  A unit is a run of
 // contexts packed together; unit_big holds the big-context index of a unit of
 // one context over T samples, UNIT_PLAIN for a unit read through the run
 // list, and UNIT_PART for a unit of parts of a split context (grp, when
