@@ -279,8 +279,34 @@ def build_structure_map_workload(ctx: Context, w, **kw) -> StructureMap:
                                w.line_file, w.line_line, **kw)
 
 
+def _device_arrays(*specs):
+    """Check that each (tensor, name, itemsize, n, optional) can be handed to the
+    library as n contiguous integers of `itemsize` bytes in device memory.  Shapes
+    and types are checked for every array before placement, and everything before
+    any library call; a mismatch raises ValueError."""
+    for t, name, itemsize, n, optional in specs:
+        if t is None:
+            if optional:
+                continue
+            raise ValueError(f"{name} is required")
+        if not hasattr(t, "data_ptr") or not hasattr(t, "element_size"):
+            raise ValueError(f"{name} must be a torch tensor, got {type(t).__name__}")
+        if t.dtype.is_floating_point or t.dtype.is_complex or str(t.dtype) == "torch.bool":
+            raise ValueError(f"{name} must hold integers, got {t.dtype}")
+        if t.element_size() != itemsize:
+            raise ValueError(f"{name} must have {itemsize}-byte elements, got {t.dtype}")
+        if not t.is_contiguous():
+            raise ValueError(f"{name} must be contiguous")
+        if n is not None and t.numel() != n:
+            raise ValueError(f"{name} has {t.numel()} elements, expected {n}")
+    for t, name, _, _, _ in specs:
+        if t is not None and not t.is_cuda:
+            raise ValueError(f"{name} must be in GPU memory (a CUDA tensor)")
+
+
 def lookup_intervals(ctx: Context, m: StructureMap, pc, out, mode: int = LOOKUP_PLAIN, stream=None):
-    """hpa_lookup_intervals on CUDA tensors pc (uint64) -> out (uint32)."""
+    """hpa_lookup_intervals on CUDA tensors pc (uint64) -> out (uint32, same length)."""
+    _device_arrays((pc, "pc", 8, None, False), (out, "out", 4, pc.numel() if hasattr(pc, "numel") else None, False))
     _check(lib().hpa_lookup_intervals(ctx.h, m.h, _ptr(pc), pc.numel(), _ptr(out), mode,
                                       C.c_void_p(_stream(stream))), "hpa_lookup_intervals")
     return out
@@ -312,7 +338,16 @@ class Attribution:
 
 def attribute(ctx: Context, m: StructureMap, pc, ctx_ids, stall, weight=None, n_ctx: int = None,
               stream=None) -> Attribution:
-    """hpa_attribute on CUDA tensors (uint64 pc, uint32/int32 ctx, uint8 stall, optional uint32 weight)."""
+    """hpa_attribute on CUDA tensors (uint64 pc, uint32/int32 ctx, uint8 stall, optional uint32 weight),
+    all of one length.  n_ctx defaults to max(ctx) + 1."""
+    n = pc.numel() if hasattr(pc, "numel") else None
+    _device_arrays((pc, "pc", 8, None, False), (ctx_ids, "ctx_ids", 4, n, False), (stall, "stall", 1, n, False),
+                   (weight, "weight", 4, n, True))
+    if n_ctx is None:
+        import torch
+        n_ctx = int(ctx_ids.view(torch.int32).max().item()) + 1 if n else 1
+    if not 0 < int(n_ctx) < 2 ** 32:
+        raise ValueError(f"n_ctx must be in [1, 2^32), got {n_ctx}")
     s = _Samples()
     s.pc, s.ctx, s.stall, s.weight = _ptr(pc), _ptr(ctx_ids), _ptr(stall), _ptr(weight)
     s.n, s.n_ctx = pc.numel(), int(n_ctx)

@@ -322,6 +322,42 @@ def test_fig4_shape_golden():
     assert len(set(t.scc.tolist())) == 4
 
 
+def _preorder_keys(t, ci):
+    """Path keys of context ci's call-path nodes in the order the tree stores them."""
+    b, e = int(t.node_off[ci]), int(t.node_off[ci + 1])
+    keys = []
+    for i in range(b, e):
+        if t.kind[i] != 0:
+            continue
+        p = int(t.parent[i])
+        keys.append((int(t.node[i]),) if p == NONE32 else keys[p] + (int(t.site[i]),))
+    return keys
+
+
+def test_cct_children_follow_call_site_pc_order():
+    # Section 6.3 step 4 unfolds the graph into a tree of call paths; the stored
+    # tree is in depth-first preorder with the children of a node ordered by the
+    # call-site PC of their edge.  Here call-site PC order, callee-id order and
+    # the order the sites are listed in all differ, at two levels:
+    #   caller 0: sites listed to callees 1, 3, 2 at instructions 2, 1, 3
+    #             -> PC order 3, 1, 2 (callee order 1, 2, 3; listing 1, 3, 2)
+    #   caller 2: sites listed to callees 5, 4 at instructions 1, 2
+    #   caller 3: sites listed to callees 4, 5 at instructions 2, 1
+    sites = [(0, 1, 2), (0, 3, 3), (0, 2, 5), (2, 5, 1), (2, 4, 2), (3, 4, 4), (3, 5, 1)]
+    slots = [2, 1, 3, 1, 2, 2, 1]
+    w = handmade.build(6, sites, {1: [(0, 3)], 4: [(2, 8)], 5: [(1, 6)]}, entry=0, site_slots=slots)
+    m, a, t, d = oracle.run_all(w)
+    got = _preorder_keys(t, 0)
+    (paths, _, _, _), _ = _brute_case(w, 0)
+    assert got == list(paths)  # brute force walks children in call-site PC order
+    pc = {(u, v): int(p) for (u, v, _), p in zip(sites, w.site_pc.tolist())}
+    want = [(0,), (0, pc[0, 3]), (0, pc[0, 3], pc[3, 5]), (0, pc[0, 3], pc[3, 4]), (0, pc[0, 1]),
+            (0, pc[0, 2]), (0, pc[0, 2], pc[2, 5]), (0, pc[0, 2], pc[2, 4])]
+    assert got == want
+    # children of the root by callee: 3, 1, 2 (neither callee-id nor listing order)
+    assert [int(t.node[i]) for i in range(int(t.node_off[1])) if len(got[i]) == 2] == [3, 1, 2]
+
+
 def test_tree_has_unit_ratios():
     # A call tree: every function has one call site, so every phi is 1 (gprof split of one).
     sites = [(0, 1, 3), (0, 2, 1), (1, 3, 0), (2, 4, 2)]

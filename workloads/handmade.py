@@ -18,10 +18,12 @@ def func_start(f: int, size: int = 16) -> int:
 
 
 def build(n_funcs: int, sites, self_rows, entry=0, size: int = 16, n_ctx: int = 1,
-          ctx_parent=None, ctx_entry=None, ctx_of=None, unknown_row=None) -> Workload:
+          ctx_parent=None, ctx_entry=None, ctx_of=None, unknown_row=None, site_slots=None) -> Workload:
     """sites: list of (caller, callee, call_samples[, stall]); self_rows: f -> list of
     (stall, count) non-call samples.  All samples go to context 0 unless ctx_of
-    maps a function to another context."""
+    maps a function to another context.  site_slots, if given, places site i at
+    instruction site_slots[i] of its caller instead of 1 + its rank among the
+    caller's sites (the call-site arrays keep the listing order)."""
     s_start = np.array([func_start(f, size) for f in range(n_funcs)], dtype=np.uint64)
     s_end = s_start + np.uint64(size * STRIDE)
     per_caller = {}
@@ -32,7 +34,8 @@ def build(n_funcs: int, sites, self_rows, entry=0, size: int = 16, n_ctx: int = 
         st = t[3] if len(t) > 3 else 0
         k = per_caller.get(u, 0)
         per_caller[u] = k + 1
-        pc = func_start(u, size) + (1 + k) * STRIDE
+        slot = (1 + k) if site_slots is None else site_slots[len(site_pc)]
+        pc = func_start(u, size) + slot * STRIDE
         site_pc.append(pc); site_caller.append(u); site_callee.append(v)
         pcs += [pc] * c; stalls += [st] * c; ctxs += [ctx_of.get(u, 0)] * c
     for f, rows in self_rows.items():
