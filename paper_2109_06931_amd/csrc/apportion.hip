@@ -84,6 +84,7 @@ struct AppArgs {
   uint32_t n_ctx;
   unsigned int* err;        // ERR_* bits
   unsigned int* ticket;      // next context to take
+  int sample_based;         // 1: step 2 (and its re-application) on; 0: weights are exact counts
   // per-workgroup workspace
   uint8_t* ws;
   uint64_t ws_stride;
@@ -163,6 +164,17 @@ __device__ inline uint32_t lower_bound_dev(const T* a, uint32_t n, T v) {
   return lo;
 }
 
+// Words that other threads of the workgroup update with atomics in the same
+// launch are read back with atomic loads at agent scope: such a load is served
+// by the L2, where the atomics were performed, never by a line that this CU's
+// vector L1 may still hold from before the updates.
+__device__ inline unsigned long long ld_at(const unsigned long long* p) {
+  return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+__device__ inline uint32_t ld_at(const uint32_t* p) {
+  return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+
 // Error bits raised by the kernel (checked by the host after each pass).
 constexpr unsigned int ERR_SCOPE = 1, ERR_STALL = 2, ERR_ROW = 4, ERR_QUEUE = 8, ERR_NODE = 16;
 
@@ -210,6 +222,10 @@ __device__ void analyze(const AppArgs& a, Shared& sh, uint32_t c, const EntDesc&
   for (uint32_t i = tid; i < E.nX; i += ABLOCK) { x_row[i] = 0; x_fl[i] = 0; }
   for (uint32_t i = tid; i < E.nE; i += ABLOCK) e_w[i] = 0;
   if (tid < NS) { sh.unk[tid] = 0; sh.unr[tid] = 0; }
+  // Each hand-over of workspace words between threads is a device-scope fence
+  // (the stores or atomics have reached the L2, and this CU's L1 is
+  // invalidated) followed by the barrier.
+  __threadfence();
   __syncthreads();
   // ---- step 1: self costs per condensed node and stall; call-site weights ----
   // (a) mark the condensed nodes that own samples; (b) give them dense rows in
@@ -225,14 +241,15 @@ __device__ void analyze(const AppArgs& a, Shared& sh, uint32_t c, const EntDesc&
     const uint32_t sc = a.k_scope[k];
     if (sc == NONE32 || sc >= a.n_ids) continue;
     const uint32_t u = local_u(sc);
-    if (u != NONE32) __hip_atomic_store(&x_row[u_x[u]], 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+    if (u != NONE32) __hip_atomic_store(&x_row[u_x[u]], 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
   }
+  __threadfence();
   __syncthreads();
   {
     uint32_t done = 0;
     for (uint32_t x0 = 0; x0 < E.nX; x0 += ABLOCK) {
       const uint32_t x = x0 + tid;
-      const uint32_t used = x < E.nX ? x_row[x] : 0u;
+      const uint32_t used = x < E.nX ? ld_at(&x_row[x]) : 0u;
       uint32_t t;
       const uint32_t r = done + block_excl_scan<ABLOCK>(used, sh.tmp32, &t);
       if (x < E.nX) x_row[x] = used ? r : NONE32;
@@ -241,6 +258,7 @@ __device__ void analyze(const AppArgs& a, Shared& sh, uint32_t c, const EntDesc&
       done += t;
     }
   }
+  __threadfence();
   __syncthreads();
   for (uint64_t k = k0 + tid; k < k1; k += ABLOCK) {
     const uint32_t sc = a.k_scope[k];
@@ -265,14 +283,15 @@ __device__ void analyze(const AppArgs& a, Shared& sh, uint32_t c, const EntDesc&
     const uint32_t e = lower_bound_dev(e_pc, E.nE, pcv);
     if (e < E.nE && e_pc[e] == pcv) atomicAdd(&e_w[e], cnt);
   }
+  __threadfence();
   __syncthreads();
   // ---- step 2 inputs: incoming nonzero weight, activity ----
   for (uint32_t e = tid; e < E.nE; e += ABLOCK)
-    if (e_w[e] > 0) u_fl[e_eu[e]] = F_NZIN;  // benign race: same value
+    if (ld_at(&e_w[e]) > 0) u_fl[e_eu[e]] = F_NZIN;  // benign race: same value
   __syncthreads();
   for (uint32_t u = tid; u < E.nU; u += ABLOCK) {
-    bool act = u_ss[u] > 0;
-    for (uint32_t i = u_oo[u]; i < u_oo[u + 1] && !act; ++i) act = e_w[u_oe[i]] > 0;
+    bool act = ld_at(&u_ss[u]) > 0;
+    for (uint32_t i = u_oo[u]; i < u_oo[u + 1] && !act; ++i) act = ld_at(&e_w[u_oe[i]]) > 0;
     if (act) u_fl[u] |= F_ACT;
   }
   __syncthreads();
@@ -294,13 +313,15 @@ __device__ void analyze(const AppArgs& a, Shared& sh, uint32_t c, const EntDesc&
     }
     __syncthreads();
   }
-  for (uint32_t e = tid; e < E.nE; e += ABLOCK)
-    e_w1[e] = e_w[e] > 0 ? e_w[e] : ((u_fl[e_eu[e]] & F_FIRES) ? 1ull : 0ull);
+  for (uint32_t e = tid; e < E.nE; e += ABLOCK) {
+    const unsigned long long w = ld_at(&e_w[e]);
+    e_w1[e] = (w > 0 || !a.sample_based) ? w : ((u_fl[e_eu[e]] & F_FIRES) ? 1ull : 0ull);
+  }
   __syncthreads();
   // ---- condensed graph: self sums, the step-2 rule once more, W', has-cost, sizes ----
   for (uint32_t x = tid; x < E.nX; x += ABLOCK) {
     unsigned long long ss = 0;
-    for (uint32_t mi = x_mo[x]; mi < x_mo[x + 1]; ++mi) ss += u_ss[x_mem[mi]];
+    for (uint32_t mi = x_mo[x]; mi < x_mo[x + 1]; ++mi) ss += ld_at(&u_ss[x_mem[mi]]);
     x_ss[x] = ss;
     bool nz = false;
     for (uint32_t i = x_io[x]; i < x_io[x + 1] && !nz; ++i) nz = e_w1[x_ie[i]] > 0;
@@ -322,7 +343,7 @@ __device__ void analyze(const AppArgs& a, Shared& sh, uint32_t c, const EntDesc&
   for (uint32_t x = tid; x < E.nX; x += ABLOCK)
     for (uint32_t i = x_oo[x]; i < x_oo[x + 1]; ++i) {
       const uint32_t e = x_oe[i];
-      e_w2[e] = e_w1[e] > 0 ? e_w1[e] : ((x_fl[u_x[e_eu[e]]] & F_FIRES) ? 1ull : 0ull);
+      e_w2[e] = (e_w1[e] > 0 || !a.sample_based) ? e_w1[e] : ((x_fl[u_x[e_eu[e]]] & F_FIRES) ? 1ull : 0ull);
     }
   __syncthreads();
   for (uint32_t x = tid; x < E.nX; x += ABLOCK) {
@@ -414,7 +435,7 @@ __global__ void __launch_bounds__(ABLOCK) k_apportion(AppArgs a) {
     const uint64_t base = a.node_off[c], end = a.node_off[c + 1];
     // final weights, by call-site pc (edges are stored in pc order)
     {
-      const uint64_t wb = a.w_off[c];
+      const uint64_t wb = a.w_off[c], we = a.w_off[c + 1];
       unsigned long long done = 0;
       for (uint32_t e0 = 0; e0 < E.nE; e0 += ABLOCK) {
         const uint32_t e = e0 + tid;
@@ -422,8 +443,13 @@ __global__ void __launch_bounds__(ABLOCK) k_apportion(AppArgs a) {
         unsigned long long t;
         unsigned long long ex = block_excl_scan<ABLOCK>((unsigned long long)pos, sh.tmp, &t);
         if (pos) {
-          a.o_wsite[wb + done + ex] = e_pc[e];
-          a.o_wval[wb + done + ex] = e_w2[e];
+          const uint64_t o = wb + done + ex;
+          if (o < we) {
+            a.o_wsite[o] = e_pc[e];
+            a.o_wval[o] = e_w2[e];
+          } else {
+            atomicOr(a.err, ERR_NODE);
+          }
         }
         done += t;
       }
@@ -478,7 +504,7 @@ __global__ void __launch_bounds__(ABLOCK) k_apportion(AppArgs a) {
         a.o_depth[o] = it.depth;
         const uint32_t r = x_row[it.x];
         for (int s = 0; s < NS; ++s)
-          a.o_excl[o * NS + s] = (r == NONE32 ? 0.0 : (double)rows[(uint64_t)r * NS + s]) * it.phi;
+          a.o_excl[o * NS + s] = (r == NONE32 ? 0.0 : (double)ld_at(&rows[(uint64_t)r * NS + s])) * it.phi;
         uint64_t off = it.pre + 1;
         for (uint32_t j = x_oo[it.x]; j < x_oo[it.x + 1]; ++j) {
           const uint32_t e = x_oe[j];
@@ -931,11 +957,6 @@ extern "C" hpa_status hpa_apportion_callpaths(hpa_ctx* ctx, const hpa_callgraph_
     if (attr->map != plan->map) fail(HPA_E_INVAL, "attribution and plan use different structure maps");
     if (attr->n_ctx != plan->n_ctx) fail(HPA_E_INVAL, "attribution and plan have different context counts");
     const int sample_based = opts ? opts->sample_based : 1;
-    if (!sample_based) fail(HPA_E_UNSUPPORTED, "exact-count call graphs (sample_based = 0) are not built");
-#ifndef HPA_ENABLE_GPU_CCT
-    fail(HPA_E_UNSUPPORTED, "GPU call-path apportioning is compiled out (HPA_ENABLE_GPU_CCT) until its kernels are "
-                            "verified on the device");
-#endif
     DeviceGuard dg(ctx->device);
     hipStream_t s = stream;
     const uint32_t C = plan->n_ctx;
@@ -967,6 +988,7 @@ extern "C" hpa_status hpa_apportion_callpaths(hpa_ctx* ctx, const hpa_callgraph_
     a.err = d_err.as<unsigned int>();
     a.n_ctx = C;
     a.ticket = d_ticket.as<unsigned int>();
+    a.sample_based = sample_based ? 1 : 0;
     a.maxU = std::max(plan->maxU, 1u);
     a.maxX = std::max(plan->maxX, 1u);
     a.maxE = std::max(plan->maxE, 1u);

@@ -194,16 +194,21 @@ __global__ void __launch_bounds__(DBLOCK) k_scope(ScopeArgs a) {
       uint32_t x = a.k_scope[k];
       for (uint32_t steps = 0; x != NONE32; ++steps) {
         if (x >= a.n_ids || steps >= a.n_ids) { atomicOr(a.err, ERR_SCOPE); break; }
-        __hip_atomic_store(&row_of[x], 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+        __hip_atomic_store(&row_of[x], 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
         x = a.sparent[x];
       }
     }
+    // hand-overs of workspace words between threads: device-scope fence, then
+    // the barrier (stores and atomics reach the L2; this CU's L1 is invalidated)
+    __threadfence();
     __syncthreads();
     // (b) dense rows in id order
     uint32_t nrows = 0;
     for (uint32_t i0 = 0; i0 < a.n_ids; i0 += DBLOCK) {
       const uint32_t i = i0 + threadIdx.x;
-      const uint32_t used = (i < a.n_ids && row_of[i] != NONE32) ? 1u : 0u;
+      const uint32_t used =
+          (i < a.n_ids && __hip_atomic_load(&row_of[i], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) != NONE32) ? 1u
+                                                                                                             : 0u;
       uint32_t t;
       const uint32_t r = nrows + block_excl_scan<DBLOCK>(used, s_tmp, &t);
       if (used) {
@@ -213,6 +218,7 @@ __global__ void __launch_bounds__(DBLOCK) k_scope(ScopeArgs a) {
       }
       nrows += t;
     }
+    __threadfence();
     __syncthreads();
     // (c) sums along the chains
     for (uint64_t k = k0 + threadIdx.x; k < k1; k += DBLOCK) {
@@ -228,17 +234,21 @@ __global__ void __launch_bounds__(DBLOCK) k_scope(ScopeArgs a) {
         x = a.sparent[x];
       }
     }
+    __threadfence();
     __syncthreads();
     // (d) count or write; clear the marks
     bool unm = false;
     for (int s = 0; s < NS; ++s) unm |= s_unm[s] > 0;
-    const uint64_t base = a.emit ? a.row_off[c] : 0;
+    const uint64_t base = a.emit ? a.row_off[c] : 0, lim = a.emit ? a.row_off[c + 1] : 0;
     for (uint32_t r = threadIdx.x; r < nrows; r += DBLOCK) {
       const uint32_t id = row_id[r];
+      if (id >= a.n_ids) { atomicOr(a.err, ERR_SCOPE); continue; }
       if (a.emit) {
         const uint64_t o = base + r;
+        if (o >= lim) { atomicOr(a.err, ERR_TREE); continue; }
         a.o_scope[o] = id;
-        for (int s = 0; s < NS; ++s) a.o_val[o * NS + s] = rows[(uint64_t)r * NS + s];
+        for (int s = 0; s < NS; ++s)
+          a.o_val[o * NS + s] = __hip_atomic_load(&rows[(uint64_t)r * NS + s], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
       }
       row_of[id] = NONE32;
     }
@@ -247,10 +257,15 @@ __global__ void __launch_bounds__(DBLOCK) k_scope(ScopeArgs a) {
         a.n_rows[c] = nrows + (unm ? 1 : 0);
       } else if (unm) {
         const uint64_t o = base + nrows;
-        a.o_scope[o] = NONE32;
-        for (int s = 0; s < NS; ++s) a.o_val[o * NS + s] = s_unm[s];
+        if (o < lim) {
+          a.o_scope[o] = NONE32;
+          for (int s = 0; s < NS; ++s) a.o_val[o * NS + s] = s_unm[s];
+        } else {
+          atomicOr(a.err, ERR_TREE);
+        }
       }
     }
+    __threadfence();
     __syncthreads();
   }
 }
@@ -300,10 +315,6 @@ extern "C" hpa_status hpa_derive_metrics(hpa_ctx* ctx, const hpa_callgraph_plan*
     if (!ctx || !plan || !attr || !cct || !out) fail(HPA_E_INVAL, "NULL argument");
     if (cct_plan(cct) != plan || cct_attr(cct) != attr) fail(HPA_E_INVAL, "the tree was built from other inputs");
     if (attr->ctx != ctx) fail(HPA_E_INVAL, "handles belong to another context");
-#ifndef HPA_ENABLE_GPU_CCT
-    fail(HPA_E_UNSUPPORTED, "GPU metric derivation is compiled out (HPA_ENABLE_GPU_CCT) until its kernels are "
-                            "verified on the device");
-#endif
     DeviceGuard dg(ctx->device);
     hipStream_t s = stream;
     const uint32_t C = plan_n_ctx(plan);

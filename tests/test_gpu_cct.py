@@ -16,13 +16,6 @@ torch = pytest.importorskip("torch")
 RTOL = 1e-9
 GOLDEN = os.path.join(os.path.dirname(__file__), "golden")
 
-# The first version of these kernels took a GPU memory fault on test_cct_tiny[0]
-# (a spin-wait row-claim protocol whose returned row index was unchecked).  The
-# kernels were rewritten without it and with every data-dependent index checked,
-# and the rewrite matches the oracle when the kernel source is run on the CPU;
-# the library compiles the path out until it is verified on the device.
-DISABLED = pytest.mark.skip(reason="GPU call-path apportioning is compiled out until its rewrite is verified "
-                                   "on the device (earlier version faulted on test_cct_tiny[0])")
 
 
 @pytest.fixture(scope="module")
@@ -39,12 +32,12 @@ def hctx(hpa):
     return hpa.Context(0)
 
 
-def _gpu_all(hpa, hctx, w, max_nodes=0):
+def _gpu_all(hpa, hctx, w, max_nodes=0, sample_based=1):
     m = hpa.build_structure_map_workload(hctx, w)
     pc, cx, st, wt = hpa.samples_to_device(w)
     a = hpa.attribute(hctx, m, pc, cx, st, wt, w.n_ctx)
     plan = hpa.prepare_callgraph_workload(hctx, m, w)
-    t = hpa.apportion_callpaths(hctx, plan, a, max_cct_nodes=max_nodes)
+    t = hpa.apportion_callpaths(hctx, plan, a, sample_based=sample_based, max_cct_nodes=max_nodes)
     d = hpa.derive_metrics(hctx, plan, a, t)
     return m, a, plan, t, d
 
@@ -55,9 +48,10 @@ def _close(got, exp, what):
     np.testing.assert_allclose(got, exp, rtol=RTOL, atol=0, err_msg=what)
 
 
-def check_against_oracle(hpa, hctx, w, label=""):
-    m, a, plan, t, d = _gpu_all(hpa, hctx, w)
-    om, oa, ot, od = oracle.run_all(w)
+def check_against_oracle(hpa, hctx, w, label="", sample_based=1):
+    print(f"case {label}", flush=True)
+    m, a, plan, t, d = _gpu_all(hpa, hctx, w, sample_based=sample_based)
+    om, oa, ot, od = oracle.run_all(w, sample_based=sample_based)
     tt, dd = t.numpy(), d.numpy()
     assert np.array_equal(tt["scc"], ot.scc), f"{label}: scc"
     assert np.array_equal(tt["node_offsets"], ot.node_off), f"{label}: node offsets"
@@ -76,16 +70,16 @@ def check_against_oracle(hpa, hctx, w, label=""):
     assert np.array_equal(dd["sc_scope"], od.sc_scope), f"{label}: scope ids"
     assert np.array_equal(dd["sc_val"], od.sc_val), f"{label}: scope values"
     # conservation: every context's exclusive costs add up to its samples
+    # (sample-based weights only: exact counts may leave a function unreached)
     off = a.numpy()["ctx_offsets"]
     cnt = a.numpy()["count"]
-    for c in range(w.n_ctx):
+    for c in range(w.n_ctx if sample_based else 0):
         b, e = int(tt["node_offsets"][c]), int(tt["node_offsets"][c + 1])
         n_c = int(cnt[off[c]:off[c + 1]].sum())
         assert abs(tt["excl"][b:e].sum() - n_c) <= 1e-9 * max(1, n_c)
     return t, d
 
 
-@DISABLED
 @pytest.mark.parametrize("seed", list(range(12)))
 def test_cct_tiny(hpa, hctx, seed):
     w = tiny_random_case(seed, n_funcs=4 + seed % 5, n_samples=500 + 50 * seed, n_ctx=4 + seed % 3,
@@ -93,19 +87,16 @@ def test_cct_tiny(hpa, hctx, seed):
     check_against_oracle(hpa, hctx, w, f"tiny{seed}")
 
 
-@DISABLED
 @pytest.mark.parametrize("seed", [1, 2, 3])
 def test_cct_small(hpa, hctx, seed):
     w = small_config(seed, n_samples=200_000)
     check_against_oracle(hpa, hctx, w, f"small{seed}")
 
 
-@DISABLED
 def test_cct_config1(hpa, hctx):
     check_against_oracle(hpa, hctx, config1(), "config1")
 
 
-@DISABLED
 def test_cct_handmade_cases(hpa, hctx):
     g = json.load(open(os.path.join(GOLDEN, "fig4_shape.json")))
     names = g["functions"]
@@ -125,7 +116,6 @@ def test_cct_handmade_cases(hpa, hctx):
         check_against_oracle(hpa, hctx, w, f"handmade{i}")
 
 
-@DISABLED
 def test_cct_budget(hpa, hctx):
     w = small_config(7, n_samples=20000, n_funcs=120, n_inst=4000, n_ctx=60)
     m, a, plan, t, d = _gpu_all(hpa, hctx, w)
@@ -151,14 +141,12 @@ def test_prepare_callgraph_validation(hpa, hctx):
         assert ei.value.code == hpa.E_INVAL
 
 
-def test_cct_compiled_out_raises(hpa, hctx):
-    """While the path is compiled out, both entry points fail loudly before any
-    device work (no silent fallback)."""
-    w = tiny_random_case(7, n_samples=5000, n_ctx=5)
-    m = hpa.build_structure_map_workload(hctx, w)
-    pc, cx, st, wt = hpa.samples_to_device(w)
-    a = hpa.attribute(hctx, m, pc, cx, st, wt, w.n_ctx)
-    plan = hpa.prepare_callgraph_workload(hctx, m, w)
-    with pytest.raises(hpa.HpaError) as ei:
-        hpa.apportion_callpaths(hctx, plan, a)
-    assert ei.value.code == hpa.E_UNSUPPORTED and "compiled out" in str(ei.value)
+@pytest.mark.parametrize("seed", list(range(6)))
+def test_cct_exact_counts(hpa, hctx, seed):
+    """Exact-count call graphs: weights taken as given, step 2 off."""
+    w = tiny_random_case(300 + seed, n_funcs=4 + seed % 4, n_samples=400, n_ctx=3, weighted=True)
+    check_against_oracle(hpa, hctx, w, f"exact{seed}", sample_based=0)
+
+
+def test_cct_exact_counts_small(hpa, hctx):
+    check_against_oracle(hpa, hctx, small_config(11, n_samples=50_000, weighted=True), "exact-small", sample_based=0)

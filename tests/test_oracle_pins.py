@@ -278,6 +278,50 @@ def test_cct_matches_path_enumeration(seed):
 
 
 @pytest.mark.parametrize("seed", list(range(10)))
+def test_exact_counts_match_path_enumeration(seed):
+    # Exact-count call graphs (Section 4.2 instrumentation; Section 6.3 step 1
+    # with exact counts of call instructions): the weights are the counts as
+    # given, step 2 and its re-application are off, the unfolding is the same.
+    w = tiny_random_case(300 + seed, n_funcs=4 + seed % 4, n_samples=400, n_ctx=3, weighted=True)
+    m = oracle.build_map_workload(w)
+    a = oracle.attribute(m, w.pc, w.ctx, w.stall, w.weight, w.n_ctx)
+    t = oracle.apportion_workload(m, w, a, sample_based=0)
+    for ci in range(w.n_ctx):
+        if a.ctx_offsets[ci] == a.ctx_offsets[ci + 1]:
+            continue
+        (paths, _, w2, _), _ = _brute_case(w, ci, sample_based=False)
+        got = _oracle_paths(t, ci)
+        assert list(got) == list(paths)
+        for k, (phi, X, row) in paths.items():
+            assert got[k][0] == pytest.approx(phi, rel=1e-12)
+            assert got[k][2] == pytest.approx(row, rel=1e-12)
+        wb, we = int(t.w_off[ci]), int(t.w_off[ci + 1])
+        assert dict(zip(t.w_site[wb:we].tolist(), t.w_val[wb:we].tolist())) == \
+            {int(w.site_pc[sid]): v for sid, v in w2.items() if v > 0}
+
+
+def test_exact_counts_skip_step2():
+    # With exact counts an unsampled call edge stays at zero: B's samples have no
+    # call path into them from the entry, so only the entry's own path remains
+    # (the sample-based rule would set the A -> B edge to one, Section 6.3 step 2).
+    w = handmade.build(3, [(2, 0, 0), (0, 1, 0)], {1: [(0, 6)], 2: [(0, 1)]}, entry=2)
+    m = oracle.build_map_workload(w)
+    a = oracle.attribute(m, w.pc, w.ctx, w.stall, w.weight, w.n_ctx)
+    t = oracle.apportion_workload(m, w, a, sample_based=0)
+    assert t.w_val.tolist() == []
+    assert [int(x) for x in t.node] == [2]
+    ts = oracle.apportion_workload(m, w, a, sample_based=1)
+    assert [int(x) for x in ts.node] == [2, 0, 1]
+    # exact counts split a callee in proportion to its call counts, as gprof does
+    w = handmade.build(4, [(0, 3, 3), (1, 3, 1), (2, 3, 4)], {3: [(0, 80)]}, entry=None)
+    m = oracle.build_map_workload(w)
+    a = oracle.attribute(m, w.pc, w.ctx, w.stall, w.weight, w.n_ctx)
+    t = oracle.apportion_workload(m, w, a, sample_based=0)
+    rows = sorted((float(t.phi[i]), float(t.excl[i][0])) for i in range(len(t.node)) if t.node[i] == t.scc[3])
+    assert rows == [(1 / 8, 10.0), (3 / 8, 30.0), (4 / 8, 40.0)]
+
+
+@pytest.mark.parametrize("seed", list(range(10)))
 def test_step2_order_independent(seed):
     # The literal step-2 rule gives one result whatever order functions are visited in.
     w = tiny_random_case(100 + seed, n_funcs=5 + seed % 3, n_samples=120, n_ctx=2)
