@@ -208,6 +208,66 @@ hpa_status hpa_lookup_intervals(hpa_ctx* ctx, const hpa_structure_map* map, cons
                                 uint32_t* d_out, int mode, hipStream_t stream);
 
 /* ------------------------------------------------------------------------ */
+/* A7: learned interval index (not in the paper; an index over the starts of  */
+/* the same map whose answers are identical to the plain search)             */
+/* ------------------------------------------------------------------------ */
+
+/* Root network parameters, FP32, in this order: W1[64][2], b1[64],
+ * W2[64][64], b2[64], w3[64], b3 (4417 floats).  Forward pass for input
+ * (x0, x1): h1 = relu(W1 x + b1), h2 = relu(W2 h1 + b2), y = w3 . h2 + b3;
+ * leaf = clamp(floor(y * n_leaves), 0, n_leaves - 1). */
+#define HPA_LEARNED_NPARAM 4417
+
+typedef struct {
+  uint32_t n_leaves;    /* 0: 4096 */
+  uint32_t train_steps; /* Adam steps on the root (0: keep the initial, untrained root) */
+  uint32_t batch;       /* rows per step (0: 8192) */
+  uint32_t train_rows;  /* evenly spaced starts used as training rows (0: min(M, 2^20)) */
+  float lr;             /* initial Adam step size, cosine-decayed (<= 0: 2e-3) */
+  uint32_t window_cap;  /* largest window half-width a leaf keeps (0: 65536) */
+  uint64_t seed;        /* initialisation seed (0: fixed default) */
+} hpa_learned_opts;
+
+typedef struct {
+  uint32_t n_leaves, train_steps;
+  double train_mse;      /* mean squared error of the root on its training rows (rank fraction) */
+  double mean_window;    /* mean over leaves of (window below + window above + 1) */
+  uint32_t max_window;
+  uint64_t uncovered;    /* starts (or start - 1 addresses) whose miss exceeded window_cap */
+  const float* params;   /* device: the root's HPA_LEARNED_NPARAM parameters */
+} hpa_learned_stats;
+
+/* (Re)train the learned index of a map on its interval starts: the root
+ * network by Adam on the device (forward/backward kernels of this library),
+ * then one least-squares linear leaf per root output bucket and each leaf's
+ * error window, evaluated with the lookup's own FP32 expression over every
+ * start and every start - 1.  opts may be NULL (defaults).  Synchronises
+ * `stream` twice.  hpa_build_structure_map with desc->learned = 1 calls this
+ * with the defaults.  Errors: HPA_E_INVAL, HPA_E_UNSUPPORTED (fewer than two
+ * intervals, or more than 2^32), HPA_E_NOMEM, HPA_E_DEVICE. */
+hpa_status hpa_learned_train(hpa_ctx* ctx, hpa_structure_map* map, const hpa_learned_opts* opts, hipStream_t stream);
+
+/* Summary of a map's learned index (params points to device memory owned by
+ * the map).  Errors: HPA_E_INVAL, HPA_E_UNSUPPORTED (no learned index). */
+hpa_status hpa_learned_stats_get(const hpa_structure_map* map, hpa_learned_stats* out);
+
+/* HPA_LOOKUP_LEARNED that also adds, into device memory d_counts[2]
+ * (u64, caller-initialised), the binary-search probes it made and the number
+ * of queries that failed verification and took the plain search.
+ * Asynchronous.  Errors as hpa_lookup_intervals. */
+hpa_status hpa_lookup_learned_counted(hpa_ctx* ctx, const hpa_structure_map* map, const uint64_t* d_pc, uint64_t n,
+                                      uint32_t* d_out, unsigned long long* d_counts, hipStream_t stream);
+
+/* Gradient of the root's loss (1/n) sum_i (y(x_i) - t_i)^2 at parameters
+ * d_params, by the training kernels: d_x is n x 2 FP32 inputs, d_t n FP32
+ * targets (device); d_grad receives HPA_LEARNED_NPARAM gradients followed by
+ * the summed squared error (device, HPA_LEARNED_NPARAM + 1 floats).  Sums are
+ * FP32, per block of 128 rows, then over blocks in order.  Synchronises once.
+ * Errors: HPA_E_INVAL (NULL, n == 0), HPA_E_NOMEM, HPA_E_DEVICE. */
+hpa_status hpa_learned_grad(hpa_ctx* ctx, const float* d_params, const float* d_x, const float* d_t, uint64_t n,
+                            float* d_grad, hipStream_t stream);
+
+/* ------------------------------------------------------------------------ */
 /* A2-A4: attribution (Section 4.2 sample record; Section 4.5 raw metrics)   */
 /* ------------------------------------------------------------------------ */
 

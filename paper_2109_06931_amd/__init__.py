@@ -83,6 +83,19 @@ class _MetricsView(C.Structure):
                 ("host_W", P), ("n_scope_rows", U64), ("sc_offsets", P), ("sc_scope", P), ("sc_val", P)]
 
 
+class _LearnedOpts(C.Structure):
+    _fields_ = [("n_leaves", U32), ("train_steps", U32), ("batch", U32), ("train_rows", U32), ("lr", C.c_float),
+                ("window_cap", U32), ("seed", U64)]
+
+
+class _LearnedStats(C.Structure):
+    _fields_ = [("n_leaves", U32), ("train_steps", U32), ("train_mse", C.c_double), ("mean_window", C.c_double),
+                ("max_window", U32), ("uncovered", U64), ("params", P)]
+
+
+LEARNED_NPARAM = 4417
+
+
 class _StageTime(C.Structure):
     _fields_ = [("name", C.c_char_p), ("ms", C.c_double), ("calls", U64), ("items_in", U64), ("items_out", U64)]
 
@@ -110,6 +123,10 @@ def lib():
         L.hpa_structure_map_free.restype = None
         L.hpa_lookup_intervals.argtypes = [P, P, P, U64, P, I, P]
         L.hpa_attribute.argtypes = [P, P, C.POINTER(_Samples), P, PP]
+        L.hpa_learned_train.argtypes = [P, P, C.POINTER(_LearnedOpts), P]
+        L.hpa_learned_stats_get.argtypes = [P, C.POINTER(_LearnedStats)]
+        L.hpa_lookup_learned_counted.argtypes = [P, P, P, U64, P, P, P]
+        L.hpa_learned_grad.argtypes = [P, P, P, P, U64, P, P]
         L.hpa_attribution_view_get.argtypes = [P, C.POINTER(_AttrView)]
         L.hpa_attribution_free.argtypes = [P]
         L.hpa_attribution_free.restype = None
@@ -154,7 +171,7 @@ def _np(a, dt):
 # device views -> torch tensors
 # ---------------------------------------------------------------------------
 _TYPESTR = {np.dtype(np.uint8): "|u1", np.dtype(np.uint32): "<u4", np.dtype(np.int32): "<i4",
-            np.dtype(np.uint64): "<u8", np.dtype(np.float64): "<f8"}
+            np.dtype(np.uint64): "<u8", np.dtype(np.float64): "<f8", np.dtype(np.float32): "<f4"}
 _hip = None
 
 
@@ -180,7 +197,8 @@ def device_view(ptr, shape, dtype, owner=None):
     shape = tuple(int(x) for x in shape)
     n = int(np.prod(shape)) if shape else 1
     tdt = {np.dtype(np.uint8): torch.uint8, np.dtype(np.uint32): torch.uint32, np.dtype(np.int32): torch.int32,
-           np.dtype(np.uint64): torch.uint64, np.dtype(np.float64): torch.float64}[np.dtype(dtype)]
+           np.dtype(np.uint64): torch.uint64, np.dtype(np.float64): torch.float64,
+           np.dtype(np.float32): torch.float32}[np.dtype(dtype)]
     if n == 0 or not ptr:
         return torch.empty(shape, dtype=tdt, device="cuda")
     try:
@@ -310,6 +328,45 @@ def lookup_intervals(ctx: Context, m: StructureMap, pc, out, mode: int = LOOKUP_
     _check(lib().hpa_lookup_intervals(ctx.h, m.h, _ptr(pc), pc.numel(), _ptr(out), mode,
                                       C.c_void_p(_stream(stream))), "hpa_lookup_intervals")
     return out
+
+
+def learned_train(ctx: Context, m: StructureMap, n_leaves: int = 0, train_steps: int = 2000, batch: int = 0,
+                  train_rows: int = 0, lr: float = 0.0, window_cap: int = 0, seed: int = 0, stream=None):
+    """hpa_learned_train: (re)train the map's learned index (train_steps=0 keeps the untrained root)."""
+    o = _LearnedOpts(int(n_leaves), int(train_steps), int(batch), int(train_rows), float(lr), int(window_cap),
+                     int(seed))
+    _check(lib().hpa_learned_train(ctx.h, m.h, C.byref(o), C.c_void_p(_stream(stream))), "hpa_learned_train")
+    return learned_stats(m)
+
+
+def learned_stats(m: StructureMap) -> dict:
+    """hpa_learned_stats_get as a dict; 'params' is a device tensor view of the root's parameters."""
+    st = _LearnedStats()
+    _check(lib().hpa_learned_stats_get(m.h, C.byref(st)), "hpa_learned_stats_get")
+    return dict(n_leaves=st.n_leaves, train_steps=st.train_steps, train_mse=st.train_mse,
+                mean_window=st.mean_window, max_window=st.max_window, uncovered=st.uncovered,
+                params=device_view(st.params, (LEARNED_NPARAM,), np.float32, m))
+
+
+def lookup_learned_counted(ctx: Context, m: StructureMap, pc, out, counts, stream=None):
+    """hpa_lookup_learned_counted: learned lookup that adds (probes, fallbacks) into counts (2 x uint64)."""
+    _device_arrays((pc, "pc", 8, None, False), (out, "out", 4, pc.numel(), False), (counts, "counts", 8, 2, False))
+    _check(lib().hpa_lookup_learned_counted(ctx.h, m.h, _ptr(pc), pc.numel(), _ptr(out), _ptr(counts),
+                                            C.c_void_p(_stream(stream))), "hpa_lookup_learned_counted")
+    return out
+
+
+def learned_grad(ctx: Context, params, x, t, stream=None):
+    """hpa_learned_grad: gradient (and summed squared error) of the root's mean squared error."""
+    import torch
+    n = t.numel()
+    for a, name, k in ((params, "params", LEARNED_NPARAM), (x, "x", 2 * n), (t, "t", n)):
+        if a.dtype != torch.float32 or not a.is_contiguous() or a.numel() != k or not a.is_cuda:
+            raise ValueError(f"{name} must be a contiguous float32 CUDA tensor of {k} elements")
+    g = torch.empty(LEARNED_NPARAM + 1, dtype=torch.float32, device=params.device)
+    _check(lib().hpa_learned_grad(ctx.h, _ptr(params), _ptr(x), _ptr(t), n, _ptr(g), C.c_void_p(_stream(stream))),
+           "hpa_learned_grad")
+    return g
 
 
 class Attribution:

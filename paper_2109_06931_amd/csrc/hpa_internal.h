@@ -269,5 +269,6 @@ void launch_scope_labels(const hpa_structure_map* m, const uint64_t* pc, uint64_
 void launch_lookup_learned(const hpa_structure_map* m, const uint64_t* pc, uint64_t n, uint32_t* out,
                            hipStream_t s);
 void learned_free(LearnedModel* lm);
+void learned_train(hpa_structure_map* m, const hpa_learned_opts* opts, hipStream_t s);
 
 }  // namespace hpa

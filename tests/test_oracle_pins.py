@@ -568,3 +568,36 @@ def test_conservation_small_and_config1():
             b, e = int(t.node_off[ci]), int(t.node_off[ci + 1])
             n_c = int(a.count[a.ctx_offsets[ci]:a.ctx_offsets[ci + 1]].sum())
             assert abs(t.excl[b:e].sum() - n_c) <= 1e-9 * max(1, n_c)
+
+
+# ---------------------------------------------------------------------------
+# learned index: FP64 reference of the root network (no passage in the paper;
+# the answer itself is the plain search, pinned by the lookup tests above)
+# ---------------------------------------------------------------------------
+
+def test_learned_ref_gradient_matches_central_differences():
+    from oracle import learned_ref as L
+    r = np.random.default_rng(5)
+    p = r.normal(0.0, 0.5, size=L.NPARAM)
+    X = r.random((7, 2))
+    T = r.random(7)
+    g = L.grad(p, X, T)
+    idx = list(range(0, L.NPARAM, 7)) + [L.NPARAM - 1]
+    fd = L.central_differences(p, X, T, idx)
+    np.testing.assert_allclose(g[idx], fd, rtol=1e-5, atol=1e-9)
+
+
+def test_learned_ref_forward_closed_form():
+    # one active path: h1_0 = x0, h2_0 = 2 * h1_0, y = 3 * h2_0 + 0.5 -> y = 6 x0 + 0.5
+    from oracle import learned_ref as L
+    p = np.zeros(L.NPARAM)
+    p[0] = 1.0                                  # W1[0][0]
+    p[2 * 64 + 64 + 0] = 2.0                    # W2[0][0]
+    p[2 * 64 + 64 + 64 * 64 + 64 + 0] = 3.0     # w3[0]
+    p[-1] = 0.5                                 # b3
+    X = np.array([[0.25, 0.9], [0.0, 0.3], [1.0, 0.0]])
+    y, _ = L.forward(p, X)
+    assert y.tolist() == [2.0, 0.5, 6.5]
+    # a negative input is cut by the first ReLU
+    y, _ = L.forward(p, np.array([[-0.5, 0.0]]))
+    assert y.tolist() == [0.5]
