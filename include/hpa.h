@@ -444,6 +444,75 @@ typedef struct {
 hpa_status hpa_metrics_view_get(const hpa_metrics* m, hpa_metrics_view* out);
 void hpa_metrics_free(hpa_metrics* m);
 
+/* ------------------------------------------------------------------------ */
+/* A9: serving ingest (Section 4.1: sample buffers delivered as they fill;   */
+/* Section 4.5: the raw metric is a sum, so arrival order does not matter)   */
+/* ------------------------------------------------------------------------ */
+
+typedef struct {
+  uint32_t n_profiles;        /* independent profiles (streams), ids 0..n_profiles-1 */
+  uint32_t n_ctx;             /* contexts per profile; a record's ctx must be < n_ctx (<= 2^28) */
+  uint64_t table_slots;       /* per-profile key table capacity, rounded up to a power of two (0: 2^22) */
+  uint64_t pc_slots;          /* distinct-PC table shared by all profiles (0: 2^20; <= 2^31) */
+  uint64_t max_batch_bytes;   /* device staging per in-flight batch; also the largest buffer (0: 64 MiB) */
+  uint32_t n_slots;           /* batches in flight at once, one HIP stream each (0: 4) */
+  uint32_t max_batch_buffers; /* buffers coalesced into one launch (0: 512) */
+  uint64_t hbm_budget;        /* device bytes the server may hold: state + staging (0: 200e9) */
+} hpa_server_opts;
+
+typedef struct {
+  uint64_t buffers, samples, bytes, batches, errors;
+  uint64_t max_inflight_bytes;
+  double p50_us, p99_us, max_us, mean_us; /* submit -> attributed latency over completed buffers */
+  double span_s;                          /* first submit to last completion */
+} hpa_server_stats;
+
+typedef struct hpa_server hpa_server;
+
+/* Create a server over a structure map: per-profile device state (a key
+ * table of (ctx, pc, stall) -> u64 count per profile, and one table of
+ * distinct PCs) and n_slots staging areas, all allocated here; the state and
+ * staging together must fit hbm_budget (else HPA_E_BUDGET).  A worker thread
+ * owned by the server batches queued buffers into free slots and launches
+ * their ingest on the slots' own streams, so batches overlap.  The map must
+ * outlive the server.  Errors: HPA_E_INVAL, HPA_E_UNSUPPORTED, HPA_E_BUDGET,
+ * HPA_E_NOMEM, HPA_E_DEVICE. */
+hpa_status hpa_server_create(hpa_ctx* ctx, const hpa_structure_map* map, const hpa_server_opts* opts,
+                             hpa_server** out);
+
+/* Queue one sample buffer of `profile`: host memory holding, back to back,
+ * pc u64[n], ctx u32[n], stall u8[n] (13 n bytes, 8-byte aligned; each
+ * record counts once).  The buffer is read asynchronously and must stay
+ * valid and unchanged until its ticket completes; pinned memory (hipHostMalloc)
+ * gives the fastest copies.  Thread-safe.  Never blocks on the device.
+ * Errors: HPA_E_INVAL, HPA_E_BUDGET (buffer larger than the batch staging),
+ * HPA_E_DEVICE (the server stopped after a device error). */
+hpa_status hpa_server_submit(hpa_server* srv, uint32_t profile, const void* buffer, uint64_t n_samples,
+                             uint64_t* ticket);
+
+/* Block until the ticket's buffer is folded into its profile's state;
+ * *latency_us (may be NULL) receives submit -> completion time.  Returns the
+ * batch's status: HPA_E_INVAL when a record of the batch had ctx >= n_ctx or
+ * stall >= 16, HPA_E_BUDGET when a table ran out of slots (the profiles of
+ * that batch then hold an undefined part of it). */
+hpa_status hpa_server_wait(hpa_server* srv, uint64_t ticket, double* latency_us);
+
+/* Block until every submitted buffer has completed. */
+hpa_status hpa_server_drain(hpa_server* srv);
+
+/* Counters and latency percentiles of completed buffers; reset != 0 clears them. */
+hpa_status hpa_server_stats_get(hpa_server* srv, int reset, hpa_server_stats* out);
+
+/* The profile's state as an attribution (same layout and guarantees as
+ * hpa_attribute's output, built from the completed buffers): ingest pauses
+ * while the table is read, then the table's entries go through the
+ * attribution path on `stream`.  Call hpa_server_drain first to include
+ * everything submitted.  Synchronises `stream`.  Errors: as hpa_attribute. */
+hpa_status hpa_server_snapshot(hpa_server* srv, uint32_t profile, hipStream_t stream, hpa_attribution** out);
+
+/* Stop the worker after the queued buffers are done and free the server. */
+void hpa_server_destroy(hpa_server* srv);
+
 #ifdef __cplusplus
 }
 #endif

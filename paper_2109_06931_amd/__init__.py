@@ -96,6 +96,17 @@ class _LearnedStats(C.Structure):
 LEARNED_NPARAM = 4417
 
 
+class _ServerOpts(C.Structure):
+    _fields_ = [("n_profiles", U32), ("n_ctx", U32), ("table_slots", U64), ("pc_slots", U64),
+                ("max_batch_bytes", U64), ("n_slots", U32), ("max_batch_buffers", U32), ("hbm_budget", U64)]
+
+
+class _ServerStats(C.Structure):
+    _fields_ = [("buffers", U64), ("samples", U64), ("bytes", U64), ("batches", U64), ("errors", U64),
+                ("max_inflight_bytes", U64), ("p50_us", C.c_double), ("p99_us", C.c_double),
+                ("max_us", C.c_double), ("mean_us", C.c_double), ("span_s", C.c_double)]
+
+
 class _StageTime(C.Structure):
     _fields_ = [("name", C.c_char_p), ("ms", C.c_double), ("calls", U64), ("items_in", U64), ("items_out", U64)]
 
@@ -124,6 +135,14 @@ def lib():
         L.hpa_lookup_intervals.argtypes = [P, P, P, U64, P, I, P]
         L.hpa_attribute.argtypes = [P, P, C.POINTER(_Samples), P, PP]
         L.hpa_learned_train.argtypes = [P, P, C.POINTER(_LearnedOpts), P]
+        L.hpa_server_create.argtypes = [P, P, C.POINTER(_ServerOpts), PP]
+        L.hpa_server_submit.argtypes = [P, U32, P, U64, C.POINTER(U64)]
+        L.hpa_server_wait.argtypes = [P, U64, C.POINTER(C.c_double)]
+        L.hpa_server_drain.argtypes = [P]
+        L.hpa_server_stats_get.argtypes = [P, I, C.POINTER(_ServerStats)]
+        L.hpa_server_snapshot.argtypes = [P, U32, P, PP]
+        L.hpa_server_destroy.argtypes = [P]
+        L.hpa_server_destroy.restype = None
         L.hpa_learned_stats_get.argtypes = [P, C.POINTER(_LearnedStats)]
         L.hpa_lookup_learned_counted.argtypes = [P, P, P, U64, P, P, P]
         L.hpa_learned_grad.argtypes = [P, P, P, P, U64, P, P]
@@ -527,3 +546,79 @@ def samples_to_device(w, device="cuda"):
     st = torch.from_numpy(w.stall).to(device)
     wt = None if w.weight is None else torch.from_numpy(w.weight.view(np.int32)).to(device).view(torch.uint32)
     return pc, cx, st, wt
+
+
+# ---------------------------------------------------------------------------
+# serving ingest
+# ---------------------------------------------------------------------------
+def sample_buffer(pc, ctx_ids, stall, pinned: bool = True):
+    """A host buffer in the layout hpa_server_submit reads: pc u64[n], ctx u32[n],
+    stall u8[n] back to back (a uint8 torch tensor, pinned by default)."""
+    import torch
+    pc = np.ascontiguousarray(pc, np.uint64)
+    cx = np.ascontiguousarray(ctx_ids, np.uint32)
+    st = np.ascontiguousarray(stall, np.uint8)
+    n = len(pc)
+    if len(cx) != n or len(st) != n:
+        raise ValueError("pc, ctx and stall must have the same length")
+    t = torch.empty(13 * n + 8, dtype=torch.uint8, pin_memory=pinned)
+    a = t.numpy()
+    a[:8 * n] = pc.view(np.uint8)
+    a[8 * n:12 * n] = cx.view(np.uint8)
+    a[12 * n:13 * n] = st
+    t.n_samples = n
+    return t
+
+
+class Server:
+    """hpa_server: continuous ingest of sample buffers into per-profile device state."""
+
+    def __init__(self, ctx: Context, m: StructureMap, n_profiles: int, n_ctx: int, table_slots: int = 0,
+                 pc_slots: int = 0, max_batch_bytes: int = 0, n_slots: int = 0, max_batch_buffers: int = 0,
+                 hbm_budget: int = 0):
+        self.ctx, self.map = ctx, m
+        o = _ServerOpts(int(n_profiles), int(n_ctx), int(table_slots), int(pc_slots), int(max_batch_bytes),
+                        int(n_slots), int(max_batch_buffers), int(hbm_budget))
+        self.h = C.c_void_p()
+        _check(lib().hpa_server_create(ctx.h, m.h, C.byref(o), C.byref(self.h)), "hpa_server_create")
+        self._held = {}
+
+    def submit(self, profile: int, buf) -> int:
+        """Queue a buffer made by sample_buffer(); it is kept alive until its ticket completes."""
+        t = U64(0)
+        _check(lib().hpa_server_submit(self.h, int(profile), C.c_void_p(buf.data_ptr()), int(buf.n_samples),
+                                       C.byref(t)), "hpa_server_submit")
+        self._held[t.value] = buf
+        return t.value
+
+    def wait(self, ticket: int) -> float:
+        lat = C.c_double(0.0)
+        try:
+            _check(lib().hpa_server_wait(self.h, int(ticket), C.byref(lat)), "hpa_server_wait")
+        finally:
+            self._held.pop(ticket, None)
+        return lat.value
+
+    def drain(self):
+        _check(lib().hpa_server_drain(self.h), "hpa_server_drain")
+        self._held.clear()
+
+    def stats(self, reset: bool = False) -> dict:
+        st = _ServerStats()
+        _check(lib().hpa_server_stats_get(self.h, int(bool(reset)), C.byref(st)), "hpa_server_stats_get")
+        return {k: getattr(st, k) for k, _ in _ServerStats._fields_}
+
+    def snapshot(self, profile: int, stream=None) -> Attribution:
+        h = C.c_void_p()
+        _check(lib().hpa_server_snapshot(self.h, int(profile), C.c_void_p(_stream(stream)), C.byref(h)),
+               "hpa_server_snapshot")
+        return Attribution(self.ctx, self.map, h)
+
+    def close(self):
+        if getattr(self, "h", None) and _lib is not None:
+            _lib.hpa_server_destroy(self.h)
+            self.h = None
+            self._held.clear()
+
+    def __del__(self):
+        self.close()
