@@ -445,6 +445,85 @@ hpa_status hpa_metrics_view_get(const hpa_metrics* m, hpa_metrics_view* out);
 void hpa_metrics_free(hpa_metrics* m);
 
 /* ------------------------------------------------------------------------ */
+/* Several profiles: unification, statistics, sparse layouts (Sections 4.5,  */
+/* 6.1 and 6.2), and combination of runs (Section 4.7)                       */
+/* ------------------------------------------------------------------------ */
+
+typedef struct hpa_unified hpa_unified;
+
+/* Unify the contexts of n_profiles attributions made on one map with one
+ * context count: the unified contexts are the sorted union of their (ctx, pc)
+ * pairs; metric m of a context is its sample count with stall reason m.
+ * Builds, on the device:
+ *  - CMS (context-major sparse): per unified context c, entries
+ *    [cms_ctx_off[c], cms_ctx_off[c+1]) of (cms_pid, cms_val) ordered by
+ *    metric then profile; its non-empty metrics are the pairs
+ *    (cms_mid[j], cms_mstart[j]) for j in [cms_m_off[c], cms_m_off[c+1]);
+ *  - PMS (profile-major sparse): per profile p, entries
+ *    [pms_off[p], pms_off[p+1]) of (pms_mid, pms_val) ordered by context then
+ *    metric, with (pms_ctx[h], pms_cstart[h]) for h in
+ *    [pms_c_off[p], pms_c_off[p+1]) marking where each of its contexts starts;
+ *  - statistics per CMS metric entry j (context cms_mctx[j], metric
+ *    cms_mid[j]) over all profiles, an absent value counting as 0: sum, min,
+ *    max (u64), mean = sum / P, population standard deviation and coefficient
+ *    of variation std / mean (0 when the mean is 0) in FP64.
+ * Synchronises `stream` (a fixed number of times, independent of P).
+ * Errors: HPA_E_INVAL (no profiles, NULL, attributions of other maps,
+ * context counts or contexts), HPA_E_NOMEM, HPA_E_DEVICE. */
+hpa_status hpa_unify_profiles(hpa_ctx* ctx, uint32_t n_profiles, const hpa_attribution* const* profiles,
+                              hipStream_t stream, hpa_unified** out);
+
+typedef struct {
+  uint32_t n_profiles;
+  uint64_t n_contexts;         /* unified (ctx, pc) contexts */
+  uint64_t n_nonzeros;         /* (profile, context, metric) entries */
+  uint64_t n_metric_entries;   /* non-empty (context, metric) pairs */
+  uint64_t n_profile_contexts; /* (profile, context) pairs */
+  const uint32_t* ctx;
+  const uint64_t* pc;
+  const uint32_t* scope;
+  const uint64_t *cms_ctx_off, *cms_m_off;
+  const uint8_t* cms_mid;
+  const uint64_t* cms_mstart;
+  const uint32_t* cms_mctx;
+  const uint32_t* cms_pid;
+  const uint64_t* cms_val;
+  const uint64_t *pms_off, *pms_c_off;
+  const uint32_t* pms_ctx;
+  const uint64_t* pms_cstart;
+  const uint8_t* pms_mid;
+  const uint64_t* pms_val;
+  const uint64_t *st_sum, *st_min, *st_max;
+  const double *st_mean, *st_std, *st_cov;
+} hpa_unified_view;
+
+hpa_status hpa_unified_view_get(const hpa_unified* u, hpa_unified_view* out);
+void hpa_unified_free(hpa_unified* u);
+
+#define HPA_SPARSE_CMS 0
+#define HPA_SPARSE_PMS 1
+
+/* Write one sparse layout to a file: eight u64 header words (magic
+ * 0x45535241505350, format, contexts, profiles, metrics = 16, non-zeros,
+ * metric entries (CMS) or profile contexts (PMS), section count), the
+ * sections' u64 file offsets, then the sections, each at an 8-aligned offset
+ * found by an exclusive scan of their sizes: ctx u32[C], pc u64[C], then for
+ * CMS cms_ctx_off, cms_m_off, cms_mid, cms_mstart, cms_pid, cms_val and for
+ * PMS pms_off, pms_c_off, pms_ctx, pms_cstart, pms_mid, pms_val.  Device
+ * data reach the file through a host buffer of at most round_bytes
+ * (0: 64 MiB), one round at a time.  Errors: HPA_E_INVAL (path, format),
+ * HPA_E_DEVICE (I/O or copy failure). */
+hpa_status hpa_unified_write(const hpa_unified* u, const char* path, int format, uint64_t round_bytes,
+                             hipStream_t stream);
+
+/* Combine runs: per (ctx, pc, stall) key, the sum of the runs' counts, as one
+ * attribution (same layout as hpa_attribute's).  The runs must share a map
+ * and a context count.  Synchronises `stream`.  Errors: as
+ * hpa_unify_profiles, and as hpa_attribute. */
+hpa_status hpa_combine_runs(hpa_ctx* ctx, uint32_t n_runs, const hpa_attribution* const* runs, hipStream_t stream,
+                            hpa_attribution** out);
+
+/* ------------------------------------------------------------------------ */
 /* A9: serving ingest (Section 4.1: sample buffers delivered as they fill;   */
 /* Section 4.5: the raw metric is a sum, so arrival order does not matter)   */
 /* ------------------------------------------------------------------------ */

@@ -107,6 +107,17 @@ class _ServerStats(C.Structure):
                 ("max_us", C.c_double), ("mean_us", C.c_double), ("span_s", C.c_double)]
 
 
+class _UnifiedView(C.Structure):
+    _fields_ = [("n_profiles", U32), ("n_contexts", U64), ("n_nonzeros", U64), ("n_metric_entries", U64),
+                ("n_profile_contexts", U64)] + [(n, P) for n in (
+                    "ctx", "pc", "scope", "cms_ctx_off", "cms_m_off", "cms_mid", "cms_mstart", "cms_mctx", "cms_pid",
+                    "cms_val", "pms_off", "pms_c_off", "pms_ctx", "pms_cstart", "pms_mid", "pms_val", "st_sum",
+                    "st_min", "st_max", "st_mean", "st_std", "st_cov")]
+
+
+SPARSE_CMS, SPARSE_PMS = 0, 1
+
+
 class _StageTime(C.Structure):
     _fields_ = [("name", C.c_char_p), ("ms", C.c_double), ("calls", U64), ("items_in", U64), ("items_out", U64)]
 
@@ -135,6 +146,12 @@ def lib():
         L.hpa_lookup_intervals.argtypes = [P, P, P, U64, P, I, P]
         L.hpa_attribute.argtypes = [P, P, C.POINTER(_Samples), P, PP]
         L.hpa_learned_train.argtypes = [P, P, C.POINTER(_LearnedOpts), P]
+        L.hpa_unify_profiles.argtypes = [P, U32, P, P, PP]
+        L.hpa_unified_view_get.argtypes = [P, C.POINTER(_UnifiedView)]
+        L.hpa_unified_free.argtypes = [P]
+        L.hpa_unified_free.restype = None
+        L.hpa_unified_write.argtypes = [P, C.c_char_p, I, U64, P]
+        L.hpa_combine_runs.argtypes = [P, U32, P, P, PP]
         L.hpa_server_create.argtypes = [P, P, C.POINTER(_ServerOpts), PP]
         L.hpa_server_submit.argtypes = [P, U32, P, U64, C.POINTER(U64)]
         L.hpa_server_wait.argtypes = [P, U64, C.POINTER(C.c_double)]
@@ -622,3 +639,67 @@ class Server:
 
     def __del__(self):
         self.close()
+
+
+# ---------------------------------------------------------------------------
+# several profiles: unification, statistics, sparse layouts, combined runs
+# ---------------------------------------------------------------------------
+class Unified:
+    """hpa_unified: unified contexts of several profiles, CMS/PMS layouts and statistics."""
+
+    def __init__(self, ctx, profiles, h):
+        self.ctx, self.profiles, self.h = ctx, profiles, h
+        v = _UnifiedView()
+        _check(lib().hpa_unified_view_get(h, C.byref(v)), "hpa_unified_view_get")
+        self._v = v
+
+    def tensors(self):
+        v = self._v
+        U, K, NM, NH, P_ = v.n_contexts, v.n_nonzeros, v.n_metric_entries, v.n_profile_contexts, v.n_profiles
+        d = lambda p, n, dt: device_view(p, (n,), dt, self)  # noqa: E731
+        return dict(ctx=d(v.ctx, U, np.uint32), pc=d(v.pc, U, np.uint64), scope=d(v.scope, U, np.uint32),
+                    cms_ctx_off=d(v.cms_ctx_off, U + 1, np.uint64), cms_m_off=d(v.cms_m_off, U + 1, np.uint64),
+                    cms_mid=d(v.cms_mid, NM, np.uint8), cms_mstart=d(v.cms_mstart, NM, np.uint64),
+                    cms_mctx=d(v.cms_mctx, NM, np.uint32), cms_pid=d(v.cms_pid, K, np.uint32),
+                    cms_val=d(v.cms_val, K, np.uint64), pms_off=d(v.pms_off, P_ + 1, np.uint64),
+                    pms_c_off=d(v.pms_c_off, P_ + 1, np.uint64), pms_ctx=d(v.pms_ctx, NH, np.uint32),
+                    pms_cstart=d(v.pms_cstart, NH, np.uint64), pms_mid=d(v.pms_mid, K, np.uint8),
+                    pms_val=d(v.pms_val, K, np.uint64), st_sum=d(v.st_sum, NM, np.uint64),
+                    st_min=d(v.st_min, NM, np.uint64), st_max=d(v.st_max, NM, np.uint64),
+                    st_mean=d(v.st_mean, NM, np.float64), st_std=d(v.st_std, NM, np.float64),
+                    st_cov=d(v.st_cov, NM, np.float64))
+
+    def numpy(self):
+        return {k: t.cpu().numpy() for k, t in self.tensors().items()}
+
+    def write(self, path: str, fmt: int = SPARSE_CMS, round_bytes: int = 0, stream=None):
+        _check(lib().hpa_unified_write(self.h, str(path).encode(), int(fmt), int(round_bytes),
+                                       C.c_void_p(_stream(stream))), "hpa_unified_write")
+
+    def __del__(self):
+        if getattr(self, "h", None) and _lib is not None:
+            _lib.hpa_unified_free(self.h)
+            self.h = None
+
+
+def _handles(attrs):
+    arr = (C.c_void_p * len(attrs))(*[a.h.value if hasattr(a.h, "value") else a.h for a in attrs])
+    return arr
+
+
+def unify_profiles(ctx: Context, profiles, stream=None) -> Unified:
+    """hpa_unify_profiles over a list of Attribution objects."""
+    h = C.c_void_p()
+    arr = _handles(profiles)
+    _check(lib().hpa_unify_profiles(ctx.h, len(profiles), C.cast(arr, C.c_void_p), C.c_void_p(_stream(stream)),
+                                    C.byref(h)), "hpa_unify_profiles")
+    return Unified(ctx, list(profiles), h)
+
+
+def combine_runs(ctx: Context, runs, stream=None) -> Attribution:
+    """hpa_combine_runs: per key, the sum of the runs' counts."""
+    h = C.c_void_p()
+    arr = _handles(runs)
+    _check(lib().hpa_combine_runs(ctx.h, len(runs), C.cast(arr, C.c_void_p), C.c_void_p(_stream(stream)),
+                                  C.byref(h)), "hpa_combine_runs")
+    return Attribution(ctx, runs[0].map, h)

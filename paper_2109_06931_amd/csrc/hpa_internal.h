@@ -270,5 +270,7 @@ void launch_lookup_learned(const hpa_structure_map* m, const uint64_t* pc, uint6
                            hipStream_t s);
 void learned_free(LearnedModel* lm);
 void learned_train(hpa_structure_map* m, const hpa_learned_opts* opts, hipStream_t s);
+// in-place exclusive scan of n u64 values; *d_total (device) receives the sum
+void exscan_u64(hpa_ctx* ctx, unsigned long long* v, uint64_t n, unsigned long long* d_total, hipStream_t s);
 
 }  // namespace hpa

@@ -601,3 +601,95 @@ def test_learned_ref_forward_closed_form():
     # a negative input is cut by the first ReLU
     y, _ = L.forward(p, np.array([[-0.5, 0.0]]))
     assert y.tolist() == [0.5]
+
+
+# ---------------------------------------------------------------------------
+# several profiles: statistics (Section 4.5), sparse layouts (Section 6.2),
+# combination of runs (Section 4.7)
+# ---------------------------------------------------------------------------
+
+class _A:
+    def __init__(self, keys):
+        ks = sorted(keys)
+        self.ctx = np.array([k[0] for k in ks], np.uint32)
+        self.pc = np.array([k[1] for k in ks], np.uint64)
+        self.stall = np.array([k[2] for k in ks], np.uint8)
+        self.count = np.array([keys[k] for k in ks], np.uint64)
+
+
+def test_unify_identical_profiles_have_no_spread():
+    from oracle import unify_ref as U
+    keys = {(0, 0x100, 0): 5, (0, 0x100, 3): 2, (1, 0x80, 1): 7}
+    r = U.unify([_A(keys)] * 4)
+    assert r["st_sum"].tolist() == [20, 8, 28]
+    assert r["st_min"].tolist() == r["st_max"].tolist() == [5, 2, 7]
+    assert r["st_mean"].tolist() == [5.0, 2.0, 7.0]
+    assert r["st_std"].tolist() == [0.0] * 3 and r["st_cov"].tolist() == [0.0] * 3
+
+
+def test_unify_single_holder_closed_form():
+    # one of P profiles holds x, the others nothing: mean x/P, std x sqrt(P-1)/P, CoV sqrt(P-1)
+    from oracle import unify_ref as U
+    P, x = 5, 40
+    profs = [_A({})] * (P - 1) + [_A({(2, 0x40, 9): x})]
+    r = U.unify(profs)
+    assert r["st_min"].tolist() == [0] and r["st_max"].tolist() == [x]
+    assert r["st_mean"][0] == pytest.approx(x / P, rel=1e-15)
+    assert r["st_std"][0] == pytest.approx(x * np.sqrt(P - 1) / P, rel=1e-15)
+    assert r["st_cov"][0] == pytest.approx(np.sqrt(P - 1), rel=1e-15)
+    assert r["cms_pid"].tolist() == [P - 1]
+
+
+def test_unify_layouts_transpose_and_space():
+    # CMS and PMS hold the same (profile, context, metric, value) entries; the CMS
+    # size is 2 nnz (pids, vals) + metric pairs + contexts + 1 (Section 6.2)
+    from oracle import unify_ref as U
+    r0 = np.random.default_rng(3)
+    profs = []
+    for p in range(4):
+        keys = {}
+        for _ in range(60):
+            keys[(int(r0.integers(0, 5)), 0x1000 + 16 * int(r0.integers(0, 9)), int(r0.integers(0, 16)))] = \
+                int(r0.integers(1, 50))
+        profs.append(_A(keys))
+    r = U.unify(profs)
+    cms = set()
+    for c in range(len(r["ctx"])):
+        for j in range(int(r["cms_m_off"][c]), int(r["cms_m_off"][c + 1])):
+            a = int(r["cms_mstart"][j])
+            b = int(r["cms_mstart"][j + 1]) if j + 1 < len(r["cms_mstart"]) else len(r["cms_pid"])
+            for i in range(a, b):
+                cms.add((int(r["cms_pid"][i]), c, int(r["cms_mid"][j]), int(r["cms_val"][i])))
+    pms = set()
+    for p in range(4):
+        hs = range(int(r["pms_c_off"][p]), int(r["pms_c_off"][p + 1]))
+        for h in hs:
+            a = int(r["pms_cstart"][h])
+            b = int(r["pms_cstart"][h + 1]) if h + 1 < hs.stop else int(r["pms_off"][p + 1])
+            for i in range(a, b):
+                pms.add((p, int(r["pms_ctx"][h]), int(r["pms_mid"][i]), int(r["pms_val"][i])))
+    nnz = sum(len(a.count) for a in profs)
+    assert cms == pms and len(cms) == nnz
+    size = 2 * len(r["cms_pid"]) + len(r["cms_mid"]) + len(r["ctx"]) + 1
+    assert size == 2 * nnz + len(r["cms_mid"]) + len(r["ctx"]) + 1
+    # the statistics' sums equal the per-key totals of the combination
+    comb = U.combine(profs)
+    tot = {(int(c), int(p), int(s)): int(n) for c, p, s, n in zip(comb["ctx"], comb["pc"], comb["stall"],
+                                                                 comb["count"])}
+    for j in range(len(r["st_sum"])):
+        c = int(r["st_ctx"][j])
+        assert tot[(int(r["ctx"][c]), int(r["pc"][c]), int(r["st_mid"][j]))] == int(r["st_sum"][j])
+
+
+def test_combine_equals_attribution_of_all_samples():
+    # Section 4.7: combining runs sums their raw metrics; attributing the union of
+    # the runs' samples at once gives the same keys (Section 4.5: a raw metric is a sum)
+    from oracle import unify_ref as U
+    w = small_config(21, n_samples=30000)
+    m = oracle.build_map_workload(w)
+    cuts = [0, 7000, 19000, 30000]
+    runs = [oracle.attribute(m, w.pc[a:b], w.ctx[a:b], w.stall[a:b], None, w.n_ctx) for a, b in zip(cuts, cuts[1:])]
+    allr = oracle.attribute(m, w.pc, w.ctx, w.stall, None, w.n_ctx)
+    comb = U.combine(runs)
+    for f in ["ctx", "pc", "stall", "count"]:
+        assert np.array_equal(comb[f], getattr(allr, f))
