@@ -190,7 +190,8 @@ __device__ inline uint8_t ctx_kind(uint64_t n) { return n <= (uint64_t)UHALF ? K
 // list.  A unit starts at context c when c is the first context, when c or
 // c - 1 is not packable (over T/2 samples), every MAXC contexts, where the
 // running count of packable samples crosses a multiple of T/2 between c - 1
-// and c, and where the group changes.
+// and c, where the group changes, and (a batch of profiles) where the profile
+// changes.
 struct PlanVals {
   unsigned long long n, r, ps, big, ch, bs;  // samples, runs, packable samples, big contexts, chunks, big samples
 };
@@ -268,7 +269,7 @@ __global__ void __launch_bounds__(1024) k_plan_tile_scan(unsigned long long* __r
 
 __global__ void __launch_bounds__(PLAN_BLOCK)
 k_plan_starts(const unsigned long long* __restrict__ hist, uint32_t n_ctx, const uint32_t* __restrict__ grp,
-              const unsigned long long* __restrict__ tile_off, uint64_t* __restrict__ sbase,
+              const uint32_t* __restrict__ pgrp, const unsigned long long* __restrict__ tile_off, uint64_t* __restrict__ sbase,
               uint64_t* __restrict__ rbase, uint32_t* __restrict__ big_ctx, uint64_t* __restrict__ big_sbase,
               uint64_t* __restrict__ big_chunk, uint8_t* __restrict__ start, uint32_t* __restrict__ tile_starts) {
   __shared__ unsigned long long s_tmp[PLAN_BLOCK / WAVE + 1];
@@ -298,7 +299,7 @@ k_plan_starts(const unsigned long long* __restrict__ hist, uint32_t n_ctx, const
     const uint8_t kp = c > 0 ? ctx_kind(n_prev) : KIND_S;
     const uint64_t ps_prev = ps - (c > 0 && kp == KIND_S ? n_prev : 0);
     st = c == 0 || k != KIND_S || kp != KIND_S || (c % MAXC) == 0 || (ps / UHALF) != (ps_prev / UHALF) ||
-         (grp && grp[c] != grp[c - 1]);
+         (grp && grp[c] != grp[c - 1]) || (pgrp && pgrp[c] != pgrp[c - 1]);
     start[c] = (uint8_t)st;
   }
   uint32_t tot;
@@ -338,44 +339,48 @@ k_plan_units(const unsigned long long* __restrict__ hist, uint32_t n_ctx, const 
 // kept units per tile, their scan, and the new unit list.
 // Between merge rounds: the merged count becomes the unit count.
 __global__ void k_set_units(PlanInfo* __restrict__ info) { info->n_units = info->n_merged; }
+// Without merge rounds the plan's units are the final ones.
+__global__ void k_keep_units(PlanInfo* __restrict__ info) { info->n_merged = info->n_units; }
 
 __device__ inline bool merge_pair(const uint32_t* unit_begin, const int32_t* unit_big, const uint64_t* sbase,
-                                  const uint32_t* grp, uint32_t nu, uint32_t a) {
+                                  const uint32_t* grp, const uint32_t* pgrp, uint32_t nu, uint32_t a) {
   if (a + 1 >= nu) return false;
   const int32_t ba = unit_big[a], bb = unit_big[a + 1];
   if (ba >= 0 || ba != bb) return false;
   const uint32_t c0 = unit_begin[a], c1 = unit_begin[a + 1], c2 = unit_begin[a + 2];
   if (grp && grp[c0] != grp[c1]) return false;
+  if (pgrp && pgrp[c0] != pgrp[c1]) return false;
   return c2 - c0 <= (uint32_t)MAXC && sbase[c2] - sbase[c0] <= (uint64_t)UT;
 }
 
 __device__ inline uint32_t unit_kept(const uint32_t* unit_begin, const int32_t* unit_big, const uint64_t* sbase,
-                                     const uint32_t* grp, uint32_t nu, uint32_t u) {
+                                     const uint32_t* grp, const uint32_t* pgrp, uint32_t nu, uint32_t u) {
   if (u >= nu) return 0u;
-  return (u & 1u) && merge_pair(unit_begin, unit_big, sbase, grp, nu, u - 1) ? 0u : 1u;
+  return (u & 1u) && merge_pair(unit_begin, unit_big, sbase, grp, pgrp, nu, u - 1) ? 0u : 1u;
 }
 
 __global__ void __launch_bounds__(PLAN_BLOCK)
 k_merge_count(const uint32_t* __restrict__ unit_begin, const int32_t* __restrict__ unit_big,
-              const uint64_t* __restrict__ sbase, const uint32_t* __restrict__ grp, const PlanInfo* __restrict__ info,
-              uint32_t* __restrict__ tile_sum) {
+              const uint64_t* __restrict__ sbase, const uint32_t* __restrict__ grp, const uint32_t* __restrict__ pgrp,
+              const PlanInfo* __restrict__ info, uint32_t* __restrict__ tile_sum) {
   __shared__ uint32_t s_tmp[PLAN_BLOCK / WAVE + 1];
   const uint32_t nu = info->n_units;
   const uint32_t u = blockIdx.x * PLAN_BLOCK + threadIdx.x;
   uint32_t tot;
-  block_excl_scan<PLAN_BLOCK>(unit_kept(unit_begin, unit_big, sbase, grp, nu, u), s_tmp, &tot);
+  block_excl_scan<PLAN_BLOCK>(unit_kept(unit_begin, unit_big, sbase, grp, pgrp, nu, u), s_tmp, &tot);
   if (threadIdx.x == 0) tile_sum[blockIdx.x] = tot;
 }
 
 __global__ void __launch_bounds__(PLAN_BLOCK)
 k_merge_write(const uint32_t* __restrict__ unit_begin, const int32_t* __restrict__ unit_big,
-              const uint64_t* __restrict__ sbase, const uint32_t* __restrict__ grp, uint32_t n_ctx,
+              const uint64_t* __restrict__ sbase, const uint32_t* __restrict__ grp, const uint32_t* __restrict__ pgrp,
+              uint32_t n_ctx,
               const uint32_t* __restrict__ tile_off, uint32_t* __restrict__ out_begin, int32_t* __restrict__ out_big,
               PlanInfo* __restrict__ info) {
   __shared__ uint32_t s_tmp[PLAN_BLOCK / WAVE + 1];
   const uint32_t nu = info->n_units;
   const uint32_t u = blockIdx.x * PLAN_BLOCK + threadIdx.x;
-  const uint32_t keep = unit_kept(unit_begin, unit_big, sbase, grp, nu, u);
+  const uint32_t keep = unit_kept(unit_begin, unit_big, sbase, grp, pgrp, nu, u);
   uint32_t tot;
   const uint32_t v = tile_off[blockIdx.x] + block_excl_scan<PLAN_BLOCK>(keep, s_tmp, &tot);
   if (keep) {
@@ -720,6 +725,23 @@ __global__ void k_scatter(const uint64_t* __restrict__ pc, const uint32_t* __res
   }
 }
 
+struct MapDev {
+  const uint64_t* start;
+  const uint64_t* end;
+  const uint32_t* scope;
+  uint64_t n_iv;
+};
+
+// A batch of profiles: every profile has its own structure map, and its
+// contexts are numbered globally from ctx_base.  Kernels that handle one
+// context (or a unit of contexts of one profile) look its profile up.
+struct ProfMap {
+  DenseDev dd;
+  MapDev md;
+  uint32_t ctx_base;
+  int dense;
+};
+
 // ----------------------------------------------------------------------------
 // Shared pieces of the sort workgroups (units and big-context chunks)
 // ----------------------------------------------------------------------------
@@ -943,13 +965,6 @@ __device__ inline void sort_reduce(SortSmem& sm, Gathered<WEIGHTED>& g, uint64_t
   }
 }
 
-struct MapDev {
-  const uint64_t* start;
-  const uint64_t* end;
-  const uint32_t* scope;
-  uint64_t n_iv;
-};
-
 struct OutDev {
   uint32_t* ctx;
   uint64_t* pc;
@@ -1165,6 +1180,8 @@ struct UnitArgs {
   int32_t kind;                // the unit class a sort launch handles (UNIT_PLAIN or UNIT_PART)
   const uint32_t* vreal;       // real context of every virtual one (null: no split contexts)
   const UnitDesc* desc;        // per unit
+  const ProfMap* pm;           // batch of profiles: per profile maps (null: one profile, dd / dense above)
+  const uint32_t* cprof;       // batch: profile of every (real) context
 };
 
 // Stage the unit's unique keys, counts and decoding parameters.
@@ -1227,7 +1244,14 @@ __global__ void __launch_bounds__(UBLOCK) k_units32(UnitArgs a) {
   const uint64_t n_u = d.s1 - s0;
   // context bases, window tables and (when they fit) the runs, behind one barrier
   for (uint32_t l = threadIdx.x; l <= ce - cb; l += UBLOCK) s_sb[l] = a.sbase[cb + l];
-  const DenseDev t = stage_dense(sm, a.dd);  // LDS view (empty when the map has no dense coordinates)
+  DenseDev src = a.dd;
+  int map_dense = a.dense;
+  if (a.pm) {  // a unit holds contexts of one profile
+    const ProfMap& pmp = a.pm[a.cprof[a.vreal ? a.vreal[cb] : cb]];
+    src = pmp.dd;
+    map_dense = pmp.dense;
+  }
+  const DenseDev t = stage_dense(sm, src);  // LDS view (empty when the map has no dense coordinates)
   const uint64_t r0 = SCATTERED ? 0 : d.r0, r1 = SCATTERED ? 0 : d.r1;
   const bool staged = !SCATTERED && r1 - r0 <= (uint64_t)RUN_CAP;
   if (staged)
@@ -1237,7 +1261,7 @@ __global__ void __launch_bounds__(UBLOCK) k_units32(UnitArgs a) {
   gather<SCATTERED, WEIGHTED>(g, s0, n_u, cb, a.grouped, r0, r1, s_sb, ce - cb, a.pc, a.stall, a.weight,
                               &a.info->err, sm.runs, staged);
   bool dense = false;
-  if (a.dense) {
+  if (map_dense) {
     densify(sm, g, n_u, t);
     __syncthreads();
     dense = sm.far == 0;
@@ -1345,7 +1369,16 @@ __global__ void __launch_bounds__(WBLOCK) k_units_write(UnitArgs a, const uint64
   if (m.nU == 0) return;
   const bool dense = (m.flags & UM_DENSE) != 0, wide = (m.flags & UM_WIDE) != 0;
   DenseDev t = a.dd;
-  if (a.dense) {
+  int map_dense = a.dense;
+  uint32_t cbase = 0;
+  if (a.pm) {
+    const ProfMap& pmp = a.pm[a.cprof[a.vreal ? a.vreal[du.cb] : du.cb]];
+    t = pmp.dd;
+    map_dense = pmp.dense;
+    map = pmp.md;
+    cbase = pmp.ctx_base;
+  }
+  if (map_dense) {
     for (uint32_t i = threadIdx.x; i < t.n_win; i += WBLOCK) {
       s_lo[i] = t.lo[i];
       s_hi[i] = t.hi[i];
@@ -1387,7 +1420,7 @@ __global__ void __launch_bounds__(WBLOCK) k_units_write(UnitArgs a, const uint64
       const uint32_t lc = (uint32_t)(k[q] >> (m.pcb + 4));
       const uint64_t v = m.lo + (((k[q] >> 4) & pmask) << m.tz);
       const uint64_t o = o0 + ui;
-      out.ctx[o] = a.vreal ? a.vreal[cb + lc] : cb + lc;
+      out.ctx[o] = (a.vreal ? a.vreal[cb + lc] : cb + lc) - cbase;
       out.stall[o] = (uint8_t)(k[q] & 15);
       out.count[o] = c[q];
       if (dense) {
@@ -1395,7 +1428,10 @@ __global__ void __launch_bounds__(WBLOCK) k_units_write(UnitArgs a, const uint64
         out.scope[o] = t.scope_of[v];
       } else {
         out.pc[o] = v;
-        if (a.dense) {  // a unit with a pc off the dense grid: binary search
+        // a unit with a pc off the dense grid, or a batch profile without
+        // dense coordinates: binary search (a single map without them is
+        // labelled by its own pass afterwards)
+        if (map_dense || a.pm) {
           const uint32_t iv = find_interval(map.start, map.end, map.n_iv, v, 0, map.n_iv);
           out.scope[o] = iv == NONE32 ? NONE32 : map.scope[iv];
         }
@@ -1423,6 +1459,8 @@ struct BigArgs {
   DenseDev dd;
   int dense;
   const uint32_t* vreal;  // real context of every virtual one (null: no split contexts)
+  const ProfMap* pm;      // batch of profiles (null: one profile)
+  const uint32_t* cprof;
 };
 
 struct ListBuf {
@@ -1512,13 +1550,20 @@ __global__ void __launch_bounds__(UBLOCK) k_big_chunks(BigArgs a, ListBuf o) {
   const uint64_t s0 = a.sbase[c] + j * UT;
   const uint64_t n_u = min((uint64_t)UT, nc - j * UT);
   if (threadIdx.x == 0) { s_sb[0] = a.sbase[c]; s_sb[1] = a.sbase[c + 1]; }
-  const DenseDev t = stage_dense(sm, a.dd);  // LDS view (empty when the map has no dense coordinates)
+  DenseDev src = a.dd;
+  int map_dense = a.dense;
+  if (a.pm) {
+    const ProfMap& pmp = a.pm[a.cprof[a.vreal ? a.vreal[c] : c]];
+    src = pmp.dd;
+    map_dense = pmp.dense;
+  }
+  const DenseDev t = stage_dense(sm, src);  // LDS view (empty when the map has no dense coordinates)
   __syncthreads();
   Gathered<WEIGHTED> g;
   gather<SCATTERED, WEIGHTED>(g, s0, n_u, c, a.grouped, SCATTERED ? 0 : a.rbase[c], SCATTERED ? 0 : a.rbase[c + 1],
                               s_sb, 1, a.pc, a.stall, a.weight, &a.info->err, sm.runs);
   bool dense = false;
-  if (a.dense) {
+  if (map_dense) {
     densify(sm, g, n_u, t);
     __syncthreads();
     dense = sm.far == 0;
@@ -1652,11 +1697,18 @@ __global__ void __launch_bounds__(256) k_big_write(BigArgs a, ListBuf fin, const
       unsigned long long cnt = fin.cnt[base + e];
       for (uint64_t f = e + 1; f < len && fin.pc[base + f] == p && fin.stall[base + f] == s; ++f) cnt += fin.cnt[base + f];
       uint64_t o = big_out[b] + slot0 + done + ex;
-      out.ctx[o] = a.vreal ? a.vreal[c] : c;
+      const uint32_t rc = a.vreal ? a.vreal[c] : c;
+      if (a.pm) {
+        const ProfMap& pmp = a.pm[a.cprof[rc]];
+        out.ctx[o] = rc - pmp.ctx_base;
+        out.scope[o] = scope_of_pc(pmp.dd, pmp.dense != 0, pmp.md.start, pmp.md.end, pmp.md.scope, pmp.md.n_iv, p);
+      } else {
+        out.ctx[o] = rc;
+        if (a.dense) out.scope[o] = scope_of_pc(a.dd, true, map.start, map.end, map.scope, map.n_iv, p);
+      }
       out.pc[o] = p;
       out.stall[o] = s;
       out.count[o] = cnt;
-      if (a.dense) out.scope[o] = scope_of_pc(a.dd, true, map.start, map.end, map.scope, map.n_iv, p);
     }
     done += tot;
   }
@@ -1667,15 +1719,28 @@ __global__ void __launch_bounds__(256) k_big_write(BigArgs a, ListBuf fin, const
 
 using namespace hpa;
 
-extern "C" hpa_status hpa_attribute(hpa_ctx* ctx, const hpa_structure_map* map, const hpa_samples* smp,
-                                    hipStream_t stream, hpa_attribution** out) {
-  return guard([&] {
-    if (!ctx || !map || !smp || !out) fail(HPA_E_INVAL, "NULL argument");
-    if (map->ctx != ctx) fail(HPA_E_INVAL, "map belongs to another context");
-    if (smp->n && (!smp->pc || !smp->ctx || !smp->stall)) fail(HPA_E_INVAL, "NULL sample array");
-    if (smp->n_ctx == 0 || smp->n_ctx >= 0x7FFFFFFFu) fail(HPA_E_INVAL, "n_ctx out of range");
-    if (smp->n >= (1ull << 40)) fail(HPA_E_INVAL, "too many samples for one call");
-    DeviceGuard dg(ctx->device);
+namespace hpa {
+
+// Run-time parameters of the pipeline (chosen by the batch autotuner).
+struct Knobs {
+  uint32_t merge_rounds = 2;    // rounds of adjacent unit-pair merges
+  uint32_t scan_wg_per_cu = 4;  // workgroups per CU of the context scan
+};
+
+// A batch of profiles for one pipeline run: per profile maps and the profile
+// of every global context (device), and the profiles' maps (host).
+struct BatchRun {
+  const ProfMap* pm = nullptr;
+  const uint32_t* cprof = nullptr;
+};
+
+// The attribution pipeline.  With `batch`, the samples' contexts are global
+// ids over the batch's profiles (units never mix profiles, each unit and big
+// context uses its profile's map, output contexts are local to their profile)
+// and big contexts always take the chunk path.
+hpa_attribution* attribute_impl(hpa_ctx* ctx, const hpa_structure_map* map, const BatchRun* batch,
+                                const hpa_samples* smp, hipStream_t stream, const Knobs& kn) {
+  {
     hipStream_t s = stream;
     const uint64_t n = smp->n;
     const uint32_t C = smp->n_ctx;
@@ -1696,8 +1761,7 @@ extern "C" hpa_status hpa_attribute(hpa_ctx* ctx, const hpa_structure_map* map, 
       HPA_HIP(hipMemsetAsync(A->ctx_offsets.p, 0, ((uint64_t)C + 1) * 8, s));
       HPA_HIP(hipStreamSynchronize(s));
       A->n_keys = 0;
-      *out = hold.release();
-      return;
+      return hold.release();
     }
     StageTimer tm(ctx, s);
     // --- scan ctx, plan ---
@@ -1712,7 +1776,7 @@ extern "C" hpa_status hpa_attribute(hpa_ctx* ctx, const hpa_structure_map* map, 
       uint64_t tiles = (n + SCAN_TILE - 1) / SCAN_TILE;
       // as many workgroups as are resident at once (four per CU at its
       // 33 KB of LDS), each looping over tiles
-      unsigned grid = (unsigned)std::min<uint64_t>(tiles, (uint64_t)ctx->n_cu * 4);
+      unsigned grid = (unsigned)std::min<uint64_t>(tiles, (uint64_t)ctx->n_cu * kn.scan_wg_per_cu);
       k_scan_ctx<<<grid, SCAN_BLOCK, 0, s>>>(smp->ctx, n, C, d_hist.as<unsigned long long>(), d_runs.as<Run>(),
                                              run_cap, d_info.as<PlanInfo>());
       HPA_HIP(hipGetLastError());
@@ -1731,7 +1795,7 @@ extern "C" hpa_status hpa_attribute(hpa_ctx* ctx, const hpa_structure_map* map, 
     tm.end(n, 0);
     const bool weighted = smp->weight != nullptr;
     // --- split of big contexts by coordinate range (run list and dense map only) ---
-    const bool split = !scattered && map->dense && info.n_bigall > 0;
+    const bool split = !batch && !scattered && map->dense && info.n_bigall > 0;
     uint32_t CV = C;  // contexts after the split
     DBuf d_vhist, d_vreal, d_vgrp, d_vbase, d_vsolo, d_bhist, d_bflag, d_partof, d_psum, d_nparts;
     uint32_t bshift = 0;
@@ -1799,7 +1863,8 @@ extern "C" hpa_status hpa_attribute(hpa_ctx* ctx, const hpa_structure_map* map, 
       k_plan_tile_scan<<<1, 1024, 0, s>>>(d_psums.as<unsigned long long>(), ptiles, CV, d_sbase.as<uint64_t>(),
                                           d_rbase.as<uint64_t>(), d_bsb.as<uint64_t>(), d_bch.as<uint64_t>(),
                                           d_info.as<PlanInfo>());
-      k_plan_starts<<<ptiles, PLAN_BLOCK, 0, s>>>(vh, CV, vg, d_psums.as<unsigned long long>(), d_sbase.as<uint64_t>(),
+      const uint32_t* pg = batch ? batch->cprof : nullptr;
+      k_plan_starts<<<ptiles, PLAN_BLOCK, 0, s>>>(vh, CV, vg, pg, d_psums.as<unsigned long long>(), d_sbase.as<uint64_t>(),
                                                  d_rbase.as<uint64_t>(), d_bctx.as<uint32_t>(), d_bsb.as<uint64_t>(),
                                                  d_bch.as<uint64_t>(), d_pstart.as<uint8_t>(), d_pts.as<uint32_t>());
       k_tile_scan<<<1, 1024, 0, s>>>(d_pts.as<uint32_t>(), ptiles, d_pts.as<uint32_t>() + ptiles);
@@ -1810,20 +1875,23 @@ extern "C" hpa_status hpa_attribute(hpa_ctx* ctx, const hpa_structure_map* map, 
       // each round reads the unit count the previous one left in n_units
       DBuf d_ubeg2(ctx, ((uint64_t)CV + 1) * 4, s);
       DBuf d_ubig2(ctx, ((uint64_t)CV + 1) * 4, s);
-      for (int round = 0; round < 2; ++round) {
+      if (kn.merge_rounds == 0) k_keep_units<<<1, 1, 0, s>>>(d_info.as<PlanInfo>());
+      for (uint32_t round = 0; round < kn.merge_rounds; ++round) {
         if (round) {
           k_set_units<<<1, 1, 0, s>>>(d_info.as<PlanInfo>());
         }
+        const uint32_t* pgm = pg;
         k_merge_count<<<ptiles, PLAN_BLOCK, 0, s>>>(d_ubeg.as<uint32_t>(), d_ubig.as<int32_t>(), d_sbase.as<uint64_t>(),
-                                                   vg, d_info.as<PlanInfo>(), d_pts.as<uint32_t>());
+                                                   vg, pgm, d_info.as<PlanInfo>(), d_pts.as<uint32_t>());
         k_tile_scan<<<1, 1024, 0, s>>>(d_pts.as<uint32_t>(), ptiles, d_pts.as<uint32_t>() + ptiles);
         k_merge_write<<<ptiles, PLAN_BLOCK, 0, s>>>(d_ubeg.as<uint32_t>(), d_ubig.as<int32_t>(), d_sbase.as<uint64_t>(),
-                                                   vg, CV, d_pts.as<uint32_t>(), d_ubeg2.as<uint32_t>(),
+                                                   vg, pgm, CV, d_pts.as<uint32_t>(), d_ubeg2.as<uint32_t>(),
                                                    d_ubig2.as<int32_t>(), d_info.as<PlanInfo>());
         HPA_HIP(hipGetLastError());
         std::swap(d_ubeg, d_ubeg2);
         std::swap(d_ubig, d_ubig2);
       }
+      HPA_HIP(hipGetLastError());
     }
     HPA_HIP(hipMemcpyAsync(&info, d_info.p, sizeof(info), hipMemcpyDeviceToHost, s));
     HPA_HIP(hipStreamSynchronize(s));
@@ -1883,6 +1951,8 @@ extern "C" hpa_status hpa_attribute(hpa_ctx* ctx, const hpa_structure_map* map, 
     ba.dd = dd;
     ba.dense = map->dense ? 1 : 0;
     ba.vreal = vreal;
+    ba.pm = batch ? batch->pm : nullptr;
+    ba.cprof = batch ? batch->cprof : nullptr;
     if (info.n_big) {
       tm.begin("big_sort");
       const uint64_t bs = info.big_samples;
@@ -1946,7 +2016,8 @@ extern "C" hpa_status hpa_attribute(hpa_ctx* ctx, const hpa_structure_map* map, 
                 d_ubeg.as<uint32_t>(), d_ubig.as<int32_t>(), d_info.as<PlanInfo>(), NU, C, dd,
                 map->dense ? 1 : 0, d_meta.as<UnitMeta>(), d_ucnt.as<uint32_t>(), d_skey.as<uint32_t>(),
                 d_shi.as<uint32_t>(), weighted ? nullptr : d_scnt.as<uint32_t>(),
-                weighted ? d_scnt.as<unsigned long long>() : nullptr, UNIT_PLAIN, vreal, d_udesc.as<UnitDesc>()};
+                weighted ? d_scnt.as<unsigned long long>() : nullptr, UNIT_PLAIN, vreal, d_udesc.as<UnitDesc>(),
+                batch ? batch->pm : nullptr, batch ? batch->cprof : nullptr};
     // the narrow launch over plain units is timed on its own: it is the
     // dominant kernel; the launches for wide keys and for parts follow
 #define HPA_UNITS(W, S, A, NAME)                          \
@@ -1994,7 +2065,7 @@ extern "C" hpa_status hpa_attribute(hpa_ctx* ctx, const hpa_structure_map* map, 
       HPA_HIP(hipGetLastError());
       tm.end();
     }
-    if (!map->dense) {
+    if (!batch && !map->dense) {
       // no dense coordinates: label every key with a binary search
       tm.begin("scope_labels");
       launch_scope_labels(map, A->pc.as<uint64_t>(), n, &d_info.as<PlanInfo>()->total_keys, A->scope.as<uint32_t>(),
@@ -2022,7 +2093,22 @@ extern "C" hpa_status hpa_attribute(hpa_ctx* ctx, const hpa_structure_map* map, 
       if (!map->dense) tm.items("scope_labels", info.total_keys, info.total_keys);
       tm.collect();
     }
-    *out = hold.release();
+    return hold.release();
+  }
+}
+
+}  // namespace hpa
+
+extern "C" hpa_status hpa_attribute(hpa_ctx* ctx, const hpa_structure_map* map, const hpa_samples* smp,
+                                    hipStream_t stream, hpa_attribution** out) {
+  return guard([&] {
+    if (!ctx || !map || !smp || !out) fail(HPA_E_INVAL, "NULL argument");
+    if (map->ctx != ctx) fail(HPA_E_INVAL, "map belongs to another context");
+    if (smp->n && (!smp->pc || !smp->ctx || !smp->stall)) fail(HPA_E_INVAL, "NULL sample array");
+    if (smp->n_ctx == 0 || smp->n_ctx >= 0x7FFFFFFFu) fail(HPA_E_INVAL, "n_ctx out of range");
+    if (smp->n >= (1ull << 40)) fail(HPA_E_INVAL, "too many samples for one call");
+    DeviceGuard dg(ctx->device);
+    *out = attribute_impl(ctx, map, nullptr, smp, stream, Knobs{});
   });
 }
 
