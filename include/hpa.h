@@ -312,6 +312,53 @@ hpa_status hpa_attribution_view_get(const hpa_attribution* a, hpa_attribution_vi
 void hpa_attribution_free(hpa_attribution* a);
 
 /* ------------------------------------------------------------------------ */
+/* Batches of profiles (Section 6.1: profiles of threads and GPU streams are */
+/* processed as concurrent tasks; Section 6.2: rounds under a memory cap)    */
+/* ------------------------------------------------------------------------ */
+
+typedef struct {
+  const hpa_structure_map* map; /* the profile's structure map */
+  uint64_t n_samples;           /* its records: the next n_samples of the batch arrays */
+  uint32_t n_ctx;               /* its contexts; its records' ctx values are < n_ctx */
+} hpa_profile_desc;
+
+typedef struct {
+  uint64_t max_round_samples; /* samples per round (0: 2^31); a larger profile forms a round of its own */
+  int autotune;               /* 1: time the run-time parameters on a pilot (<= 2^26 samples of the first
+                                 round) and keep the fastest in the context for later calls */
+  uint32_t merge_rounds;      /* without autotune: rounds of unit-pair merges, 0..3 (default 2 when opts is NULL) */
+  uint32_t scan_wg_per_cu;    /* without autotune: context-scan workgroups per compute unit (0: 4) */
+} hpa_batch_opts;
+
+typedef struct {
+  uint32_t n_rounds, merge_rounds, scan_wg_per_cu, autotuned;
+  uint64_t total_keys;
+  double tune_ms; /* host time spent autotuning (0 when the context already had parameters) */
+} hpa_batch_info;
+
+typedef struct hpa_batch hpa_batch;
+
+/* Attribute many profiles at once.  `samples` holds every profile's records
+ * back to back in profile order (device SoA as for hpa_attribute; n is the
+ * total, n_ctx is ignored).  Profiles are grouped into rounds of consecutive
+ * profiles; in a round the contexts of all profiles are numbered globally and
+ * every stage of the attribution runs once for the whole round (each unit of
+ * the sort holds contexts of one profile and uses that profile's map).  Each
+ * profile's result equals hpa_attribute on its own records, byte for byte.
+ * Synchronises `stream` a fixed number of times per round.  Errors: as
+ * hpa_attribute (HPA_E_INVAL also when the profiles' counts do not add up to
+ * samples->n or a record's ctx is not below its profile's n_ctx). */
+hpa_status hpa_attribute_batched(hpa_ctx* ctx, uint32_t n_profiles, const hpa_profile_desc* profiles,
+                                 const hpa_samples* samples, const hpa_batch_opts* opts, hipStream_t stream,
+                                 hpa_batch** out);
+
+/* One profile's result, as the view of its own attribution (device pointers
+ * into the batch's arrays, ctx and ctx_offsets local to the profile). */
+hpa_status hpa_batch_profile_view(const hpa_batch* b, uint32_t profile, hpa_attribution_view* out);
+hpa_status hpa_batch_info_get(const hpa_batch* b, hpa_batch_info* out);
+void hpa_batch_free(hpa_batch* b);
+
+/* ------------------------------------------------------------------------ */
 /* A5: GPU calling context tree (Section 6.3)                                */
 /* ------------------------------------------------------------------------ */
 

@@ -118,6 +118,19 @@ class _UnifiedView(C.Structure):
 SPARSE_CMS, SPARSE_PMS = 0, 1
 
 
+class _ProfileDesc(C.Structure):
+    _fields_ = [("map", P), ("n_samples", U64), ("n_ctx", U32)]
+
+
+class _BatchOpts(C.Structure):
+    _fields_ = [("max_round_samples", U64), ("autotune", I), ("merge_rounds", U32), ("scan_wg_per_cu", U32)]
+
+
+class _BatchInfo(C.Structure):
+    _fields_ = [("n_rounds", U32), ("merge_rounds", U32), ("scan_wg_per_cu", U32), ("autotuned", U32),
+                ("total_keys", U64), ("tune_ms", C.c_double)]
+
+
 class _StageTime(C.Structure):
     _fields_ = [("name", C.c_char_p), ("ms", C.c_double), ("calls", U64), ("items_in", U64), ("items_out", U64)]
 
@@ -146,6 +159,11 @@ def lib():
         L.hpa_lookup_intervals.argtypes = [P, P, P, U64, P, I, P]
         L.hpa_attribute.argtypes = [P, P, C.POINTER(_Samples), P, PP]
         L.hpa_learned_train.argtypes = [P, P, C.POINTER(_LearnedOpts), P]
+        L.hpa_attribute_batched.argtypes = [P, U32, P, C.POINTER(_Samples), C.POINTER(_BatchOpts), P, PP]
+        L.hpa_batch_profile_view.argtypes = [P, U32, C.POINTER(_AttrView)]
+        L.hpa_batch_info_get.argtypes = [P, C.POINTER(_BatchInfo)]
+        L.hpa_batch_free.argtypes = [P]
+        L.hpa_batch_free.restype = None
         L.hpa_unify_profiles.argtypes = [P, U32, P, P, PP]
         L.hpa_unified_view_get.argtypes = [P, C.POINTER(_UnifiedView)]
         L.hpa_unified_free.argtypes = [P]
@@ -703,3 +721,66 @@ def combine_runs(ctx: Context, runs, stream=None) -> Attribution:
     _check(lib().hpa_combine_runs(ctx.h, len(runs), C.cast(arr, C.c_void_p), C.c_void_p(_stream(stream)),
                                   C.byref(h)), "hpa_combine_runs")
     return Attribution(ctx, runs[0].map, h)
+
+
+# ---------------------------------------------------------------------------
+# batches of profiles
+# ---------------------------------------------------------------------------
+class _BatchProfile(Attribution):
+    """One profile's result inside a batch (views into the batch's arrays)."""
+
+    def __init__(self, batch, p):
+        self.ctx, self.map, self.h, self._batch = batch.ctx, batch.maps[p], None, batch
+        v = _AttrView()
+        _check(lib().hpa_batch_profile_view(batch.h, p, C.byref(v)), "hpa_batch_profile_view")
+        self.n_keys, self.n_ctx, self._v = v.n_keys, v.n_ctx, v
+
+    def __del__(self):
+        pass
+
+
+class Batch:
+    """hpa_batch: the results of hpa_attribute_batched, one view per profile."""
+
+    def __init__(self, ctx, maps, h):
+        self.ctx, self.maps, self.h = ctx, maps, h
+
+    def profile(self, p: int) -> Attribution:
+        return _BatchProfile(self, p)
+
+    def info(self) -> dict:
+        i = _BatchInfo()
+        _check(lib().hpa_batch_info_get(self.h, C.byref(i)), "hpa_batch_info_get")
+        return {k: getattr(i, k) for k, _ in _BatchInfo._fields_}
+
+    def __len__(self):
+        return len(self.maps)
+
+    def __del__(self):
+        if getattr(self, "h", None) and _lib is not None:
+            _lib.hpa_batch_free(self.h)
+            self.h = None
+
+
+def attribute_batched(ctx: Context, maps, n_samples, n_ctx, pc, ctx_ids, stall, weight=None,
+                      max_round_samples: int = 0, autotune: bool = False, merge_rounds: int = 2,
+                      scan_wg_per_cu: int = 0, stream=None) -> Batch:
+    """hpa_attribute_batched: maps / n_samples / n_ctx per profile; pc, ctx_ids (local per profile), stall
+    (and weight) are the profiles' records back to back as CUDA tensors."""
+    n = pc.numel() if hasattr(pc, "numel") else None
+    _device_arrays((pc, "pc", 8, None, False), (ctx_ids, "ctx_ids", 4, n, False), (stall, "stall", 1, n, False),
+                   (weight, "weight", 4, n, True))
+    P_ = len(maps)
+    if len(n_samples) != P_ or len(n_ctx) != P_:
+        raise ValueError("maps, n_samples and n_ctx must have one entry per profile")
+    if int(sum(int(x) for x in n_samples)) != n:
+        raise ValueError("the profiles' sample counts must add up to the records given")
+    descs = (_ProfileDesc * P_)(*[_ProfileDesc(m.h, int(k), int(c)) for m, k, c in zip(maps, n_samples, n_ctx)])
+    s = _Samples()
+    s.pc, s.ctx, s.stall, s.weight = _ptr(pc), _ptr(ctx_ids), _ptr(stall), _ptr(weight)
+    s.n, s.n_ctx = n, 1
+    o = _BatchOpts(int(max_round_samples), int(bool(autotune)), int(merge_rounds), int(scan_wg_per_cu))
+    h = C.c_void_p()
+    _check(lib().hpa_attribute_batched(ctx.h, P_, C.cast(descs, C.c_void_p), C.byref(s), C.byref(o),
+                                       C.c_void_p(_stream(stream)), C.byref(h)), "hpa_attribute_batched")
+    return Batch(ctx, list(maps), h)

@@ -31,6 +31,7 @@
 // When runs are short (shuffled input) the run list would cost more than the
 // samples themselves; the samples are then scattered into context order first.
 #include <algorithm>
+#include <chrono>
 #include <memory>
 
 #include "block_prims.h"
@@ -2127,3 +2128,273 @@ extern "C" hpa_status hpa_attribution_view_get(const hpa_attribution* a, hpa_att
 }
 
 extern "C" void hpa_attribution_free(hpa_attribution* a) { delete a; }
+
+// ============================================================================
+// A batch of profiles (Section 6.1: profiles processed as concurrent tasks):
+// the profiles' contexts are numbered globally, so one run of the pipeline
+// attributes every profile of a round at once -- each stage is one launch
+// over the whole round, and the hardware spreads the round's units over the
+// chip however uneven the profiles are.  Rounds keep the working set under a
+// preset sample count (the out-of-core rounds of Section 6.2).
+// ============================================================================
+namespace hpa {
+namespace {
+
+// global context of every record of a round: local ctx + its profile's base
+__global__ void __launch_bounds__(256)
+k_global_ctx(const uint32_t* __restrict__ ctx, uint64_t n, const uint64_t* __restrict__ soff,
+             const uint32_t* __restrict__ cbase, uint32_t P, uint32_t* __restrict__ g, PlanInfo* __restrict__ info) {
+  for (uint64_t i = (uint64_t)blockIdx.x * 256 + threadIdx.x; i < n; i += (uint64_t)gridDim.x * 256) {
+    uint32_t lo = 0, hi = P;  // last profile with soff <= i
+    while (hi - lo > 1) {
+      const uint32_t mid = (lo + hi) >> 1;
+      if (soff[mid] <= i) lo = mid;
+      else hi = mid;
+    }
+    const uint32_t c = ctx[i];
+    if (c >= cbase[lo + 1] - cbase[lo]) {
+      atomicOr(&info->err, (uint32_t)ERR_CTX);
+      g[i] = 0;
+    } else {
+      g[i] = cbase[lo] + c;
+    }
+  }
+}
+
+__global__ void __launch_bounds__(256)
+k_fill_cprof(const uint32_t* __restrict__ cbase, uint32_t P, uint32_t G, uint32_t* __restrict__ cprof) {
+  for (uint32_t c = blockIdx.x * 256 + threadIdx.x; c < G; c += gridDim.x * 256) {
+    uint32_t lo = 0, hi = P;
+    while (hi - lo > 1) {
+      const uint32_t mid = (lo + hi) >> 1;
+      if (cbase[mid] <= c) lo = mid;
+      else hi = mid;
+    }
+    cprof[c] = lo;
+  }
+}
+
+// Per profile of a round: first key, and its context offsets rebased to it.
+__global__ void __launch_bounds__(256)
+k_rebase(const uint64_t* __restrict__ ctx_off, const uint32_t* __restrict__ cbase, uint32_t P,
+         uint64_t* __restrict__ first_key, uint64_t* __restrict__ rebased) {
+  const uint32_t total = cbase[P] + P;  // C_p + 1 entries per profile
+  for (uint32_t e = blockIdx.x * 256 + threadIdx.x; e < total; e += gridDim.x * 256) {
+    uint32_t lo = 0, hi = P;  // last profile whose entries start at or before e
+    while (hi - lo > 1) {
+      const uint32_t mid = (lo + hi) >> 1;
+      if (cbase[mid] + mid <= e) lo = mid;
+      else hi = mid;
+    }
+    const uint32_t j = e - (cbase[lo] + lo);
+    const uint64_t k0 = ctx_off[cbase[lo]];
+    rebased[e] = ctx_off[cbase[lo] + j] - k0;
+    if (j == 0) first_key[lo] = k0;
+  }
+  if (blockIdx.x == 0 && threadIdx.x == 0) first_key[P] = ctx_off[cbase[P]];
+}
+
+}  // namespace
+}  // namespace hpa
+
+struct hpa_batch {
+  hpa_ctx* ctx = nullptr;
+  struct Round {
+    hpa_attribution* a = nullptr;
+    DBuf rebased;
+  };
+  std::vector<Round> rounds;
+  struct Prof {
+    uint32_t round, n_ctx;
+    uint64_t key0, n_keys, reb0;  // first key in the round, keys, first rebased entry
+  };
+  std::vector<Prof> prof;
+  hpa_batch_info info{};
+  ~hpa_batch() {
+    for (auto& r : rounds)
+      if (r.a) hpa_attribution_free(r.a);
+  }
+};
+
+namespace {
+
+struct RoundPlan {
+  uint32_t p0, p1;  // profiles [p0, p1)
+  uint64_t s0, s1;  // samples
+};
+
+// One round: device tables, global contexts, the pipeline, per-profile offsets.
+void run_round(hpa_ctx* ctx, const hpa_profile_desc* pd, const hpa_samples* smp, const RoundPlan& r,
+               const std::vector<uint64_t>& soff_all, hipStream_t s, const Knobs& kn, hpa_batch* B, bool keep) {
+  const uint32_t P = r.p1 - r.p0;
+  std::vector<ProfMap> pm(P);
+  std::vector<uint32_t> cbase(P + 1);
+  std::vector<uint64_t> soff(P + 1);
+  uint64_t G = 0;
+  for (uint32_t i = 0; i < P; ++i) {
+    const hpa_structure_map* m = pd[r.p0 + i].map;
+    cbase[i] = (uint32_t)G;
+    soff[i] = soff_all[r.p0 + i] - r.s0;
+    pm[i].dd = DenseDev{m->win_lo.as<uint64_t>(), m->win_hi.as<uint64_t>(), m->win_d.as<uint64_t>(),
+                        m->scope_of.as<uint32_t>(), m->n_win, m->dense_tz};
+    pm[i].md = MapDev{m->start.as<uint64_t>(), m->end.as<uint64_t>(), m->scope.as<uint32_t>(), m->n_iv};
+    pm[i].ctx_base = (uint32_t)G;
+    pm[i].dense = m->dense ? 1 : 0;
+    G += pd[r.p0 + i].n_ctx;
+  }
+  cbase[P] = (uint32_t)G;
+  soff[P] = r.s1 - r.s0;
+  DBuf d_pm = upload(ctx, pm, s), d_cbase = upload(ctx, cbase, s), d_soff = upload(ctx, soff, s);
+  DBuf d_cprof(ctx, std::max<uint64_t>(G, 1) * 4, s);
+  k_fill_cprof<<<grid_for(G, 256, ctx->n_cu * 8), 256, 0, s>>>(d_cbase.as<uint32_t>(), P, (uint32_t)G,
+                                                               d_cprof.as<uint32_t>());
+  const uint64_t n = r.s1 - r.s0;
+  DBuf d_g(ctx, std::max<uint64_t>(n, 1) * 4, s), d_info(ctx, sizeof(PlanInfo), s);
+  HPA_HIP(hipMemsetAsync(d_info.p, 0, sizeof(PlanInfo), s));
+  if (n)
+    k_global_ctx<<<grid_for(n, 256, ctx->n_cu * 16), 256, 0, s>>>(smp->ctx + r.s0, n, d_soff.as<uint64_t>(),
+                                                                  d_cbase.as<uint32_t>(), P, d_g.as<uint32_t>(),
+                                                                  d_info.as<PlanInfo>());
+  HPA_HIP(hipGetLastError());
+  PlanInfo info{};
+  HPA_HIP(hipMemcpyAsync(&info, d_info.p, sizeof(info), hipMemcpyDeviceToHost, s));
+  HPA_HIP(hipStreamSynchronize(s));
+  if (info.err & ERR_CTX) fail(HPA_E_INVAL, "a sample's ctx is not below its profile's n_ctx");
+  hpa_samples rs{smp->pc + r.s0, d_g.as<uint32_t>(), smp->stall + r.s0, smp->weight ? smp->weight + r.s0 : nullptr,
+                 n, (uint32_t)G};
+  BatchRun br{d_pm.as<ProfMap>(), d_cprof.as<uint32_t>()};
+  hpa_attribution* a = attribute_impl(ctx, pd[r.p0].map, &br, &rs, s, kn);
+  if (!keep) {
+    hpa_attribution_free(a);
+    return;
+  }
+  hpa_batch::Round R;
+  R.a = a;
+  R.rebased = DBuf(ctx, ((uint64_t)G + P) * 8, s);
+  DBuf d_k0(ctx, ((uint64_t)P + 1) * 8, s);
+  k_rebase<<<grid_for(G + P, 256, ctx->n_cu * 8), 256, 0, s>>>(a->ctx_offsets.as<uint64_t>(), d_cbase.as<uint32_t>(),
+                                                               P, d_k0.as<uint64_t>(), R.rebased.as<uint64_t>());
+  HPA_HIP(hipGetLastError());
+  std::vector<uint64_t> k0(P + 1);
+  HPA_HIP(hipMemcpyAsync(k0.data(), d_k0.p, (P + 1) * 8, hipMemcpyDeviceToHost, s));
+  HPA_HIP(hipStreamSynchronize(s));
+  const uint32_t ri = (uint32_t)B->rounds.size();
+  for (uint32_t i = 0; i < P; ++i)
+    B->prof.push_back(hpa_batch::Prof{ri, pd[r.p0 + i].n_ctx, k0[i], k0[i + 1] - k0[i], (uint64_t)cbase[i] + i});
+  B->rounds.push_back(std::move(R));
+  B->info.total_keys += k0[P];
+}
+
+}  // namespace
+
+extern "C" hpa_status hpa_attribute_batched(hpa_ctx* ctx, uint32_t n_profiles, const hpa_profile_desc* pd,
+                                            const hpa_samples* smp, const hpa_batch_opts* opts, hipStream_t stream,
+                                            hpa_batch** out) {
+  return guard([&] {
+    if (!ctx || !pd || !smp || !out || n_profiles == 0) fail(HPA_E_INVAL, "NULL argument or no profiles");
+    if (smp->n && (!smp->pc || !smp->ctx || !smp->stall)) fail(HPA_E_INVAL, "NULL sample array");
+    std::vector<uint64_t> soff(n_profiles + 1, 0);
+    for (uint32_t p = 0; p < n_profiles; ++p) {
+      if (!pd[p].map || pd[p].map->ctx != ctx) fail(HPA_E_INVAL, "profile map missing or of another context");
+      if (pd[p].n_ctx == 0 || pd[p].n_ctx >= 0x7FFFFFFFu) fail(HPA_E_INVAL, "profile n_ctx out of range");
+      soff[p + 1] = soff[p] + pd[p].n_samples;
+    }
+    if (soff[n_profiles] != smp->n) fail(HPA_E_INVAL, "samples->n differs from the profiles' total");
+    hpa_batch_opts o{};
+    if (opts) o = *opts;
+    const uint64_t cap = o.max_round_samples ? o.max_round_samples : (1ull << 31);
+    // rounds: consecutive profiles up to `cap` samples and 2^31 contexts
+    std::vector<RoundPlan> plan;
+    {
+      uint32_t p0 = 0;
+      while (p0 < n_profiles) {
+        uint32_t p1 = p0 + 1;
+        uint64_t ns = pd[p0].n_samples, nc = pd[p0].n_ctx;
+        while (p1 < n_profiles && ns + pd[p1].n_samples <= cap && nc + pd[p1].n_ctx < 0x7FFFFFFFull) {
+          ns += pd[p1].n_samples;
+          nc += pd[p1].n_ctx;
+          ++p1;
+        }
+        if (ns >= (1ull << 40)) fail(HPA_E_INVAL, "a profile has too many samples");
+        plan.push_back(RoundPlan{p0, p1, soff[p0], soff[p1]});
+        p0 = p1;
+      }
+    }
+    DeviceGuard dg(ctx->device);
+    hipStream_t s = stream;
+    auto* B = new hpa_batch();
+    std::unique_ptr<hpa_batch> hold(B);
+    B->ctx = ctx;
+    Knobs kn;
+    if (o.merge_rounds <= 3 && opts) kn.merge_rounds = o.merge_rounds;
+    if (o.scan_wg_per_cu) kn.scan_wg_per_cu = o.scan_wg_per_cu;
+    if (o.autotune) {
+      if (ctx->tuned) {
+        kn.merge_rounds = ctx->tuned_merge_rounds;
+        kn.scan_wg_per_cu = ctx->tuned_scan_wg;
+      } else {
+        // pilot: the first round's leading profiles, up to 2^26 samples
+        RoundPlan pilot = plan[0];
+        while (pilot.p1 > pilot.p0 + 1 && soff[pilot.p1] - soff[pilot.p0] > (1ull << 26)) --pilot.p1;
+        pilot.s1 = soff[pilot.p1];
+        hipEvent_t e0, e1;
+        HPA_HIP(hipEventCreate(&e0));
+        HPA_HIP(hipEventCreate(&e1));
+        float best = 3.4e38f;
+        Knobs bk = kn;
+        const auto t0 = std::chrono::steady_clock::now();
+        run_round(ctx, pd, smp, pilot, soff, s, kn, B, false);  // warm-up
+        for (uint32_t mr = 0; mr <= 3; ++mr)
+          for (uint32_t wg : {2u, 4u, 8u}) {
+            Knobs k{mr, wg};
+            HPA_HIP(hipEventRecord(e0, s));
+            run_round(ctx, pd, smp, pilot, soff, s, k, B, false);
+            HPA_HIP(hipEventRecord(e1, s));
+            HPA_HIP(hipEventSynchronize(e1));
+            float ms = 0.f;
+            HPA_HIP(hipEventElapsedTime(&ms, e0, e1));
+            if (ms < best) { best = ms; bk = k; }
+          }
+        (void)hipEventDestroy(e0);
+        (void)hipEventDestroy(e1);
+        B->info.tune_ms = std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
+        kn = bk;
+        ctx->tuned = true;
+        ctx->tuned_merge_rounds = kn.merge_rounds;
+        ctx->tuned_scan_wg = kn.scan_wg_per_cu;
+      }
+    }
+    for (const RoundPlan& r : plan) run_round(ctx, pd, smp, r, soff, s, kn, B, true);
+    B->info.n_rounds = (uint32_t)plan.size();
+    B->info.merge_rounds = kn.merge_rounds;
+    B->info.scan_wg_per_cu = kn.scan_wg_per_cu;
+    B->info.autotuned = o.autotune ? 1 : 0;
+    *out = hold.release();
+  });
+}
+
+extern "C" hpa_status hpa_batch_profile_view(const hpa_batch* b, uint32_t profile, hpa_attribution_view* v) {
+  return guard([&] {
+    if (!b || !v) fail(HPA_E_INVAL, "NULL argument");
+    if (profile >= b->prof.size()) fail(HPA_E_INVAL, "profile out of range");
+    const hpa_batch::Prof& p = b->prof[profile];
+    const hpa_attribution* a = b->rounds[p.round].a;
+    v->n_keys = p.n_keys;
+    v->n_ctx = p.n_ctx;
+    v->ctx = a->ctx_id.as<uint32_t>() + p.key0;
+    v->pc = a->pc.as<uint64_t>() + p.key0;
+    v->stall = a->stall.as<uint8_t>() + p.key0;
+    v->count = a->count.as<uint64_t>() + p.key0;
+    v->scope = a->scope.as<uint32_t>() + p.key0;
+    v->ctx_offsets = b->rounds[p.round].rebased.as<uint64_t>() + p.reb0;
+  });
+}
+
+extern "C" hpa_status hpa_batch_info_get(const hpa_batch* b, hpa_batch_info* out) {
+  return guard([&] {
+    if (!b || !out) fail(HPA_E_INVAL, "NULL argument");
+    *out = b->info;
+  });
+}
+
+extern "C" void hpa_batch_free(hpa_batch* b) { delete b; }

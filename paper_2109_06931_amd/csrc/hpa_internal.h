@@ -72,6 +72,9 @@ struct hpa_ctx {
   };
   std::mutex cache_mu;
   std::multimap<size_t, Cached> cache;
+  // run-time pipeline parameters chosen by the batch autotuner, kept for later calls
+  bool tuned = false;
+  uint32_t tuned_merge_rounds = 2, tuned_scan_wg = 4;
   ~hpa_ctx();
 };
 
