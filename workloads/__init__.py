@@ -15,5 +15,5 @@ from .gen import (  # noqa: F401
     make_samples,
     learned_intervals,
     learned_queries,
-    batched_profiles,
 )
+from .batched import batched_sizes, batched_structures, GpuSampler  # noqa: F401

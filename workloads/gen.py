@@ -731,7 +731,3 @@ def learned_queries(start: np.ndarray, end: np.ndarray, n: int, seed: int = 2109
     with ThreadPoolExecutor(max_workers=max(1, threads)) as ex:
         list(ex.map(work, range(nc)))
     return out
-
-
-def batched_profiles(*args, **kwargs):  # pragma: no cover - built with the batched path
-    raise NotImplementedError("batched profile generator")
