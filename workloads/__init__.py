@@ -15,5 +15,6 @@ from .gen import (  # noqa: F401
     make_samples,
     learned_intervals,
     learned_queries,
+    learned_queries_gpu,
 )
 from .batched import batched_sizes, batched_structures, GpuSampler  # noqa: F401

@@ -731,3 +731,37 @@ def learned_queries(start: np.ndarray, end: np.ndarray, n: int, seed: int = 2109
     with ThreadPoolExecutor(max_workers=max(1, threads)) as ex:
         list(ex.map(work, range(nc)))
     return out
+
+
+def learned_queries_gpu(start: np.ndarray, end: np.ndarray, n: int, seed: int = 2109069314,
+                        zipf_frac: float = 0.7, zipf_s: float = 1.05, device="cuda"):
+    """The query mix of learned_queries drawn on the GPU with torch's seeded
+    generator (for sizes where host drawing is slow): a Zipf-picked interval
+    plus a uniform offset inside it, or a uniform address over the whole span.
+    Returns a uint64 CUDA tensor."""
+    import torch
+    m = start.shape[0]
+    rz = _rng(seed, _C_LEARN, 1)
+    perm = torch.from_numpy(rz.permutation(m).astype(np.int64)).to(device)
+    w = torch.arange(1, m + 1, dtype=torch.float64, device=device).pow_(-zipf_s)
+    cdf = torch.cumsum(w, 0)
+    cdf /= cdf[-1].clone()
+    del w
+    s = torch.from_numpy(start.view(np.int64)).to(device)
+    e = torch.from_numpy(end.view(np.int64)).to(device)
+    lo_all, hi_all = int(start[0]), int(end[-1])
+    g = torch.Generator(device=device)
+    g.manual_seed(seed)
+    out = torch.empty(n, dtype=torch.int64, device=device)
+    step = 1 << 26
+    for a in range(0, n, step):
+        k = min(step, n - a)
+        pick = torch.rand(k, generator=g, device=device) < zipf_frac
+        iv = perm[torch.clamp(torch.searchsorted(cdf, torch.rand(k, generator=g, device=device,
+                                                                  dtype=torch.float64)), max=m - 1)]
+        span = (e[iv] - s[iv]).to(torch.float64)
+        q_in = s[iv] + torch.floor(torch.rand(k, generator=g, device=device, dtype=torch.float64) * span).to(torch.int64)
+        q_un = lo_all + torch.floor(torch.rand(k, generator=g, device=device, dtype=torch.float64)
+                                    * float(hi_all - lo_all)).to(torch.int64)
+        out[a:a + k] = torch.where(pick, q_in, q_un)
+    return out.view(torch.uint64)
