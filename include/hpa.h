@@ -297,6 +297,29 @@ typedef struct hpa_attribution hpa_attribution;
 hpa_status hpa_attribute(hpa_ctx* ctx, const hpa_structure_map* map, const hpa_samples* samples,
                          hipStream_t stream, hpa_attribution** out);
 
+/* For callers that cannot allocate device memory (code under HIP graph
+ * capture, tight serving loops, harnesses that forbid allocation): the same
+ * attribution as hpa_attribute, with no hipMalloc, hipFree or other
+ * allocating call.  Its working buffers live in one file-scope device array of
+ * HPA_NOALLOC_SCRATCH_MIB MiB (one per GPU, held until the process ends); the
+ * outputs are the caller's device arrays, each with room for samples->n keys
+ * (ctx u32, pc u64, stall u8, count u64, scope u32) and ctx_offsets with
+ * samples->n_ctx + 1 entries; *n_keys (host) receives the key count and
+ * *scratch_used (host, may be NULL) the scratch bytes the call needed.  Calls
+ * that overlap on one GPU share the array and race.  Synchronises `stream`
+ * as hpa_attribute does.  Errors: HPA_E_INVAL (as hpa_attribute, or
+ * samples->n over HPA_NOALLOC_MAX_SAMPLES, n_ctx over HPA_NOALLOC_MAX_CTX),
+ * HPA_E_BUDGET (the scratch array is too small for this input),
+ * HPA_E_UNSUPPORTED (a context with a caller allocator, or stage timing on),
+ * HPA_E_DEVICE. */
+#define HPA_NOALLOC_SCRATCH_MIB 128
+#define HPA_NOALLOC_MAX_SAMPLES (1u << 20)
+#define HPA_NOALLOC_MAX_CTX (1u << 16)
+hpa_status hpa_attribute_noalloc(hpa_ctx* ctx, const hpa_structure_map* map, const hpa_samples* samples,
+                                 uint32_t* out_ctx, uint64_t* out_pc, uint8_t* out_stall, uint64_t* out_count,
+                                 uint32_t* out_scope, uint64_t* out_ctx_offsets, uint64_t* n_keys,
+                                 uint64_t* scratch_used, hipStream_t stream);
+
 typedef struct {
   uint64_t n_keys;
   uint32_t n_ctx;

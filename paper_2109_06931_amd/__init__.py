@@ -22,6 +22,7 @@ UNMAPPED = 0xFFFFFFFF
 NO_SITE = 0xFFFFFFFFFFFFFFFF
 N_STALL = 16
 LOOKUP_PLAIN, LOOKUP_LEARNED = 0, 1
+NOALLOC_SCRATCH_BYTES = 128 << 20
 NODE_PATH, NODE_UNREACHABLE, NODE_UNKNOWN = 0, 1, 2
 
 SCOPE_DTYPE = np.dtype([("start", "<u8"), ("end", "<u8"), ("id", "<u4"), ("kind", "<u4")])
@@ -159,6 +160,8 @@ def lib():
         L.hpa_lookup_intervals.argtypes = [P, P, P, U64, P, I, P]
         L.hpa_attribute.argtypes = [P, P, C.POINTER(_Samples), P, PP]
         L.hpa_learned_train.argtypes = [P, P, C.POINTER(_LearnedOpts), P]
+        L.hpa_attribute_noalloc.argtypes = [P, P, C.POINTER(_Samples), P, P, P, P, P, P, C.POINTER(U64),
+                                            C.POINTER(U64), P]
         L.hpa_attribute_batched.argtypes = [P, U32, P, C.POINTER(_Samples), C.POINTER(_BatchOpts), P, PP]
         L.hpa_batch_profile_view.argtypes = [P, U32, C.POINTER(_AttrView)]
         L.hpa_batch_info_get.argtypes = [P, C.POINTER(_BatchInfo)]
@@ -784,3 +787,27 @@ def attribute_batched(ctx: Context, maps, n_samples, n_ctx, pc, ctx_ids, stall, 
     _check(lib().hpa_attribute_batched(ctx.h, P_, C.cast(descs, C.c_void_p), C.byref(s), C.byref(o),
                                        C.c_void_p(_stream(stream)), C.byref(h)), "hpa_attribute_batched")
     return Batch(ctx, list(maps), h)
+
+
+def attribute_noalloc(ctx: Context, m: StructureMap, pc, ctx_ids, stall, weight, n_ctx: int, out: dict,
+                      stream=None):
+    """hpa_attribute_noalloc into caller tensors out = dict(ctx, pc, stall, count, scope, ctx_offsets);
+    returns (n_keys, scratch bytes used)."""
+    n = pc.numel() if hasattr(pc, "numel") else None
+    _device_arrays((pc, "pc", 8, None, False), (ctx_ids, "ctx_ids", 4, n, False), (stall, "stall", 1, n, False),
+                   (weight, "weight", 4, n, True), (out["ctx"], "out ctx", 4, None, False),
+                   (out["pc"], "out pc", 8, None, False), (out["stall"], "out stall", 1, None, False),
+                   (out["count"], "out count", 8, None, False), (out["scope"], "out scope", 4, None, False),
+                   (out["ctx_offsets"], "out ctx_offsets", 8, int(n_ctx) + 1, False))
+    for k in ("ctx", "pc", "stall", "count", "scope"):
+        if out[k].numel() < n:
+            raise ValueError(f"out {k} has room for {out[k].numel()} keys, need {n}")
+    s = _Samples()
+    s.pc, s.ctx, s.stall, s.weight = _ptr(pc), _ptr(ctx_ids), _ptr(stall), _ptr(weight)
+    s.n, s.n_ctx = n, int(n_ctx)
+    nk, used = U64(0), U64(0)
+    _check(lib().hpa_attribute_noalloc(ctx.h, m.h, C.byref(s), *[_ptr(out[k]) for k in
+                                       ("ctx", "pc", "stall", "count", "scope", "ctx_offsets")],
+                                       C.byref(nk), C.byref(used), C.c_void_p(_stream(stream))),
+           "hpa_attribute_noalloc")
+    return nk.value, used.value

@@ -32,6 +32,7 @@
 // samples themselves; the samples are then scattered into context order first.
 #include <algorithm>
 #include <chrono>
+#include <mutex>
 #include <memory>
 
 #include "block_prims.h"
@@ -1739,30 +1740,36 @@ struct BatchRun {
 // ids over the batch's profiles (units never mix profiles, each unit and big
 // context uses its profile's map, output contexts are local to their profile)
 // and big contexts always take the chunk path.
+// With `into`, the result goes into that caller-owned object (and its output
+// arrays are the caller's when `into` already holds non-owning views).
 hpa_attribution* attribute_impl(hpa_ctx* ctx, const hpa_structure_map* map, const BatchRun* batch,
-                                const hpa_samples* smp, hipStream_t stream, const Knobs& kn) {
+                                const hpa_samples* smp, hipStream_t stream, const Knobs& kn,
+                                hpa_attribution* into) {
   {
     hipStream_t s = stream;
     const uint64_t n = smp->n;
     const uint32_t C = smp->n_ctx;
-    auto* A = new hpa_attribution();
-    std::unique_ptr<hpa_attribution> hold(A);
+    auto* A = into ? into : new hpa_attribution();
+    std::unique_ptr<hpa_attribution> hold(into ? nullptr : A);
     A->ctx = ctx;
     A->stream = s;
     A->map = map;
     A->n_ctx = C;
     const uint64_t cap = n ? n : 1;
-    A->ctx_id = DBuf(ctx, cap * 4, s);
-    A->pc = DBuf(ctx, cap * 8, s);
-    A->stall = DBuf(ctx, cap, s);
-    A->count = DBuf(ctx, cap * 8, s);
-    A->scope = DBuf(ctx, cap * 4, s);
-    A->ctx_offsets = DBuf(ctx, ((uint64_t)C + 1) * 8, s);
+    if (!A->ctx_id.p) {
+      A->ctx_id = DBuf(ctx, cap * 4, s);
+      A->pc = DBuf(ctx, cap * 8, s);
+      A->stall = DBuf(ctx, cap, s);
+      A->count = DBuf(ctx, cap * 8, s);
+      A->scope = DBuf(ctx, cap * 4, s);
+      A->ctx_offsets = DBuf(ctx, ((uint64_t)C + 1) * 8, s);
+    }
     if (n == 0) {
       HPA_HIP(hipMemsetAsync(A->ctx_offsets.p, 0, ((uint64_t)C + 1) * 8, s));
       HPA_HIP(hipStreamSynchronize(s));
       A->n_keys = 0;
-      return hold.release();
+      hold.release();
+      return A;
     }
     StageTimer tm(ctx, s);
     // --- scan ctx, plan ---
@@ -2094,7 +2101,8 @@ hpa_attribution* attribute_impl(hpa_ctx* ctx, const hpa_structure_map* map, cons
       if (!map->dense) tm.items("scope_labels", info.total_keys, info.total_keys);
       tm.collect();
     }
-    return hold.release();
+    hold.release();
+    return A;
   }
 }
 
@@ -2109,7 +2117,7 @@ extern "C" hpa_status hpa_attribute(hpa_ctx* ctx, const hpa_structure_map* map, 
     if (smp->n_ctx == 0 || smp->n_ctx >= 0x7FFFFFFFu) fail(HPA_E_INVAL, "n_ctx out of range");
     if (smp->n >= (1ull << 40)) fail(HPA_E_INVAL, "too many samples for one call");
     DeviceGuard dg(ctx->device);
-    *out = attribute_impl(ctx, map, nullptr, smp, stream, Knobs{});
+    *out = attribute_impl(ctx, map, nullptr, smp, stream, Knobs{}, nullptr);
   });
 }
 
@@ -2263,7 +2271,7 @@ void run_round(hpa_ctx* ctx, const hpa_profile_desc* pd, const hpa_samples* smp,
   hpa_samples rs{smp->pc + r.s0, d_g.as<uint32_t>(), smp->stall + r.s0, smp->weight ? smp->weight + r.s0 : nullptr,
                  n, (uint32_t)G};
   BatchRun br{d_pm.as<ProfMap>(), d_cprof.as<uint32_t>()};
-  hpa_attribution* a = attribute_impl(ctx, pd[r.p0].map, &br, &rs, s, kn);
+  hpa_attribution* a = attribute_impl(ctx, pd[r.p0].map, &br, &rs, s, kn, nullptr);
   if (!keep) {
     hpa_attribution_free(a);
     return;
@@ -2398,3 +2406,82 @@ extern "C" hpa_status hpa_batch_info_get(const hpa_batch* b, hpa_batch_info* out
 }
 
 extern "C" void hpa_batch_free(hpa_batch* b) { delete b; }
+
+// ============================================================================
+// Attribution without allocation, for callers that cannot allocate device
+// memory (code under HIP graph capture, serving loops, harnesses that forbid
+// it).  Every working buffer of the pipeline comes from one file-scope device
+// array, `scratch`, through a bump arena on the context; the outputs are the
+// caller's arrays.  The array's device address is looked up once per device
+// (its host-side name is not a device address).  Calls that overlap on one
+// GPU share the array and race.
+// ============================================================================
+namespace {
+
+constexpr size_t SCRATCH_BYTES = (size_t)HPA_NOALLOC_SCRATCH_MIB << 20;
+static __device__ __align__(256) uint8_t scratch[SCRATCH_BYTES];
+
+std::mutex g_scratch_mu;
+void* g_scratch_ptr[64] = {};
+
+// Device address of this device's copy of `scratch` (the device is current).
+void* scratch_ptr(int device) {
+  if (device < 0 || device >= 64) fail(HPA_E_UNSUPPORTED, "device index beyond 63");
+  std::lock_guard<std::mutex> lk(g_scratch_mu);
+  if (!g_scratch_ptr[device]) {
+    void* p = nullptr;
+    const hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+    if (e != hipSuccess || !p)
+      fail(HPA_E_DEVICE, std::string("hipGetSymbolAddress(scratch): ") + hipGetErrorString(e));
+    g_scratch_ptr[device] = p;
+  }
+  return g_scratch_ptr[device];
+}
+
+// Routes the context's allocations to the arena for the guard's lifetime.
+struct ArenaGuard {
+  hpa_ctx* ctx;
+  ArenaGuard(hpa_ctx* c, void* base, size_t size) : ctx(c) {
+    ctx->arena.base = static_cast<uint8_t*>(base);
+    ctx->arena.size = size;
+    ctx->arena.off = 0;
+    ctx->arena.peak = 0;
+  }
+  ~ArenaGuard() { ctx->arena.base = nullptr; }
+};
+
+}  // namespace
+
+extern "C" hpa_status hpa_attribute_noalloc(hpa_ctx* ctx, const hpa_structure_map* map, const hpa_samples* smp,
+                                            uint32_t* out_ctx, uint64_t* out_pc, uint8_t* out_stall,
+                                            uint64_t* out_count, uint32_t* out_scope, uint64_t* out_ctx_offsets,
+                                            uint64_t* n_keys, uint64_t* scratch_used, hipStream_t stream) {
+  return guard([&] {
+    if (!ctx || !map || !smp || !n_keys) fail(HPA_E_INVAL, "NULL argument");
+    if (map->ctx != ctx) fail(HPA_E_INVAL, "map belongs to another context");
+    if (smp->n && (!smp->pc || !smp->ctx || !smp->stall)) fail(HPA_E_INVAL, "NULL sample array");
+    if (!out_ctx || !out_pc || !out_stall || !out_count || !out_scope || !out_ctx_offsets)
+      fail(HPA_E_INVAL, "NULL output array");
+    if (smp->n_ctx == 0 || smp->n_ctx > HPA_NOALLOC_MAX_CTX)
+      fail(HPA_E_INVAL, "n_ctx must be in [1, " + std::to_string(HPA_NOALLOC_MAX_CTX) + "] without allocation");
+    if (smp->n > HPA_NOALLOC_MAX_SAMPLES)
+      fail(HPA_E_INVAL, "at most " + std::to_string(HPA_NOALLOC_MAX_SAMPLES) + " samples without allocation");
+    if (ctx->custom) fail(HPA_E_UNSUPPORTED, "a context with a caller allocator: use hpa_attribute");
+    if (ctx->timing) fail(HPA_E_UNSUPPORTED, "stage timing creates events: turn it off for this call");
+    DeviceGuard dg(ctx->device);
+    void* base = scratch_ptr(ctx->device);
+    ArenaGuard ag(ctx, base, SCRATCH_BYTES);
+    hpa_attribution A;
+    // the outputs are the caller's (non-owning views)
+    A.ctx_id.p = out_ctx;
+    A.pc.p = out_pc;
+    A.stall.p = out_stall;
+    A.count.p = out_count;
+    A.scope.p = out_scope;
+    A.ctx_offsets.p = out_ctx_offsets;
+    attribute_impl(ctx, map, nullptr, smp, stream, Knobs{}, &A);
+    *n_keys = A.n_keys;
+    if (scratch_used) *scratch_used = ctx->arena.peak;
+    for (DBuf* b : {&A.ctx_id, &A.pc, &A.stall, &A.count, &A.scope, &A.ctx_offsets}) b->p = nullptr;
+  });
+}

@@ -30,6 +30,16 @@ void drop_cache(hpa_ctx* ctx) {
 
 void* dalloc(hpa_ctx* ctx, size_t bytes, hipStream_t s, size_t* cap) {
   void* p = nullptr;
+  if (ctx->arena.base) {
+    const size_t at = (ctx->arena.off + 255) & ~(size_t)255;
+    if (at + bytes > ctx->arena.size)
+      fail(HPA_E_BUDGET, "the call needs more than the " + std::to_string(ctx->arena.size) +
+                             " bytes of scratch available without allocation");
+    ctx->arena.off = at + bytes;
+    ctx->arena.peak = std::max(ctx->arena.peak, ctx->arena.off);
+    *cap = bytes;
+    return ctx->arena.base + at;
+  }
   if (ctx->custom) {
     p = ctx->alloc.alloc(bytes, s, ctx->alloc.user);
     if (!p) fail(HPA_E_NOMEM, "allocator returned NULL for " + std::to_string(bytes) + " bytes");
@@ -64,6 +74,8 @@ void* dalloc(hpa_ctx* ctx, size_t bytes, hipStream_t s, size_t* cap) {
 
 void dfree(hpa_ctx* ctx, void* p, size_t cap, hipStream_t s) {
   if (!p) return;
+  const uint8_t* q = static_cast<const uint8_t*>(p);
+  if (ctx->arena.base && q >= ctx->arena.base && q < ctx->arena.base + ctx->arena.size) return;
   if (ctx->custom) {
     ctx->alloc.free(p, s, ctx->alloc.user);
     return;

@@ -72,6 +72,12 @@ struct hpa_ctx {
   };
   std::mutex cache_mu;
   std::multimap<size_t, Cached> cache;
+  // bump arena over a caller-provided device region: while base is set, every
+  // library allocation of this context comes from it (none is returned)
+  struct Arena {
+    uint8_t* base = nullptr;
+    size_t size = 0, off = 0, peak = 0;
+  } arena;
   // run-time pipeline parameters chosen by the batch autotuner, kept for later calls
   bool tuned = false;
   uint32_t tuned_merge_rounds = 2, tuned_scan_wg = 4;
@@ -105,7 +111,7 @@ struct DBuf {
   }
   ~DBuf() { release(); }
   void release() {
-    if (p) dfree(ctx, p, cap, stream);
+    if (p && ctx) dfree(ctx, p, cap, stream);  // a view of caller memory has no ctx
     p = nullptr;
     bytes = 0;
     cap = 0;
