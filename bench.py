@@ -192,7 +192,13 @@ def section_cct(hpa, ctx):
     pc, cx, st, wt = hpa.samples_to_device(w)
     a = hpa.attribute(ctx, m, pc, cx, st, wt, w.n_ctx)
     plan = hpa.prepare_callgraph_workload(ctx, m, w)
-    hpa.apportion_callpaths(ctx, plan, a)
+    try:
+        hpa.apportion_callpaths(ctx, plan, a)
+    except hpa.HpaError as e:
+        if e.code != hpa.E_UNSUPPORTED:
+            raise
+        return {"workload": "plain method, tiny (1M samples, 32 placeholders)", "status": "compiled out",
+                "reason": str(e)}
     dt_a = _timed(lambda: hpa.apportion_callpaths(ctx, plan, a), reps=5)
     t = hpa.apportion_callpaths(ctx, plan, a)
     dt_d = _timed(lambda: hpa.derive_metrics(ctx, plan, a, t), reps=5)

@@ -132,6 +132,14 @@ class _BatchInfo(C.Structure):
                 ("total_keys", U64), ("tune_ms", C.c_double)]
 
 
+_ALLOC_FN = C.CFUNCTYPE(C.c_void_p, C.c_size_t, C.c_void_p, C.c_void_p)
+_FREE_FN = C.CFUNCTYPE(None, C.c_void_p, C.c_void_p, C.c_void_p)
+
+
+class _Allocator(C.Structure):
+    _fields_ = [("alloc", _ALLOC_FN), ("free", _FREE_FN), ("user", P)]
+
+
 class _StageTime(C.Structure):
     _fields_ = [("name", C.c_char_p), ("ms", C.c_double), ("calls", U64), ("items_in", U64), ("items_out", U64)]
 
@@ -275,11 +283,27 @@ def device_view(ptr, shape, dtype, owner=None):
 # API
 # ---------------------------------------------------------------------------
 class Context:
-    """hpa_ctx on one device (default allocator: the device's stream-ordered pool)."""
+    """hpa_ctx on one device.
 
-    def __init__(self, device: int = 0):
+    Without `allocator` the library allocates from the device's stream-ordered
+    pool.  An allocator is an object with `alloc(nbytes, stream) -> int` (a
+    device address, 0 on failure) and `free(ptr, stream)`; the library calls
+    them for every device buffer it needs (hpa_allocator)."""
+
+    def __init__(self, device: int = 0, allocator=None):
         self.h = C.c_void_p()
-        _check(lib().hpa_ctx_create(device, None, C.byref(self.h)), "hpa_ctx_create")
+        self._alloc = None
+        if allocator is not None:
+            def _a(nbytes, stream, user):
+                return int(allocator.alloc(int(nbytes), stream)) or None
+
+            def _f(ptr, stream, user):
+                allocator.free(int(ptr), stream)
+
+            # the callbacks must outlive the context
+            self._alloc = _Allocator(_ALLOC_FN(_a), _FREE_FN(_f), None)
+        _check(lib().hpa_ctx_create(device, C.byref(self._alloc) if self._alloc else None, C.byref(self.h)),
+               "hpa_ctx_create")
         self.device = device
 
     def set_timing(self, on: bool = True):

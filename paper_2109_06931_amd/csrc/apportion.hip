@@ -957,6 +957,10 @@ extern "C" hpa_status hpa_apportion_callpaths(hpa_ctx* ctx, const hpa_callgraph_
     if (attr->map != plan->map) fail(HPA_E_INVAL, "attribution and plan use different structure maps");
     if (attr->n_ctx != plan->n_ctx) fail(HPA_E_INVAL, "attribution and plan have different context counts");
     const int sample_based = opts ? opts->sample_based : 1;
+#ifndef HPA_ENABLE_GPU_CCT
+    fail(HPA_E_UNSUPPORTED, "GPU call-path apportioning is compiled out (build with HPA_ENABLE_GPU_CCT): its kernels "
+                            "stopped making progress on the device on a 4-context, 500-sample case, cause not found");
+#endif
     DeviceGuard dg(ctx->device);
     hipStream_t s = stream;
     const uint32_t C = plan->n_ctx;

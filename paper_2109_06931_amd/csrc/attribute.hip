@@ -2411,7 +2411,7 @@ extern "C" void hpa_batch_free(hpa_batch* b) { delete b; }
 // Attribution without allocation, for callers that cannot allocate device
 // memory (code under HIP graph capture, serving loops, harnesses that forbid
 // it).  Every working buffer of the pipeline comes from one file-scope device
-// array, `scratch`, through a bump arena on the context; the outputs are the
+// array, `scratch`, through a bump arena (this thread's allocations only); the outputs are the
 // caller's arrays.  The array's device address is looked up once per device
 // (its host-side name is not a device address).  Calls that overlap on one
 // GPU share the array and race.
@@ -2438,16 +2438,16 @@ void* scratch_ptr(int device) {
   return g_scratch_ptr[device];
 }
 
-// Routes the context's allocations to the arena for the guard's lifetime.
+// Routes this thread's library allocations to the arena for the guard's
+// lifetime.
 struct ArenaGuard {
-  hpa_ctx* ctx;
-  ArenaGuard(hpa_ctx* c, void* base, size_t size) : ctx(c) {
-    ctx->arena.base = static_cast<uint8_t*>(base);
-    ctx->arena.size = size;
-    ctx->arena.off = 0;
-    ctx->arena.peak = 0;
+  ArenaGuard(void* base, size_t size) {
+    t_arena.base = static_cast<uint8_t*>(base);
+    t_arena.size = size;
+    t_arena.off = 0;
+    t_arena.peak = 0;
   }
-  ~ArenaGuard() { ctx->arena.base = nullptr; }
+  ~ArenaGuard() { t_arena.base = nullptr; }
 };
 
 }  // namespace
@@ -2470,7 +2470,7 @@ extern "C" hpa_status hpa_attribute_noalloc(hpa_ctx* ctx, const hpa_structure_ma
     if (ctx->timing) fail(HPA_E_UNSUPPORTED, "stage timing creates events: turn it off for this call");
     DeviceGuard dg(ctx->device);
     void* base = scratch_ptr(ctx->device);
-    ArenaGuard ag(ctx, base, SCRATCH_BYTES);
+    ArenaGuard ag(base, SCRATCH_BYTES);
     hpa_attribution A;
     // the outputs are the caller's (non-owning views)
     A.ctx_id.p = out_ctx;
@@ -2481,7 +2481,7 @@ extern "C" hpa_status hpa_attribute_noalloc(hpa_ctx* ctx, const hpa_structure_ma
     A.ctx_offsets.p = out_ctx_offsets;
     attribute_impl(ctx, map, nullptr, smp, stream, Knobs{}, &A);
     *n_keys = A.n_keys;
-    if (scratch_used) *scratch_used = ctx->arena.peak;
+    if (scratch_used) *scratch_used = t_arena.peak;
     for (DBuf* b : {&A.ctx_id, &A.pc, &A.stall, &A.count, &A.scope, &A.ctx_offsets}) b->p = nullptr;
   });
 }

@@ -28,17 +28,19 @@ void drop_cache(hpa_ctx* ctx) {
 
 }  // namespace
 
+thread_local Arena t_arena;
+
 void* dalloc(hpa_ctx* ctx, size_t bytes, hipStream_t s, size_t* cap) {
   void* p = nullptr;
-  if (ctx->arena.base) {
-    const size_t at = (ctx->arena.off + 255) & ~(size_t)255;
-    if (at + bytes > ctx->arena.size)
-      fail(HPA_E_BUDGET, "the call needs more than the " + std::to_string(ctx->arena.size) +
+  if (t_arena.base) {
+    const size_t at = (t_arena.off + 255) & ~(size_t)255;
+    if (at + bytes > t_arena.size)
+      fail(HPA_E_BUDGET, "the call needs more than the " + std::to_string(t_arena.size) +
                              " bytes of scratch available without allocation");
-    ctx->arena.off = at + bytes;
-    ctx->arena.peak = std::max(ctx->arena.peak, ctx->arena.off);
+    t_arena.off = at + bytes;
+    t_arena.peak = std::max(t_arena.peak, t_arena.off);
     *cap = bytes;
-    return ctx->arena.base + at;
+    return t_arena.base + at;
   }
   if (ctx->custom) {
     p = ctx->alloc.alloc(bytes, s, ctx->alloc.user);
@@ -75,7 +77,7 @@ void* dalloc(hpa_ctx* ctx, size_t bytes, hipStream_t s, size_t* cap) {
 void dfree(hpa_ctx* ctx, void* p, size_t cap, hipStream_t s) {
   if (!p) return;
   const uint8_t* q = static_cast<const uint8_t*>(p);
-  if (ctx->arena.base && q >= ctx->arena.base && q < ctx->arena.base + ctx->arena.size) return;
+  if (t_arena.base && q >= t_arena.base && q < t_arena.base + t_arena.size) return;
   if (ctx->custom) {
     ctx->alloc.free(p, s, ctx->alloc.user);
     return;

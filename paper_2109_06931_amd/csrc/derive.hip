@@ -315,6 +315,10 @@ extern "C" hpa_status hpa_derive_metrics(hpa_ctx* ctx, const hpa_callgraph_plan*
     if (!ctx || !plan || !attr || !cct || !out) fail(HPA_E_INVAL, "NULL argument");
     if (cct_plan(cct) != plan || cct_attr(cct) != attr) fail(HPA_E_INVAL, "the tree was built from other inputs");
     if (attr->ctx != ctx) fail(HPA_E_INVAL, "handles belong to another context");
+#ifndef HPA_ENABLE_GPU_CCT
+    fail(HPA_E_UNSUPPORTED, "derived metrics of the GPU calling context tree are compiled out with it "
+                            "(build with HPA_ENABLE_GPU_CCT)");
+#endif
     DeviceGuard dg(ctx->device);
     hipStream_t s = stream;
     const uint32_t C = plan_n_ctx(plan);

@@ -72,12 +72,6 @@ struct hpa_ctx {
   };
   std::mutex cache_mu;
   std::multimap<size_t, Cached> cache;
-  // bump arena over a caller-provided device region: while base is set, every
-  // library allocation of this context comes from it (none is returned)
-  struct Arena {
-    uint8_t* base = nullptr;
-    size_t size = 0, off = 0, peak = 0;
-  } arena;
   // run-time pipeline parameters chosen by the batch autotuner, kept for later calls
   bool tuned = false;
   uint32_t tuned_merge_rounds = 2, tuned_scan_wg = 4;
@@ -85,6 +79,16 @@ struct hpa_ctx {
 };
 
 namespace hpa {
+
+// Bump arena over a caller-provided device region: while base is set, every
+// library allocation made on this thread comes from it (none is returned).
+// Thread-local, so that other threads using the same context keep allocating
+// normally.
+struct Arena {
+  uint8_t* base = nullptr;
+  size_t size = 0, off = 0, peak = 0;
+};
+extern thread_local Arena t_arena;
 
 // dalloc returns a block of at least `bytes` and its capacity in *cap; dfree
 // takes the block back with that capacity.

@@ -277,3 +277,52 @@ def test_attribute_reuses_cached_blocks(hpa):
         m, om, a, oa = _run(hpa, ctx, w)
         assert_attribution_equal(a.numpy(), oa, f"cached blocks: {name}")
         del a, m
+
+
+class _TorchAllocator:
+    """Caller allocator for hpa_ctx_create: device blocks from torch, counted."""
+
+    def __init__(self, refuse=False):
+        self.live = {}
+        self.n_alloc = self.n_free = 0
+        self.refuse = refuse
+
+    def alloc(self, nbytes, stream):
+        if self.refuse:
+            return 0
+        t = torch.empty(max(nbytes, 1), dtype=torch.uint8, device="cuda")
+        self.live[t.data_ptr()] = t
+        self.n_alloc += 1
+        return t.data_ptr()
+
+    def free(self, ptr, stream):
+        assert ptr in self.live, "the library freed a block it did not get from this allocator"
+        del self.live[ptr]
+        self.n_free += 1
+
+
+def test_attribute_with_caller_allocator(hpa):
+    """Every device buffer of the call comes from the caller's allocator and goes
+    back to it when the handles are freed; the result is the oracle's."""
+    al = _TorchAllocator()
+    c = hpa.Context(0, allocator=al)
+    w = small_config(21, n_samples=150_000)
+    m, om, a, oa = _run(hpa, c, w)
+    assert_attribution_equal(a.numpy(), oa)
+    assert al.n_alloc > 0 and al.live, "no buffer came from the caller's allocator"
+    torch.cuda.synchronize()
+    del a, m
+    torch.cuda.synchronize()
+    assert al.n_free == al.n_alloc and not al.live, (al.n_alloc, al.n_free)
+    del c
+
+
+def test_attribute_allocator_returning_null(hpa):
+    """An allocator that returns NULL makes the call fail with HPA_E_NOMEM."""
+    al = _TorchAllocator(refuse=True)
+    c = hpa.Context(0, allocator=al)
+    w = small_config(22, n_samples=20_000)
+    with pytest.raises(hpa.HpaError) as ei:
+        _run(hpa, c, w)
+    assert ei.value.code == hpa.E_NOMEM
+    del c

@@ -16,6 +16,14 @@ torch = pytest.importorskip("torch")
 RTOL = 1e-9
 GOLDEN = os.path.join(os.path.dirname(__file__), "golden")
 
+# The device path of A5/A6 is compiled out.  Its first version took a GPU
+# memory fault on test_cct_tiny[0] (twice, the second time after a first fix);
+# its rewrite, which matches the oracle when the kernel source runs on the CPU,
+# stopped making progress on the device on the same case (no output for 180 s,
+# no fault).  The cause is not found, so these cases stay off the device.
+DISABLED = pytest.mark.skip(reason="GPU call-path apportioning is compiled out: its rewrite stopped making "
+                                   "progress on the device on test_cct_tiny[0]; cause not found")
+
 
 
 @pytest.fixture(scope="module")
@@ -80,6 +88,7 @@ def check_against_oracle(hpa, hctx, w, label="", sample_based=1):
     return t, d
 
 
+@DISABLED
 @pytest.mark.parametrize("seed", list(range(12)))
 def test_cct_tiny(hpa, hctx, seed):
     w = tiny_random_case(seed, n_funcs=4 + seed % 5, n_samples=500 + 50 * seed, n_ctx=4 + seed % 3,
@@ -87,16 +96,19 @@ def test_cct_tiny(hpa, hctx, seed):
     check_against_oracle(hpa, hctx, w, f"tiny{seed}")
 
 
+@DISABLED
 @pytest.mark.parametrize("seed", [1, 2, 3])
 def test_cct_small(hpa, hctx, seed):
     w = small_config(seed, n_samples=200_000)
     check_against_oracle(hpa, hctx, w, f"small{seed}")
 
 
+@DISABLED
 def test_cct_config1(hpa, hctx):
     check_against_oracle(hpa, hctx, config1(), "config1")
 
 
+@DISABLED
 def test_cct_handmade_cases(hpa, hctx):
     g = json.load(open(os.path.join(GOLDEN, "fig4_shape.json")))
     names = g["functions"]
@@ -116,6 +128,7 @@ def test_cct_handmade_cases(hpa, hctx):
         check_against_oracle(hpa, hctx, w, f"handmade{i}")
 
 
+@DISABLED
 def test_cct_budget(hpa, hctx):
     w = small_config(7, n_samples=20000, n_funcs=120, n_inst=4000, n_ctx=60)
     m, a, plan, t, d = _gpu_all(hpa, hctx, w)
@@ -141,6 +154,7 @@ def test_prepare_callgraph_validation(hpa, hctx):
         assert ei.value.code == hpa.E_INVAL
 
 
+@DISABLED
 @pytest.mark.parametrize("seed", list(range(6)))
 def test_cct_exact_counts(hpa, hctx, seed):
     """Exact-count call graphs: weights taken as given, step 2 off."""
@@ -148,5 +162,19 @@ def test_cct_exact_counts(hpa, hctx, seed):
     check_against_oracle(hpa, hctx, w, f"exact{seed}", sample_based=0)
 
 
+@DISABLED
 def test_cct_exact_counts_small(hpa, hctx):
     check_against_oracle(hpa, hctx, small_config(11, n_samples=50_000, weighted=True), "exact-small", sample_based=0)
+
+
+def test_cct_entry_points_compiled_out(hpa, hctx):
+    """Until the device path is verified, both entry points fail with
+    HPA_E_UNSUPPORTED before any kernel is launched."""
+    w = handmade.build(3, [(0, 1, 1)], {1: [(0, 1)]}, entry=0)
+    m = hpa.build_structure_map_workload(hctx, w)
+    pc, cx, st, wt = hpa.samples_to_device(w)
+    a = hpa.attribute(hctx, m, pc, cx, st, wt, w.n_ctx)
+    plan = hpa.prepare_callgraph_workload(hctx, m, w)
+    with pytest.raises(hpa.HpaError) as ei:
+        hpa.apportion_callpaths(hctx, plan, a)
+    assert ei.value.code == hpa.E_UNSUPPORTED
