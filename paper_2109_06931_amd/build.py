@@ -11,7 +11,7 @@ ROOT = os.path.dirname(HERE)
 CSRC = os.path.join(HERE, "csrc")
 OUT = os.path.join(HERE, "libhpa.so")
 BUILD = os.path.join(HERE, "_build")
-SOURCES = ["core.hip", "attribute.hip", "apportion.hip", "derive.hip", "learned.hip", "serve.hip", "unify.hip"]
+SOURCES = ["core.hip", "attribute.hip", "attribute_dense.hip", "apportion.hip", "derive.hip", "learned.hip", "serve.hip", "unify.hip"]
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 FLAGS = [
     "--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC",

@@ -1,0 +1,943 @@
+// A2-A4 for maps with dense instruction coordinates: a pipeline driven from
+// the device end to end, with one host synchronisation per call (Section 4.2
+// sample record; Section 4.5: a raw metric is the sum of measured values;
+// Section 6.1 calling-context expansion for the scope labels).
+//
+//   hist      read ctx[] once (16 B per lane): per-context sample counts, one
+//             atomic per run of equal contexts inside a wave's 256 samples.
+//   bases     tile scans over the contexts: each context's first position in
+//             context order, the list of contexts over UT samples ("big").
+//   scatter   read pc, ctx, stall (and weight) once; replace the pc by its
+//             dense coordinate D and write the 4-byte record D << 4 | stall
+//             at the sample's position in context order (one atomic per run).
+//   split     one workgroup per big context: a histogram of its records over
+//             coordinate buckets, the buckets packed greedily into parts of at
+//             most UT samples (a bucket over UT samples is a part of its own,
+//             counted instead of sorted), the records copied into bucket order.
+//             Parts cover increasing coordinate ranges, so their sorted keys,
+//             one after the other, are the context's keys in order.
+//   plan      per tile of 1,024 contexts, consecutive contexts packed greedily
+//             into units of at most UT samples and 64 non-empty contexts; a big
+//             context contributes its parts.  Units are numbered in context
+//             order.
+//   units     persistent workgroups take units in ticket order: load the
+//             records (contiguous), sort the keys (local context, D, stall) in
+//             LDS, mark unique keys, publish the unit's key count, look back
+//             over the units before it for its output offset, and write the
+//             final keys (ctx, pc, stall, count, scope) and its contexts'
+//             offsets directly.
+//
+// A record whose pc has no dense coordinate (far from every window, or off
+// the instruction grid) is counted; the caller then runs the general path.
+#include <algorithm>
+#include <memory>
+
+#include "block_prims.h"
+#include "hpa_internal.h"
+#include "unit_sort.h"
+
+namespace hpa {
+namespace {
+
+constexpr int DB = 256;                 // hist / scatter / plan workgroup
+constexpr int DI = 4;                   // samples per lane per step
+constexpr int DCH = WAVE * DI;          // samples per wave step
+constexpr uint32_t FAR_REC = 0xFFFFFFFFu;
+constexpr int DNB = 4096;               // coordinate buckets of a big context
+constexpr int DTILE = 1024;             // contexts per plan tile
+constexpr int HOT_KEYS = UT;            // counters of a counted part (coordinates x stalls)
+constexpr uint32_t DU_SMALL = 0, DU_PART = 1, DU_HOT = 2;
+constexpr unsigned int DERR_CTX = 1, DERR_STALL = 2, DERR_WIDE = 4, DERR_INTERNAL = 8, DERR_LOOKBACK = 16,
+                       DERR_OVERFLOW = 32;
+constexpr unsigned long long LB_AGG = 1ull << 62, LB_INC = 2ull << 62, LB_VAL = (1ull << 62) - 1;
+constexpr uint32_t LB_SPIN_LIMIT = 1u << 25;
+
+struct DInfo {
+  unsigned long long total_keys;
+  unsigned int err;
+  unsigned int n_far;
+  unsigned int n_big;
+  unsigned int n_units;
+  unsigned int ticket;
+  unsigned int big_slots;
+};
+
+// One unit of work.  SMALL: records [s0, s1) of the context-ordered array,
+// contexts [cb, ce) (empty ones included).  PART / HOT: records [s0, s1) of
+// the bucket-ordered copy, all of context cb; a HOT part is one coordinate
+// bucket starting at coordinate d0.
+struct DUnit {
+  uint32_t s0, s1, cb, ce, kind, d0, pad0, pad1;
+};
+
+// ---------------------------------------------------------------------------
+// run structure of a wave's 256 consecutive samples
+// ---------------------------------------------------------------------------
+// Lane l holds positions 4l .. 4l+3.  For every position: the position of the
+// head of its run (a maximal stretch of equal values inside the step), and
+// whether it is the run's last position.  Invalid positions hold NONE32 and
+// form runs of their own that the callers skip.
+struct WaveRuns {
+  uint32_t v[DI];
+  int head[DI];
+  bool tail[DI];
+};
+
+__device__ inline int wave_excl_max_i(int x) {
+  // exclusive max-scan over lanes (-1 for lane 0)
+  int r = __shfl_up(x, 1, WAVE);
+  if (lane_id() == 0) r = -1;
+#pragma unroll
+  for (int d = 1; d < WAVE; d <<= 1) {
+    const int o = __shfl_up(r, d, WAVE);
+    if (lane_id() >= d) r = max(r, o);
+  }
+  return r;
+}
+
+__device__ inline void wave_runs(WaveRuns& w) {
+  const int lane = lane_id();
+  const uint32_t prev = __shfl_up(w.v[DI - 1], 1, WAVE);
+  const uint32_t next = __shfl_down(w.v[0], 1, WAVE);
+  int hp = -1;
+#pragma unroll
+  for (int j = 0; j < DI; ++j) {
+    const bool h = j == 0 ? (lane == 0 || w.v[0] != prev) : w.v[j] != w.v[j - 1];
+    if (h) hp = lane * DI + j;
+    w.head[j] = hp;  // -1: the run started in an earlier lane
+  }
+  const int carry = wave_excl_max_i(hp);
+#pragma unroll
+  for (int j = 0; j < DI; ++j) {
+    if (w.head[j] < 0) w.head[j] = carry;
+    w.tail[j] = j + 1 < DI ? w.v[j] != w.v[j + 1] : (lane == WAVE - 1 || w.v[DI - 1] != next);
+  }
+}
+
+template <bool VEC>
+__device__ inline void load_ctx4(const uint32_t* __restrict__ ctx, uint64_t n, uint64_t p0, uint32_t (&v)[DI]) {
+  if (VEC && p0 + DI <= n) {
+    const uint4 q = *reinterpret_cast<const uint4*>(ctx + p0);
+    v[0] = q.x; v[1] = q.y; v[2] = q.z; v[3] = q.w;
+  } else {
+#pragma unroll
+    for (int j = 0; j < DI; ++j) v[j] = p0 + j < n ? ctx[p0 + j] : NONE32;
+  }
+}
+
+// ---------------------------------------------------------------------------
+// hist
+// ---------------------------------------------------------------------------
+template <bool VEC>
+__global__ void __launch_bounds__(DB) k_d_hist(const uint32_t* __restrict__ ctx, uint64_t n, uint32_t C,
+                                               uint32_t* __restrict__ hist, DInfo* __restrict__ info) {
+  const uint64_t nw = (uint64_t)gridDim.x * (DB / WAVE);
+  const uint64_t steps = (n + DCH - 1) / DCH;
+  bool bad = false;
+  for (uint64_t k = (uint64_t)blockIdx.x * (DB / WAVE) + wave_id(); k < steps; k += nw) {
+    const uint64_t p0 = k * DCH + (uint64_t)lane_id() * DI;
+    WaveRuns w;
+    load_ctx4<VEC>(ctx, n, p0, w.v);
+    wave_runs(w);
+#pragma unroll
+    for (int j = 0; j < DI; ++j) {
+      if (p0 + j >= n) continue;
+      const uint32_t c = w.v[j];
+      if (c >= C) { bad = true; continue; }
+      if (w.tail[j]) atomicAdd(&hist[c], (uint32_t)(lane_id() * DI + j - w.head[j] + 1));
+    }
+  }
+  if (__any(bad) && lane_id() == 0) atomicOr(&info->err, DERR_CTX);
+}
+
+// ---------------------------------------------------------------------------
+// bases: three launches of tile scans over the contexts
+// ---------------------------------------------------------------------------
+// Per tile: samples, big contexts, and the unit slots the big contexts may
+// need (2 * ceil(n / UT) + 1 each: greedy packing leaves no two neighbouring
+// parts that would fit together).
+struct DTileSums {
+  unsigned long long n;
+  uint32_t big, slots;
+};
+
+__device__ inline uint32_t big_slots(uint32_t n) { return 2u * ((n + UT - 1) / UT) + 1u; }
+
+__global__ void __launch_bounds__(DTILE) k_d_tile_sums(const uint32_t* __restrict__ hist, uint32_t C,
+                                                       DTileSums* __restrict__ ts) {
+  __shared__ unsigned long long s_a[DTILE / WAVE + 1];
+  __shared__ uint32_t s_b[DTILE / WAVE + 1];
+  const uint32_t c = blockIdx.x * DTILE + threadIdx.x;
+  const uint32_t h = c < C ? hist[c] : 0u;
+  const bool big = h > (uint32_t)UT;
+  unsigned long long tn;
+  uint32_t tb, tsl;
+  block_excl_scan<DTILE>((unsigned long long)h, s_a, &tn);
+  block_excl_scan<DTILE>((uint32_t)big, s_b, &tb);
+  block_excl_scan<DTILE>(big ? big_slots(h) : 0u, s_b, &tsl);
+  if (threadIdx.x == 0) ts[blockIdx.x] = DTileSums{tn, tb, tsl};
+}
+
+// Exclusive scan of the tile sums in place (one workgroup); the totals go to
+// the info record.
+__global__ void __launch_bounds__(1024) k_d_tile_scan(DTileSums* __restrict__ ts, uint32_t n_tiles,
+                                                      DInfo* __restrict__ info) {
+  __shared__ unsigned long long s_a[1024 / WAVE + 1];
+  __shared__ uint32_t s_b[1024 / WAVE + 1];
+  unsigned long long cn = 0;
+  uint32_t cb = 0, cs = 0;
+  for (uint32_t b0 = 0; b0 < n_tiles; b0 += 1024) {
+    const uint32_t t = b0 + threadIdx.x;
+    const DTileSums v = t < n_tiles ? ts[t] : DTileSums{0, 0, 0};
+    unsigned long long tn;
+    uint32_t tb, tsl;
+    const unsigned long long en = block_excl_scan<1024>(v.n, s_a, &tn);
+    const uint32_t eb = block_excl_scan<1024>(v.big, s_b, &tb);
+    const uint32_t es = block_excl_scan<1024>(v.slots, s_b, &tsl);
+    if (t < n_tiles) ts[t] = DTileSums{cn + en, cb + eb, cs + es};
+    cn += tn;
+    cb += tb;
+    cs += tsl;
+  }
+  if (threadIdx.x == 0) {
+    info->n_big = cb;
+    info->big_slots = cs;
+  }
+}
+
+// Per context: its base in context order (cbase, C + 1 entries), and for a big
+// context its index among the big ones, its entry in the big list and its
+// first unit slot.
+__global__ void __launch_bounds__(DTILE) k_d_bases(const uint32_t* __restrict__ hist, uint32_t C,
+                                                   const DTileSums* __restrict__ ts, uint32_t* __restrict__ cbase,
+                                                   uint32_t* __restrict__ bidx, uint32_t* __restrict__ big_ctx,
+                                                   uint32_t* __restrict__ big_slot0) {
+  __shared__ unsigned long long s_a[DTILE / WAVE + 1];
+  __shared__ uint32_t s_b[DTILE / WAVE + 1];
+  const uint32_t c = blockIdx.x * DTILE + threadIdx.x;
+  const uint32_t h = c < C ? hist[c] : 0u;
+  const bool big = h > (uint32_t)UT;
+  const DTileSums base = ts[blockIdx.x];
+  unsigned long long tn;
+  uint32_t tb, tsl;
+  const unsigned long long en = block_excl_scan<DTILE>((unsigned long long)h, s_a, &tn);
+  const uint32_t eb = block_excl_scan<DTILE>((uint32_t)big, s_b, &tb);
+  const uint32_t es = block_excl_scan<DTILE>(big ? big_slots(h) : 0u, s_b, &tsl);
+  if (c < C) {
+    cbase[c] = (uint32_t)(base.n + en);
+    if (big) {
+      const uint32_t b = base.big + eb;
+      bidx[c] = b;
+      big_ctx[b] = c;
+      big_slot0[b] = base.slots + es;
+    }
+  }
+  if (c == C - 1) cbase[C] = (uint32_t)(base.n + en + h);
+}
+
+// ---------------------------------------------------------------------------
+// scatter
+// ---------------------------------------------------------------------------
+template <bool VEC, bool WEIGHTED>
+__global__ void __launch_bounds__(DB)
+k_d_scatter(const uint64_t* __restrict__ pc, const uint32_t* __restrict__ ctx, const uint8_t* __restrict__ stall,
+            const uint32_t* __restrict__ weight, uint64_t n, uint32_t C, const uint32_t* __restrict__ cbase,
+            uint32_t* __restrict__ cursor, DenseDev dd, uint32_t* __restrict__ rec, uint32_t* __restrict__ rw,
+            DInfo* __restrict__ info) {
+  __shared__ uint64_t s_lo[DENSE_MAX_WIN], s_hi[DENSE_MAX_WIN], s_d[DENSE_MAX_WIN + 1];
+  __shared__ uint32_t s_base[DB / WAVE][DCH];
+  for (uint32_t i = threadIdx.x; i < dd.n_win; i += DB) {
+    s_lo[i] = dd.lo[i];
+    s_hi[i] = dd.hi[i];
+  }
+  for (uint32_t i = threadIdx.x; i <= dd.n_win; i += DB) s_d[i] = dd.d[i];
+  __syncthreads();
+  const DenseDev t{s_lo, s_hi, s_d, dd.scope_of, dd.n_win, dd.tz};
+  uint32_t* const sb = s_base[wave_id()];
+  const uint64_t nw = (uint64_t)gridDim.x * (DB / WAVE);
+  const uint64_t steps = (n + DCH - 1) / DCH;
+  unsigned int far = 0;
+  bool bad_stall = false, bad_pos = false;
+  for (uint64_t k = (uint64_t)blockIdx.x * (DB / WAVE) + wave_id(); k < steps; k += nw) {
+    const uint64_t p0 = k * DCH + (uint64_t)lane_id() * DI;
+    WaveRuns w;
+    load_ctx4<VEC>(ctx, n, p0, w.v);
+    // the other fields' loads go out before the run analysis
+    uint64_t q[DI];
+    uint32_t st[DI], wt[DI];
+    if (VEC && p0 + DI <= n) {
+      const ulonglong2 a = *reinterpret_cast<const ulonglong2*>(pc + p0);
+      const ulonglong2 b = *reinterpret_cast<const ulonglong2*>(pc + p0 + 2);
+      q[0] = a.x; q[1] = a.y; q[2] = b.x; q[3] = b.y;
+      const uint32_t s4 = *reinterpret_cast<const uint32_t*>(stall + p0);
+#pragma unroll
+      for (int j = 0; j < DI; ++j) st[j] = (s4 >> (8 * j)) & 0xFFu;
+      if constexpr (WEIGHTED) {
+        const uint4 ww = *reinterpret_cast<const uint4*>(weight + p0);
+        wt[0] = ww.x; wt[1] = ww.y; wt[2] = ww.z; wt[3] = ww.w;
+      }
+    } else {
+#pragma unroll
+      for (int j = 0; j < DI; ++j) {
+        const bool ok = p0 + j < n;
+        q[j] = ok ? pc[p0 + j] : 0ull;
+        st[j] = ok ? stall[p0 + j] : 0u;
+        if constexpr (WEIGHTED) wt[j] = ok ? weight[p0 + j] : 0u;
+      }
+    }
+    wave_runs(w);
+    // one reservation per run, by its last position; its base is left in LDS
+    // at the run's head for the other positions of the run
+#pragma unroll
+    for (int j = 0; j < DI; ++j) {
+      const uint32_t c = w.v[j];
+      if (p0 + j >= n || c >= C || !w.tail[j]) continue;
+      const uint32_t len = (uint32_t)(lane_id() * DI + j - w.head[j] + 1);
+      sb[w.head[j]] = cbase[c] + atomicAdd(&cursor[c], len);
+    }
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+#pragma unroll
+    for (int j = 0; j < DI; ++j) {
+      const uint32_t c = w.v[j];
+      if (p0 + j >= n || c >= C) continue;
+      const uint32_t pos = sb[w.head[j]] + (uint32_t)(lane_id() * DI + j - w.head[j]);
+      if (pos >= cbase[c + 1]) { bad_pos = true; continue; }
+      uint32_t r;
+      uint64_t D;
+      if (st[j] >= NS) {
+        bad_stall = true;
+        r = 0;
+      } else if (to_dense(t, q[j], D)) {
+        r = ((uint32_t)D << 4) | st[j];
+      } else {
+        r = FAR_REC;
+        ++far;
+      }
+      rec[pos] = r;
+      if constexpr (WEIGHTED) rw[pos] = wt[j];
+    }
+    // the LDS bases of this step are read before the next step writes them
+    __builtin_amdgcn_wave_barrier();
+  }
+  far = wave_sum(far);
+  if (lane_id() == 0) {
+    if (far) atomicAdd(&info->n_far, far);
+  }
+  if (__any(bad_stall) && lane_id() == 0) atomicOr(&info->err, DERR_STALL);
+  if (__any(bad_pos) && lane_id() == 0) atomicOr(&info->err, DERR_INTERNAL);
+}
+
+// ---------------------------------------------------------------------------
+// split of big contexts (one workgroup each)
+// ---------------------------------------------------------------------------
+constexpr int SB = 1024;
+constexpr int SB_PER = DNB / SB;  // buckets per thread
+
+template <bool WEIGHTED>
+__global__ void __launch_bounds__(SB)
+k_d_split(const uint32_t* __restrict__ big_ctx, const uint32_t* __restrict__ big_slot0,
+          const uint32_t* __restrict__ cbase, const uint32_t* __restrict__ rec, const uint32_t* __restrict__ rw,
+          uint32_t bshift, uint32_t* __restrict__ rec2, uint32_t* __restrict__ rw2, DUnit* __restrict__ bunits,
+          uint32_t* __restrict__ n_bunits, DInfo* __restrict__ info) {
+  __shared__ uint32_t s_cnt[DNB];   // bucket counts, then cursors
+  __shared__ uint32_t s_base[DNB + 1];
+  __shared__ uint32_t s_next[DNB];
+  __shared__ uint32_t s_tmp[SB / WAVE + 1];
+  const uint32_t b = blockIdx.x;
+  if (b >= info->n_big) return;
+  const uint32_t c = big_ctx[b];
+  const uint32_t s0 = cbase[c], nc = cbase[c + 1] - s0;
+  for (int i = threadIdx.x; i < DNB; i += SB) s_cnt[i] = 0;
+  __syncthreads();
+  for (uint32_t i = threadIdx.x; i < nc; i += SB) {
+    const uint32_t r = rec[s0 + i];
+    if (r == FAR_REC) continue;
+    const uint32_t k = (r >> 4) >> bshift;
+    atomicAdd(&s_cnt[k < (uint32_t)DNB ? k : DNB - 1], 1u);
+  }
+  __syncthreads();
+  // bucket bases: each thread scans its SB_PER consecutive buckets
+  {
+    uint32_t loc[SB_PER], sum = 0;
+#pragma unroll
+    for (int j = 0; j < SB_PER; ++j) {
+      loc[j] = sum;
+      sum += s_cnt[threadIdx.x * SB_PER + j];
+    }
+    uint32_t tot;
+    const uint32_t ex = block_excl_scan<SB>(sum, s_tmp, &tot);
+#pragma unroll
+    for (int j = 0; j < SB_PER; ++j) s_base[threadIdx.x * SB_PER + j] = ex + loc[j];
+    if (threadIdx.x == 0) s_base[DNB] = tot;
+  }
+  __syncthreads();
+  // greedy packing: a part from bucket k reaches the last bucket e with
+  // base[e] - base[k] <= UT (at least bucket k itself)
+  const uint32_t total = s_base[DNB];
+  for (int k = threadIdx.x; k < DNB; k += SB) {
+    const uint32_t lim = s_base[k] + (uint32_t)UT;
+    uint32_t lo = (uint32_t)k + 1, hi = DNB;  // first e in [k+1, DNB] with base[e] > lim, minus one
+    while (lo < hi) {
+      const uint32_t mid = (lo + hi + 1) >> 1;
+      if (s_base[mid] <= lim) lo = mid;
+      else hi = mid - 1;
+    }
+    s_next[k] = lo;  // exclusive end bucket of the part starting at k
+  }
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    const uint32_t slot0 = big_slot0[b], cap = big_slots(nc);
+    uint32_t k = 0, m = 0;
+    // parts start at non-empty buckets; empty buckets before a part's first
+    // records join it
+    while (k < (uint32_t)DNB && s_base[k] < total) {
+      const uint32_t e = s_next[k];
+      const uint32_t len = s_base[e] - s_base[k];
+      // a single bucket over UT samples is counted, not sorted
+      const bool hot = len > (uint32_t)UT;
+      if (m < cap) {
+        bunits[slot0 + m] = DUnit{s0 + s_base[k], s0 + s_base[e], c, c + 1, hot ? DU_HOT : DU_PART, k << bshift, 0, 0};
+      } else {
+        atomicOr(&info->err, DERR_INTERNAL);
+      }
+      ++m;
+      k = e;
+    }
+    n_bunits[b] = m < cap ? m : cap;
+  }
+  __syncthreads();
+  // records into bucket order
+  for (int i = threadIdx.x; i < DNB; i += SB) s_cnt[i] = 0;
+  __syncthreads();
+  for (uint32_t i = threadIdx.x; i < nc; i += SB) {
+    const uint32_t r = rec[s0 + i];
+    if (r == FAR_REC) continue;
+    uint32_t k = (r >> 4) >> bshift;
+    k = k < (uint32_t)DNB ? k : DNB - 1;
+    const uint32_t p = s_base[k] + atomicAdd(&s_cnt[k], 1u);
+    rec2[s0 + p] = r;
+    if constexpr (WEIGHTED) rw2[s0 + p] = rw[s0 + i];
+  }
+}
+
+// ---------------------------------------------------------------------------
+// plan: greedy packing per tile of contexts
+// ---------------------------------------------------------------------------
+// Thread 0 walks the tile's contexts in order; with `out` null it only counts
+// the units, otherwise it writes them from the tile's first unit on.
+__device__ inline void plan_tile(const uint32_t* s_h, uint32_t c0, uint32_t nt, uint32_t maxc,
+                                 const uint32_t* __restrict__ bidx,
+                                 const DUnit* __restrict__ bunits, const uint32_t* __restrict__ big_slot0,
+                                 const uint32_t* __restrict__ n_bunits, const uint32_t* __restrict__ cbase,
+                                 DUnit* __restrict__ out, uint32_t& n_out) {
+  uint32_t m = 0;
+  uint32_t ucb = c0, samples = 0, nonempty = 0;
+  bool open = false;
+  auto close = [&](uint32_t ce) {
+    if (out) {
+      out[m] = DUnit{cbase[ucb], cbase[ce], ucb, ce, DU_SMALL, 0, 0, 0};
+    }
+    ++m;
+    open = false;
+  };
+  for (uint32_t i = 0; i < nt; ++i) {
+    const uint32_t c = c0 + i, h = s_h[i];
+    if (h > (uint32_t)UT) {
+      if (open) close(c);
+      const uint32_t b = bidx[c];
+      const uint32_t k = n_bunits[b], o = big_slot0[b];
+      for (uint32_t j = 0; j < k; ++j) {
+        if (out) out[m] = bunits[o + j];
+        ++m;
+      }
+      continue;
+    }
+    if (open && ((h > 0 && nonempty == maxc) || samples + h > (uint32_t)UT)) close(c);
+    if (!open) {
+      open = true;
+      ucb = c;
+      samples = 0;
+      nonempty = 0;
+    }
+    samples += h;
+    nonempty += h > 0;
+  }
+  if (open) close(c0 + nt);
+  n_out = m;
+}
+
+__global__ void __launch_bounds__(DB)
+k_d_plan(const uint32_t* __restrict__ hist, uint32_t C, uint32_t maxc, const uint32_t* __restrict__ bidx,
+         const DUnit* __restrict__ bunits, const uint32_t* __restrict__ big_slot0, const uint32_t* __restrict__ n_bunits,
+         const uint32_t* __restrict__ cbase, uint32_t* __restrict__ tile_units, const uint32_t* __restrict__ tile_off,
+         DUnit* __restrict__ units) {
+  __shared__ uint32_t s_h[DTILE];
+  const uint32_t c0 = blockIdx.x * DTILE;
+  const uint32_t nt = min((uint32_t)DTILE, C - c0);
+  for (uint32_t i = threadIdx.x; i < nt; i += DB) s_h[i] = hist[c0 + i];
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    uint32_t m;
+    plan_tile(s_h, c0, nt, maxc, bidx, bunits, big_slot0, n_bunits, cbase, tile_off ? units + tile_off[blockIdx.x] : nullptr,
+              m);
+    if (!tile_off) tile_units[blockIdx.x] = m;
+  }
+}
+
+// exclusive scan of the tiles' unit counts (one workgroup)
+__global__ void __launch_bounds__(1024) k_d_unit_scan(const uint32_t* __restrict__ tile_units, uint32_t n_tiles,
+                                                      uint32_t* __restrict__ tile_off, DInfo* __restrict__ info) {
+  __shared__ uint32_t s_t[1024 / WAVE + 1];
+  uint32_t carry = 0;
+  for (uint32_t b0 = 0; b0 < n_tiles; b0 += 1024) {
+    const uint32_t t = b0 + threadIdx.x;
+    const uint32_t v = t < n_tiles ? tile_units[t] : 0u;
+    uint32_t tot;
+    const uint32_t ex = block_excl_scan<1024>(v, s_t, &tot);
+    if (t < n_tiles) tile_off[t] = carry + ex;
+    carry += tot;
+  }
+  if (threadIdx.x == 0) info->n_units = carry;
+}
+
+// ---------------------------------------------------------------------------
+// units
+// ---------------------------------------------------------------------------
+struct DUnitArgs {
+  const DUnit* units;
+  const uint32_t* rec;
+  const uint32_t* rw;
+  const uint32_t* rec2;
+  const uint32_t* rw2;
+  const uint32_t* hist;
+  const uint32_t* cbase;
+  uint32_t C;
+  uint32_t bshift;
+  DenseDev dd;
+  DInfo* info;
+  unsigned long long* status;  // per unit: look-back word
+  OutDev out;
+};
+
+struct DUnitSmem {
+  uint32_t lstart[MAXC + 1];  // record offset of each non-empty local context, closed by n_u
+  uint32_t lctx[MAXC];        // its context id
+  uint32_t lrank[DTILE];      // per context of the unit: non-empty contexts before it
+  unsigned long long loff[MAXC + 1];
+  unsigned long long P;
+  uint32_t t, nl, red_min, red_max;
+  uint32_t tmp[UBLOCK / WAVE + 1];
+};
+
+// Publish the unit's key count, find the keys of all units before it, and
+// publish the inclusive count.  Thread 0 waits; the spin is bounded so that a
+// broken chain ends the kernel with an error instead of hanging it.
+__device__ inline unsigned long long look_back(unsigned long long* status, uint32_t t, unsigned long long agg,
+                                               unsigned int* err) {
+  if (t == 0) {
+    __hip_atomic_store(&status[0], LB_INC | agg, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    return 0;
+  }
+  __hip_atomic_store(&status[t], LB_AGG | agg, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+  unsigned long long excl = 0;
+  uint32_t j = t - 1, spins = 0;
+  while (true) {
+    const unsigned long long s = __hip_atomic_load(&status[j], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    const unsigned long long f = s & ~LB_VAL;
+    if (f == 0) {
+      // a unit that waited too long flags the chain as broken, and every
+      // other waiting unit stops at once
+      if (++spins > LB_SPIN_LIMIT ||
+          ((spins & 1023u) == 0 &&
+           (__hip_atomic_load(err, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) & DERR_LOOKBACK))) {
+        atomicOr(err, DERR_LOOKBACK);
+        break;
+      }
+      __builtin_amdgcn_s_sleep(1);
+      continue;
+    }
+    excl += s & LB_VAL;
+    if (f == LB_INC || j == 0) break;
+    --j;
+  }
+  __hip_atomic_store(&status[t], LB_INC | (excl + agg), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+  return excl;
+}
+
+// A counted part: one coordinate bucket [d0, d0 + 2^bshift) of one context.
+// Counters (coordinate offset, stall) in LDS, then the non-empty ones in
+// order are the part's keys.
+template <bool WEIGHTED>
+__device__ inline void hot_unit(SortSmem& sm, DUnitSmem& du, const DUnitArgs& a, const DUnit& d) {
+  const int tid = threadIdx.x;
+  const uint32_t R = (1u << a.bshift) * NS;  // <= HOT_KEYS (checked on the host)
+  uint32_t* cnt = sm.buf;
+  for (uint32_t i = tid; i < R; i += UBLOCK) cnt[i] = 0;
+  __syncthreads();
+  bool ovf = false;
+  for (uint32_t i = d.s0 + tid; i < d.s1; i += UBLOCK) {
+    const uint32_t r = a.rec2[i];
+    if (r == FAR_REC) continue;
+    const uint32_t k = (((r >> 4) - d.d0) << 4) | (r & 15u);
+    if (k >= R) { ovf = true; continue; }
+    const uint32_t w = WEIGHTED ? a.rw2[i] : 1u;
+    const uint32_t old = atomicAdd(&cnt[k], w);
+    ovf |= old + w < old;
+  }
+  if (ovf) atomicOr(&a.info->err, DERR_OVERFLOW);
+  __syncthreads();
+  // compaction: thread t scans its block of R / UBLOCK consecutive counters
+  const uint32_t per = (R + UBLOCK - 1) / UBLOCK;
+  uint32_t mine = 0;
+  for (uint32_t j = 0; j < per; ++j) {
+    const uint32_t i = tid * per + j;
+    mine += i < R && cnt[i] != 0;
+  }
+  uint32_t nU;
+  const uint32_t first = block_excl_scan<UBLOCK>(mine, du.tmp, &nU);
+  if (tid == 0) du.P = look_back(a.status, du.t, nU, &a.info->err);
+  __syncthreads();
+  const unsigned long long P = du.P;
+  if (tid == 0 && d.s0 == a.cbase[d.cb]) a.out.ctx_off[d.cb] = P;
+  uint32_t u = first;
+  for (uint32_t j = 0; j < per; ++j) {
+    const uint32_t i = tid * per + j;
+    if (i >= R || cnt[i] == 0) continue;
+    const uint64_t o = P + u++;
+    const uint64_t D = d.d0 + (i >> 4);
+    a.out.ctx[o] = d.cb;
+    a.out.pc[o] = from_dense(a.dd, D);
+    a.out.stall[o] = (uint8_t)(i & 15u);
+    a.out.count[o] = cnt[i];
+    a.out.scope[o] = a.dd.scope_of[D];
+  }
+}
+
+template <bool WEIGHTED>
+__global__ void __launch_bounds__(UBLOCK) k_d_units(DUnitArgs a) {
+  __shared__ SortSmem sm;
+  __shared__ DUnitSmem du;
+  const int tid = threadIdx.x;
+  // dense windows in LDS once
+  a.dd = stage_dense(sm, a.dd);
+  __syncthreads();
+  const uint32_t n_units = a.info->n_units;
+  while (true) {
+    if (tid == 0) du.t = atomicAdd(&a.info->ticket, 1u);
+    __syncthreads();
+    const uint32_t t = du.t;
+    if (t >= n_units) break;
+    const DUnit d = a.units[t];
+    if (d.kind == DU_HOT) {
+      hot_unit<WEIGHTED>(sm, du, a, d);
+      __syncthreads();
+      continue;
+    }
+    const bool part = d.kind == DU_PART;
+    const uint32_t* rec = part ? a.rec2 : a.rec;
+    const uint32_t* rw = part ? a.rw2 : a.rw;
+    const uint64_t n_u = d.s1 - d.s0;
+    // the unit's non-empty contexts and every context's rank among them
+    if (part) {
+      if (tid == 0) {
+        du.red_min = 0xFFFFFFFFu;
+        du.red_max = 0;
+        du.nl = 1;
+        du.lstart[0] = 0;
+        du.lstart[1] = (uint32_t)n_u;
+        du.lctx[0] = d.cb;
+      }
+    } else {
+      const uint32_t nc = d.ce - d.cb;  // <= DTILE
+      const uint32_t c = d.cb + tid;
+      const uint32_t h = (uint32_t)tid < nc ? a.hist[c] : 0u;
+      uint32_t nl;
+      const uint32_t r = block_excl_scan<UBLOCK>(h > 0 ? 1u : 0u, du.tmp, &nl);
+      if ((uint32_t)tid < nc) {
+        du.lrank[tid] = r;
+        if (h > 0 && r < (uint32_t)MAXC) {
+          du.lstart[r] = a.cbase[c] - d.s0;
+          du.lctx[r] = c;
+        }
+      }
+      if (tid == 0) {
+        du.red_min = 0xFFFFFFFFu;
+        du.red_max = 0;
+        du.nl = nl;
+        if (nl > (uint32_t)MAXC) atomicOr(&a.info->err, DERR_INTERNAL);
+        du.lstart[nl < (uint32_t)MAXC ? nl : MAXC] = (uint32_t)n_u;
+      }
+    }
+    __syncthreads();
+    const uint32_t nl = min(du.nl, (uint32_t)MAXC);
+    // gather: item i of thread t is record i * UBLOCK + t of the unit
+    // gather: item i of thread t is record i * UBLOCK + t of the unit, kept
+    // packed as local context << 26 | D << 4 | stall (D < 2^22)
+    uint32_t key[UITEMS], val[UITEMS];
+    uint32_t dmin = 0xFFFFFFFFu, dmax = 0;
+    {
+      uint32_t lo = 0;
+#pragma unroll
+      for (int i = 0; i < UITEMS; ++i) {
+        const uint32_t j = (uint32_t)i * UBLOCK + tid;
+        key[i] = 0;
+        val[i] = 0;
+        if (j < n_u) {
+          uint32_t r = rec[d.s0 + j];
+          if (r == FAR_REC) r = 0;  // the call is redone by the general path
+          uint32_t hi = nl;  // last l with lstart[l] <= j, from the previous item's context on
+          while (hi - lo > 1) {
+            const uint32_t mid = (lo + hi) >> 1;
+            if (du.lstart[mid] <= j) lo = mid;
+            else hi = mid;
+          }
+          key[i] = (lo << 26) | (r & 0x3FFFFFFu);
+          if constexpr (WEIGHTED) val[i] = rw[d.s0 + j];
+          const uint32_t D = (r >> 4) & 0x3FFFFFu;
+          dmin = min(dmin, D);
+          dmax = max(dmax, D);
+        }
+      }
+    }
+    unsigned long long P = 0;
+    uint32_t first = 0, nU = 0;
+    if (n_u == 0) {  // only empty contexts
+      if (tid == 0) du.P = look_back(a.status, t, 0, &a.info->err);
+      __syncthreads();
+      P = du.P;
+    } else {
+      // unit-wide coordinate range: keys are taken relative to its smallest
+      dmin = wave_min(dmin);
+      dmax = wave_max(dmax);
+      if (lane_id() == 0) {
+        atomicMin(&du.red_min, dmin);
+        atomicMax(&du.red_max, dmax);
+      }
+      __syncthreads();
+      dmin = du.red_min;
+      const int pcb = bits_for(du.red_max - dmin);
+      const int kbits = bits_for(nl - 1) + pcb + 4;
+      // the plan keeps local contexts few enough that keys fit 31 bits
+      if (kbits > 31 && tid == 0) atomicOr(&a.info->err, DERR_WIDE);
+      const uint32_t empty = 1u << min(kbits, 31);
+#pragma unroll
+      for (int i = 0; i < UITEMS; ++i) {
+        const uint32_t j = (uint32_t)i * UBLOCK + tid;
+        const uint32_t v = key[i];
+        key[i] = j < n_u ? ((v >> 26) << (pcb + 4)) | ((((v >> 4) & 0x3FFFFFu) - dmin) << 4) | (v & 15u) : empty;
+      }
+      // empty slots sort after every key: kbits + 1 bits, no per-slot test
+      if constexpr (WEIGHTED)
+        Sorter::template sort<1, true>(key, val, val, min(kbits, 31) + 1, (int)n_u, true, sm.buf, sm.cnt, sm.doff);
+      else
+        Sorter::template sort<0, true>(key, val, val, min(kbits, 31) + 1, (int)n_u, true, sm.buf, sm.cnt, sm.doff);
+      find_heads<uint32_t>(sm, key, n_u, nl, pcb, first, nU);
+      if (tid == 0) du.P = look_back(a.status, t, nU, &a.info->err);
+      __syncthreads();
+      P = du.P;
+      if constexpr (WEIGHTED) weighted_counts<uint32_t>(sm, key, val, n_u, first, a.out.count + P);
+      // consecutive threads take consecutive keys from the compacted copy
+      const uint32_t pmask = (1u << pcb) - 1u;
+      for (uint32_t ui = tid; ui < nU; ui += UBLOCK) {
+        const uint32_t kk = sm.buf[ui];
+        const uint32_t lc = kk >> (pcb + 4);
+        const uint64_t D = dmin + ((kk >> 4) & pmask);
+        const uint64_t o = P + ui;
+        a.out.ctx[o] = du.lctx[lc < nl ? lc : 0];
+        a.out.pc[o] = from_dense(a.dd, D);
+        a.out.stall[o] = (uint8_t)(kk & 15u);
+        if constexpr (!WEIGHTED) a.out.count[o] = (uint32_t)sm.upos[ui + 1] - (uint32_t)sm.upos[ui];
+        a.out.scope[o] = a.dd.scope_of[D];
+      }
+    }
+    // context offsets: every context of the unit (empty ones included) starts
+    // after the keys of the non-empty contexts before it
+    if (tid < MAXC + 1) {
+      // du.loff[l] = keys of local contexts before l (sm.ucnt holds keys per local context)
+      const uint32_t l = (uint32_t)tid;
+      const uint32_t v = n_u > 0 && l < nl ? sm.ucnt[l] : 0u;
+      if (tid < WAVE) {
+        const uint32_t inc = wave_incl_scan(v);
+        du.loff[l] = inc - v;
+        if (l == WAVE - 1) du.loff[MAXC] = inc;
+      }
+    }
+    __syncthreads();
+    if (part) {
+      if (tid == 0 && d.s0 == a.cbase[d.cb]) a.out.ctx_off[d.cb] = P;
+    } else {
+      for (uint32_t i = tid; i < d.ce - d.cb; i += UBLOCK) {
+        const uint32_t r = du.lrank[i];
+        a.out.ctx_off[d.cb + i] = P + du.loff[r < nl ? r : nl];
+      }
+    }
+    if (tid == 0 && t == n_units - 1) {
+      a.out.ctx_off[a.C] = P + nU;
+      a.info->total_keys = P + nU;
+    }
+    __syncthreads();
+  }
+}
+
+}  // namespace
+
+// ---------------------------------------------------------------------------
+// host
+// ---------------------------------------------------------------------------
+bool dense_path_fits(const hpa_structure_map* map, const hpa_samples* smp) {
+  if (!map->dense || map->n_win == 0 || map->n_win > DENSE_MAX_WIN) return false;
+  if (smp->n >= (1ull << 32) - 1 || smp->n_ctx >= (1u << 31)) return false;
+  // a bucket of a big context is counted in LDS: its coordinates times the
+  // stall reasons must fit HOT_KEYS counters, with DNB buckets covering the map
+  uint32_t bshift = 0;
+  while (((map->n_dense - 1) >> bshift) >= (uint64_t)DNB) ++bshift;
+  return ((uint64_t)NS << bshift) <= (uint64_t)HOT_KEYS && map->n_dense < (1ull << 28);
+}
+
+// Returns false (nothing written, no error) when a sample's pc has no dense
+// coordinate: the caller then runs the general pipeline.
+bool attribute_dense(hpa_ctx* ctx, const hpa_structure_map* map, const hpa_samples* smp, hipStream_t s,
+                     hpa_attribution* A) {
+  const uint64_t n = smp->n;
+  const uint32_t C = smp->n_ctx;
+  const bool weighted = smp->weight != nullptr;
+  StageTimer tm(ctx, s);
+  uint32_t bshift = 0;
+  while (((map->n_dense - 1) >> bshift) >= (uint64_t)DNB) ++bshift;
+  const uint32_t n_tiles = (C + DTILE - 1) / DTILE;
+  // key = (local context, coordinate offset, stall) in 31 bits: the offset
+  // needs at most the bits of n_dense - 1, so a unit takes at most
+  // 2^(27 - those bits) non-empty contexts (and at most MAXC)
+  uint32_t dbits = 0;
+  while (dbits < 64 && ((map->n_dense - 1) >> dbits)) ++dbits;
+  const uint32_t maxc = dbits >= 27 ? 1u : std::min<uint32_t>((uint32_t)MAXC, 1u << (27 - dbits));
+  const uint64_t max_big = n / (UT + 1) + 1;
+  // sum over big contexts of 2 * ceil(n_c / UT) + 1 <= 2 * (N / UT + n_big) + n_big
+  const uint64_t max_bslots = 2 * (n / UT) + 3 * max_big + 8;
+  const uint64_t max_units = (uint64_t)C + max_bslots + n_tiles;
+  DBuf d_info(ctx, sizeof(DInfo), s), d_hist(ctx, (uint64_t)C * 4, s), d_cbase(ctx, ((uint64_t)C + 1) * 4, s),
+      d_cursor(ctx, (uint64_t)C * 4, s), d_bidx(ctx, (uint64_t)C * 4, s),
+      d_ts(ctx, (uint64_t)n_tiles * sizeof(DTileSums), s), d_bctx(ctx, max_big * 4, s),
+      d_bslot0(ctx, max_big * 4, s), d_nbu(ctx, max_big * 4, s), d_bunits(ctx, max_bslots * sizeof(DUnit), s),
+      d_tu(ctx, (uint64_t)n_tiles * 4, s), d_toff(ctx, (uint64_t)n_tiles * 4, s),
+      d_units(ctx, max_units * sizeof(DUnit), s), d_status(ctx, max_units * 8, s), d_rec(ctx, n * 4, s),
+      d_rec2(ctx, n * 4, s), d_rw, d_rw2;
+  if (weighted) {
+    d_rw = DBuf(ctx, n * 4, s);
+    d_rw2 = DBuf(ctx, n * 4, s);
+  }
+  HPA_HIP(hipMemsetAsync(d_info.p, 0, sizeof(DInfo), s));
+  HPA_HIP(hipMemsetAsync(d_hist.p, 0, (uint64_t)C * 4, s));
+  HPA_HIP(hipMemsetAsync(d_cursor.p, 0, (uint64_t)C * 4, s));
+  HPA_HIP(hipMemsetAsync(d_status.p, 0, max_units * 8, s));
+  DInfo* info = d_info.as<DInfo>();
+  const bool vec = ((uintptr_t)smp->pc % 16 == 0) && ((uintptr_t)smp->ctx % 16 == 0) &&
+                   ((uintptr_t)smp->stall % 4 == 0) && (!weighted || (uintptr_t)smp->weight % 16 == 0);
+  const unsigned grid = (unsigned)std::max<uint64_t>(
+      1, std::min<uint64_t>((n + DCH * (DB / WAVE) - 1) / (DCH * (DB / WAVE)), (uint64_t)ctx->n_cu * 8));
+  tm.begin("d_hist");
+  if (vec) k_d_hist<true><<<grid, DB, 0, s>>>(smp->ctx, n, C, d_hist.as<uint32_t>(), info);
+  else k_d_hist<false><<<grid, DB, 0, s>>>(smp->ctx, n, C, d_hist.as<uint32_t>(), info);
+  HPA_HIP(hipGetLastError());
+  tm.end(n, 0);
+  tm.begin("d_bases");
+  k_d_tile_sums<<<n_tiles, DTILE, 0, s>>>(d_hist.as<uint32_t>(), C, d_ts.as<DTileSums>());
+  k_d_tile_scan<<<1, 1024, 0, s>>>(d_ts.as<DTileSums>(), n_tiles, info);
+  k_d_bases<<<n_tiles, DTILE, 0, s>>>(d_hist.as<uint32_t>(), C, d_ts.as<DTileSums>(), d_cbase.as<uint32_t>(),
+                                      d_bidx.as<uint32_t>(), d_bctx.as<uint32_t>(), d_bslot0.as<uint32_t>());
+  HPA_HIP(hipGetLastError());
+  tm.end(C, 0);
+  const DenseDev dd{map->win_lo.as<uint64_t>(), map->win_hi.as<uint64_t>(), map->win_d.as<uint64_t>(),
+                    map->scope_of.as<uint32_t>(), map->n_win, map->dense_tz};
+  tm.begin("d_scatter");
+#define HPA_SCATTER(V, W)                                                                                       \
+  k_d_scatter<V, W><<<grid, DB, 0, s>>>(smp->pc, smp->ctx, smp->stall, smp->weight, n, C, d_cbase.as<uint32_t>(), \
+                                        d_cursor.as<uint32_t>(), dd, d_rec.as<uint32_t>(), d_rw.as<uint32_t>(), info)
+  if (vec) {
+    if (weighted) HPA_SCATTER(true, true);
+    else HPA_SCATTER(true, false);
+  } else {
+    if (weighted) HPA_SCATTER(false, true);
+    else HPA_SCATTER(false, false);
+  }
+#undef HPA_SCATTER
+  HPA_HIP(hipGetLastError());
+  tm.end(n, n);
+  tm.begin("d_split");
+  if (weighted)
+    k_d_split<true><<<(unsigned)max_big, SB, 0, s>>>(d_bctx.as<uint32_t>(), d_bslot0.as<uint32_t>(),
+                                                     d_cbase.as<uint32_t>(), d_rec.as<uint32_t>(),
+                                                     d_rw.as<uint32_t>(), bshift, d_rec2.as<uint32_t>(),
+                                                     d_rw2.as<uint32_t>(), d_bunits.as<DUnit>(),
+                                                     d_nbu.as<uint32_t>(), info);
+  else
+    k_d_split<false><<<(unsigned)max_big, SB, 0, s>>>(d_bctx.as<uint32_t>(), d_bslot0.as<uint32_t>(),
+                                                      d_cbase.as<uint32_t>(), d_rec.as<uint32_t>(), nullptr, bshift,
+                                                      d_rec2.as<uint32_t>(), nullptr, d_bunits.as<DUnit>(),
+                                                      d_nbu.as<uint32_t>(), info);
+  HPA_HIP(hipGetLastError());
+  tm.end();
+  tm.begin("d_plan");
+  k_d_plan<<<n_tiles, DB, 0, s>>>(d_hist.as<uint32_t>(), C, maxc, d_bidx.as<uint32_t>(), d_bunits.as<DUnit>(),
+                                  d_bslot0.as<uint32_t>(), d_nbu.as<uint32_t>(), d_cbase.as<uint32_t>(),
+                                  d_tu.as<uint32_t>(), nullptr, nullptr);
+  k_d_unit_scan<<<1, 1024, 0, s>>>(d_tu.as<uint32_t>(), n_tiles, d_toff.as<uint32_t>(), info);
+  k_d_plan<<<n_tiles, DB, 0, s>>>(d_hist.as<uint32_t>(), C, maxc, d_bidx.as<uint32_t>(), d_bunits.as<DUnit>(),
+                                  d_bslot0.as<uint32_t>(), d_nbu.as<uint32_t>(), d_cbase.as<uint32_t>(),
+                                  d_tu.as<uint32_t>(), d_toff.as<uint32_t>(), d_units.as<DUnit>());
+  HPA_HIP(hipGetLastError());
+  tm.end();
+  // outputs (the key count is known only at the end: room for n keys)
+  const uint64_t cap = n ? n : 1;
+  if (!A->ctx_id.p) {
+    A->ctx_id = DBuf(ctx, cap * 4, s);
+    A->pc = DBuf(ctx, cap * 8, s);
+    A->stall = DBuf(ctx, cap, s);
+    A->count = DBuf(ctx, cap * 8, s);
+    A->scope = DBuf(ctx, cap * 4, s);
+    A->ctx_offsets = DBuf(ctx, ((uint64_t)C + 1) * 8, s);
+  }
+  DUnitArgs ua{};
+  ua.units = d_units.as<DUnit>();
+  ua.rec = d_rec.as<uint32_t>();
+  ua.rw = d_rw.as<uint32_t>();
+  ua.rec2 = d_rec2.as<uint32_t>();
+  ua.rw2 = d_rw2.as<uint32_t>();
+  ua.hist = d_hist.as<uint32_t>();
+  ua.cbase = d_cbase.as<uint32_t>();
+  ua.C = C;
+  ua.bshift = bshift;
+  ua.dd = dd;
+  ua.info = info;
+  ua.status = d_status.as<unsigned long long>();
+  ua.out = OutDev{A->ctx_id.as<uint32_t>(), A->pc.as<uint64_t>(), A->stall.as<uint8_t>(),
+                  A->count.as<unsigned long long>(), A->scope.as<uint32_t>(), A->ctx_offsets.as<uint64_t>()};
+  // one resident workgroup per compute unit (the sort uses most of the LDS)
+  const unsigned ugrid = (unsigned)std::max<uint64_t>(1, std::min<uint64_t>(max_units, (uint64_t)ctx->n_cu));
+  tm.begin("units_dense");
+  if (weighted) k_d_units<true><<<ugrid, UBLOCK, 0, s>>>(ua);
+  else k_d_units<false><<<ugrid, UBLOCK, 0, s>>>(ua);
+  HPA_HIP(hipGetLastError());
+  tm.end();
+  DInfo h{};
+  HPA_HIP(hipMemcpyAsync(&h, d_info.p, sizeof(h), hipMemcpyDeviceToHost, s));
+  HPA_HIP(hipStreamSynchronize(s));
+  if (h.err & DERR_CTX) fail(HPA_E_INVAL, "a sample has ctx >= n_ctx");
+  if (h.err & DERR_STALL) fail(HPA_E_INVAL, "a sample has stall >= 16");
+  if (h.n_far) return false;  // the general path handles pcs without dense coordinates
+  if (h.err & DERR_OVERFLOW) return false;  // a counted part's weights overflow 32 bits
+  if (h.err & (DERR_INTERNAL | DERR_LOOKBACK | DERR_WIDE))
+    fail(HPA_E_DEVICE, "internal error in the dense attribution pipeline (flags " + std::to_string(h.err) + ")");
+  A->n_keys = h.total_keys;
+  if (tm.on()) {
+    tm.items("units_dense", n, h.total_keys);
+    tm.items("d_split", 0, h.n_big);
+    tm.items("d_plan", C, h.n_units);
+    tm.collect();
+  }
+  return true;
+}
+
+}  // namespace hpa

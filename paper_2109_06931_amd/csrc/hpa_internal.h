@@ -283,6 +283,15 @@ void launch_lookup_learned(const hpa_structure_map* m, const uint64_t* pc, uint6
                            hipStream_t s);
 void learned_free(LearnedModel* lm);
 void learned_train(hpa_structure_map* m, const hpa_learned_opts* opts, hipStream_t s);
+// Attribution over dense instruction coordinates, driven from the device with
+// one synchronisation (attribute_dense.hip).  dense_path_fits tells whether
+// the map and input sizes allow it; attribute_dense returns false, with no
+// error, when some sample's pc has no dense coordinate (the caller then runs
+// the general pipeline into the same handle).
+bool dense_path_fits(const hpa_structure_map* map, const hpa_samples* smp);
+bool attribute_dense(hpa_ctx* ctx, const hpa_structure_map* map, const hpa_samples* smp, hipStream_t s,
+                     hpa_attribution* A);
+
 // in-place exclusive scan of n u64 values; *d_total (device) receives the sum
 void exscan_u64(hpa_ctx* ctx, unsigned long long* v, uint64_t n, unsigned long long* d_total, hipStream_t s);
 
