@@ -45,10 +45,10 @@ if ROOT not in sys.path:
     sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBPS = 8000.0  # MI355X HBM3E, published
-TRAFFIC_FILE = os.path.join(ROOT, "profiles", "k_units32_medium_traffic.json")
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "k_d_units_medium_traffic.json")
 # the unit kernel's sources, in the order their hash is taken
 UNITS_SRCS = [os.path.join(ROOT, "paper_2109_06931_amd", "csrc", f)
-              for f in ("attribute.hip", "block_prims.h", "hpa_internal.h")]
+              for f in ("attribute_dense.hip", "unit_sort.h", "block_prims.h", "hpa_internal.h")]
 SECTIONS = ("tiny", "cct", "learned", "batched", "serve")
 
 
@@ -440,14 +440,25 @@ def main():
 
     M = m.n_intervals
     b_alg = 13.0 + 25.0 * U / N + 16.0 * M / N
-    # the unit sort kernel (its launch over the units read through the run
-    # list) reads its samples (13 B each by the record layout)
-    u = stages.get("units_plain", {})
-    u_ms = u.get("ms", 0.0) / max(u.get("calls", 1), 1)
-    u_bytes = 13.0 * u.get("items_in", 0) / max(u.get("calls", 1), 1)
+    if "units_dense" in stages:
+        # the dense pipeline's unit kernel reads each 4-byte record (and its
+        # 4-byte weight) once and writes each key once (25 B)
+        u = stages["units_dense"]
+        calls = max(u.get("calls", 1), 1)
+        per_rec = 8.0 if wt is not None else 4.0
+        u_bytes = (per_rec * u.get("items_in", 0) + 25.0 * u.get("items_out", 0)) / calls
+        kname = "k_d_units<%s>" % ("true" if wt is not None else "false")
+    else:
+        # the general pipeline's unit sort kernel (its launch over the units
+        # read through the run list) reads its samples (13 B each)
+        u = stages.get("units_plain", {})
+        calls = max(u.get("calls", 1), 1)
+        u_bytes = 13.0 * u.get("items_in", 0) / calls
+        kname = "k_units32<false, false, false>"
+    u_ms = u.get("ms", 0.0) / calls
     achieved = u_bytes / (u_ms * 1e-3) / 1e9 if u_ms > 0 else 0.0
     traffic = _units_traffic()
-    roofline = {"bound": "hbm", "kernel": "k_units32<false, false, false>", "achieved": round(achieved, 1),
+    roofline = {"bound": "hbm", "kernel": kname, "achieved": round(achieved, 1),
                 "peak": HBM_PEAK_GBPS, "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBPS, 4),
                 "traffic": None if traffic is None else round(traffic),
                 "launch_ms": round(u_ms, 3), "algorithmic_bytes": round(u_bytes)}

@@ -122,6 +122,11 @@ typedef struct {
   uint64_t items_in;    /* summed over calls */
   uint64_t items_out;
 } hpa_stage_time;
+/* Number of times the library's calls on this context have waited for a
+ * stream on the host (every synchronisation of every entry point is counted),
+ * into *out (host).  A profiling aid: the difference around a call is the
+ * number of times that call synchronised.  Errors: HPA_E_INVAL (NULL). */
+hpa_status hpa_ctx_get_sync_count(const hpa_ctx* ctx, uint64_t* out);
 hpa_status hpa_ctx_set_timing(hpa_ctx* ctx, int enable);
 hpa_status hpa_ctx_get_timing(const hpa_ctx* ctx, hpa_stage_time* out, uint32_t cap, uint32_t* n_stages);
 
@@ -231,8 +236,8 @@ typedef struct {
 typedef struct {
   uint32_t n_leaves, train_steps;
   double train_mse;      /* mean squared error of the root on its training rows (rank fraction) */
-  double mean_window;    /* mean over leaves of (window below + window above + 1) */
-  uint32_t max_window;
+  double mean_window;    /* mean over the starts of their leaf's window (below + above + 1) */
+  uint32_t max_window;   /* largest window of a leaf that some start is routed to */
   uint64_t uncovered;    /* starts (or start - 1 addresses) whose miss exceeded window_cap */
   const float* params;   /* device: the root's HPA_LEARNED_NPARAM parameters */
 } hpa_learned_stats;

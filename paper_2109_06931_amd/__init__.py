@@ -160,6 +160,7 @@ def lib():
         L.hpa_ctx_destroy.argtypes = [P]
         L.hpa_ctx_destroy.restype = None
         L.hpa_ctx_set_timing.argtypes = [P, I]
+        L.hpa_ctx_get_sync_count.argtypes = [P, C.POINTER(U64)]
         L.hpa_ctx_get_timing.argtypes = [P, C.POINTER(_StageTime), U32, C.POINTER(U32)]
         L.hpa_build_structure_map.argtypes = [P, C.POINTER(_StructureDesc), P, PP]
         L.hpa_structure_map_view_get.argtypes = [P, C.POINTER(_MapView)]
@@ -305,6 +306,12 @@ class Context:
         _check(lib().hpa_ctx_create(device, C.byref(self._alloc) if self._alloc else None, C.byref(self.h)),
                "hpa_ctx_create")
         self.device = device
+
+    def sync_count(self) -> int:
+        """hpa_ctx_get_sync_count: host synchronisations the library has made on this context."""
+        n = U64(0)
+        _check(lib().hpa_ctx_get_sync_count(self.h, C.byref(n)), "hpa_ctx_get_sync_count")
+        return n.value
 
     def set_timing(self, on: bool = True):
         """hpa_ctx_set_timing: per-stage device timing of later calls (clears the table)."""

@@ -899,7 +899,7 @@ extern "C" hpa_status hpa_prepare_callgraph(hpa_ctx* ctx, const hpa_structure_ma
     for (uint32_t i = 1; i <= C; ++i)
       if (i == C || depth[P->h_depth_order[i]] != depth[P->h_depth_order[i - 1]]) P->h_depth_lvl.push_back(i);
     P->depth_lvl = up32(P->h_depth_lvl);
-    HPA_HIP(hipStreamSynchronize(stream));
+    sync_stream(ctx, stream);
     *out = hold.release();
   });
 }
@@ -1017,7 +1017,7 @@ extern "C" hpa_status hpa_apportion_callpaths(hpa_ctx* ctx, const hpa_callgraph_
     unsigned int err = 0;
     HPA_HIP(hipMemcpyAsync(tot, d_tot.p, sizeof(tot), hipMemcpyDeviceToHost, s));
     HPA_HIP(hipMemcpyAsync(&err, d_err.p, sizeof(err), hipMemcpyDeviceToHost, s));
-    HPA_HIP(hipStreamSynchronize(s));
+    sync_stream(ctx, s);
     check_err(err);
     if (opts && opts->required_nodes) *opts->required_nodes = tot[0];
     if (tot[0] >= SAT) fail(HPA_E_BUDGET, "the calling context tree has more than 2^62 nodes");
@@ -1060,7 +1060,7 @@ extern "C" hpa_status hpa_apportion_callpaths(hpa_ctx* ctx, const hpa_callgraph_
       k_apportion<<<n_wg, ABLOCK, 0, s>>>(a);
       HPA_HIP(hipGetLastError());
       HPA_HIP(hipMemcpyAsync(&err, d_err.p, sizeof(err), hipMemcpyDeviceToHost, s));
-      HPA_HIP(hipStreamSynchronize(s));
+      sync_stream(ctx, s);
       check_err(err);
     }
     *out = hold.release();

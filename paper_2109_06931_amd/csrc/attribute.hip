@@ -46,9 +46,9 @@ namespace {
 // ----------------------------------------------------------------------------
 // scan_ctx: run detection over ctx[] (Section 4.2: one placeholder per buffer)
 // ----------------------------------------------------------------------------
-// Each workgroup owns a contiguous range of tiles.  It counts the run heads of
-// its range first, reserves that many run slots with one atomic, then walks the
-// range again writing the runs and adding each run to its context's histogram
+// Workgroups take tiles of SCAN_TILE samples in turn.  For each tile the
+// workgroup finds the run heads, reserves that many run slots with one atomic
+// per tile, then writes the runs and adds each run to its context's histogram
 // word (one 64-bit atomic per run: run count << 40 | samples).  A run is cut at
 // every tile start.
 __device__ inline void scan_tile_heads(const uint32_t* __restrict__ ctx, uint64_t t0, int cnt, uint32_t* s_ctx,
@@ -1333,7 +1333,7 @@ hpa_attribution* attribute_impl(hpa_ctx* ctx, const hpa_structure_map* map, cons
     }
     if (n == 0) {
       HPA_HIP(hipMemsetAsync(A->ctx_offsets.p, 0, ((uint64_t)C + 1) * 8, s));
-      HPA_HIP(hipStreamSynchronize(s));
+      sync_stream(ctx, s);
       A->n_keys = 0;
       hold.release();
       return A;
@@ -1364,7 +1364,7 @@ hpa_attribution* attribute_impl(hpa_ctx* ctx, const hpa_structure_map* map, cons
     HPA_HIP(hipGetLastError());
     PlanInfo info;
     HPA_HIP(hipMemcpyAsync(&info, d_info.p, sizeof(info), hipMemcpyDeviceToHost, s));
-    HPA_HIP(hipStreamSynchronize(s));
+    sync_stream(ctx, s);
     if (info.err & ERR_CTX) fail(HPA_E_INVAL, "a sample has ctx >= n_ctx");
     const bool scattered = info.n_runs > run_cap;
     tm.end(n, 0);
@@ -1414,7 +1414,7 @@ hpa_attribution* attribute_impl(hpa_ctx* ctx, const hpa_structure_map* map, cons
                                            d_info.as<PlanInfo>());
       HPA_HIP(hipGetLastError());
       HPA_HIP(hipMemcpyAsync(&info, d_info.p, sizeof(info), hipMemcpyDeviceToHost, s));
-      HPA_HIP(hipStreamSynchronize(s));
+      sync_stream(ctx, s);
       CV = info.n_virtual;
       tm.end(info.split_samples, info.n_parts);
     }
@@ -1469,7 +1469,7 @@ hpa_attribution* attribute_impl(hpa_ctx* ctx, const hpa_structure_map* map, cons
       HPA_HIP(hipGetLastError());
     }
     HPA_HIP(hipMemcpyAsync(&info, d_info.p, sizeof(info), hipMemcpyDeviceToHost, s));
-    HPA_HIP(hipStreamSynchronize(s));
+    sync_stream(ctx, s);
     tm.end(CV, info.n_units);
     const uint32_t* vreal = split ? d_vreal.as<uint32_t>() : nullptr;
     // --- order samples by context ---
@@ -1648,7 +1648,7 @@ hpa_attribution* attribute_impl(hpa_ctx* ctx, const hpa_structure_map* map, cons
       tm.end();
     }
     HPA_HIP(hipMemcpyAsync(&info, d_info.p, sizeof(info), hipMemcpyDeviceToHost, s));
-    HPA_HIP(hipStreamSynchronize(s));
+    sync_stream(ctx, s);
     if (info.err & ERR_STALL) fail(HPA_E_INVAL, "a sample has stall >= 16");
     if (info.err & ERR_SPLIT) fail(HPA_E_DEVICE, "internal error: a split context's samples missed their parts");
     if (info.err & ERR_WIDE) fail(HPA_E_UNSUPPORTED, "the PCs of one context span more than 2^56 bytes");
@@ -1657,7 +1657,7 @@ hpa_attribution* attribute_impl(hpa_ctx* ctx, const hpa_structure_map* map, cons
       std::vector<uint64_t> bu(info.n_big);
       if (info.n_big) {
         HPA_HIP(hipMemcpyAsync(bu.data(), d_bigU.p, info.n_big * 8, hipMemcpyDeviceToHost, s));
-        HPA_HIP(hipStreamSynchronize(s));
+        sync_stream(ctx, s);
       }
       uint64_t big_keys = 0;
       for (uint64_t v : bu) big_keys += v;
@@ -1860,7 +1860,7 @@ void run_round(hpa_ctx* ctx, const hpa_profile_desc* pd, const hpa_samples* smp,
   HPA_HIP(hipGetLastError());
   PlanInfo info{};
   HPA_HIP(hipMemcpyAsync(&info, d_info.p, sizeof(info), hipMemcpyDeviceToHost, s));
-  HPA_HIP(hipStreamSynchronize(s));
+  sync_stream(ctx, s);
   if (info.err & ERR_CTX) fail(HPA_E_INVAL, "a sample's ctx is not below its profile's n_ctx");
   hpa_samples rs{smp->pc + r.s0, d_g.as<uint32_t>(), smp->stall + r.s0, smp->weight ? smp->weight + r.s0 : nullptr,
                  n, (uint32_t)G};
@@ -1879,7 +1879,7 @@ void run_round(hpa_ctx* ctx, const hpa_profile_desc* pd, const hpa_samples* smp,
   HPA_HIP(hipGetLastError());
   std::vector<uint64_t> k0(P + 1);
   HPA_HIP(hipMemcpyAsync(k0.data(), d_k0.p, (P + 1) * 8, hipMemcpyDeviceToHost, s));
-  HPA_HIP(hipStreamSynchronize(s));
+  sync_stream(ctx, s);
   const uint32_t ri = (uint32_t)B->rounds.size();
   for (uint32_t i = 0; i < P; ++i)
     B->prof.push_back(hpa_batch::Prof{ri, pd[r.p0 + i].n_ctx, k0[i], k0[i + 1] - k0[i], (uint64_t)cbase[i] + i});

@@ -923,7 +923,7 @@ bool attribute_dense(hpa_ctx* ctx, const hpa_structure_map* map, const hpa_sampl
   tm.end();
   DInfo h{};
   HPA_HIP(hipMemcpyAsync(&h, d_info.p, sizeof(h), hipMemcpyDeviceToHost, s));
-  HPA_HIP(hipStreamSynchronize(s));
+  sync_stream(ctx, s);
   if (h.err & DERR_CTX) fail(HPA_E_INVAL, "a sample has ctx >= n_ctx");
   if (h.err & DERR_STALL) fail(HPA_E_INVAL, "a sample has stall >= 16");
   if (h.n_far) return false;  // the general path handles pcs without dense coordinates

@@ -128,6 +128,13 @@ hpa_ctx::~hpa_ctx() {
 
 extern "C" void hpa_ctx_destroy(hpa_ctx* ctx) { delete ctx; }
 
+extern "C" hpa_status hpa_ctx_get_sync_count(const hpa_ctx* ctx, uint64_t* out) {
+  return guard([&] {
+    if (!ctx || !out) fail(HPA_E_INVAL, "NULL argument");
+    *out = ctx->n_syncs.load(std::memory_order_relaxed);
+  });
+}
+
 extern "C" hpa_status hpa_ctx_set_timing(hpa_ctx* ctx, int enable) {
   return guard([&] {
     if (!ctx) fail(HPA_E_INVAL, "ctx is NULL");
@@ -456,7 +463,7 @@ extern "C" hpa_status hpa_build_structure_map(hpa_ctx* ctx, const hpa_structure_
       m->h_end = std::move(b.end);
       m->h_scope = std::move(b.scope);
       if (desc->learned) learned_train(m, stream);
-      HPA_HIP(hipStreamSynchronize(stream));
+      sync_stream(ctx, stream);
     } catch (...) {
       delete m;
       throw;

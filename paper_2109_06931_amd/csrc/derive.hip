@@ -385,7 +385,7 @@ extern "C" hpa_status hpa_derive_metrics(hpa_ctx* ctx, const hpa_callgraph_plan*
       unsigned int err = 0;
       HPA_HIP(hipMemcpyAsync(&tot, d_tot.p, 8, hipMemcpyDeviceToHost, s));
       HPA_HIP(hipMemcpyAsync(&err, d_err.p, 4, hipMemcpyDeviceToHost, s));
-      HPA_HIP(hipStreamSynchronize(s));
+      sync_stream(ctx, s);
       check_err(err);
       M->n_rows = tot;
       M->sc_scope = DBuf(ctx, std::max<uint64_t>(tot, 1) * 4, s);
@@ -398,7 +398,7 @@ extern "C" hpa_status hpa_derive_metrics(hpa_ctx* ctx, const hpa_callgraph_plan*
       k_scope<<<nwg_s, DBLOCK, 0, s>>>(sa);
       HPA_HIP(hipGetLastError());
       HPA_HIP(hipMemcpyAsync(&err, d_err.p, 4, hipMemcpyDeviceToHost, s));
-      HPA_HIP(hipStreamSynchronize(s));
+      sync_stream(ctx, s);
       check_err(err);
     }
     *out = hold.release();

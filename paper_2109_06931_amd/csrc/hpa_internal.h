@@ -4,6 +4,7 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <atomic>
 #include <cstdint>
 #include <cstring>
 #include <map>
@@ -60,6 +61,7 @@ struct hpa_ctx {
   hpa_allocator alloc{};
   bool custom = false;
   int n_cu = 256;
+  std::atomic<uint64_t> n_syncs{0};  // host synchronisations made by the library's calls
   bool timing = false;
   std::vector<hpa_stage_time> stages;  // accumulated stage timings
   // Device blocks released by the library's buffers, by size, with the
@@ -89,6 +91,13 @@ struct Arena {
   size_t size = 0, off = 0, peak = 0;
 };
 extern thread_local Arena t_arena;
+
+// Wait for the stream on the host, counted on the context (the count is
+// reported by hpa_ctx_get_sync_count).
+inline void sync_stream(hpa_ctx* ctx, hipStream_t s) {
+  ctx->n_syncs.fetch_add(1, std::memory_order_relaxed);
+  HPA_HIP(hipStreamSynchronize(s));
+}
 
 // dalloc returns a block of at least `bytes` and its capacity in *cap; dfree
 // takes the block back with that capacity.
@@ -132,7 +141,7 @@ DBuf upload(hpa_ctx* ctx, const std::vector<T>& v, hipStream_t s) {
   DBuf b(ctx, std::max<size_t>(v.size(), 1) * sizeof(T), s);
   if (!v.empty()) {
     HPA_HIP(hipMemcpyAsync(b.p, v.data(), v.size() * sizeof(T), hipMemcpyHostToDevice, s));
-    HPA_HIP(hipStreamSynchronize(s));
+    sync_stream(ctx, s);
   }
   return b;
 }

@@ -553,7 +553,7 @@ void learned_train(hpa_structure_map* m, const hpa_learned_opts* o, hipStream_t 
     HPA_HIP(hipGetLastError());
     float loss = 0.f;
     HPA_HIP(hipMemcpyAsync(&loss, g.as<float>() + NPARAM, 4, hipMemcpyDeviceToHost, s));
-    HPA_HIP(hipStreamSynchronize(s));
+    sync_stream(ctx, s);
     lm->st.train_mse = (double)loss / (double)n_rows;
   }
   tm.end(n_rows, 0);
@@ -587,22 +587,27 @@ void learned_train(hpa_structure_map* m, const hpa_learned_opts* o, hipStream_t 
   HPA_HIP(hipGetLastError());
   tm.end(M, 0);
   std::vector<uint32_t> elo(NL), ehi(NL);
+  std::vector<double> hs(5ull * NL);
   unsigned long long uncovered = 0;
+  HPA_HIP(hipMemcpyAsync(hs.data(), sums.p, 5ull * NL * 8, hipMemcpyDeviceToHost, s));
   HPA_HIP(hipMemcpyAsync(elo.data(), lm->elo.p, (uint64_t)NL * 4, hipMemcpyDeviceToHost, s));
   HPA_HIP(hipMemcpyAsync(ehi.data(), lm->ehi.p, (uint64_t)NL * 4, hipMemcpyDeviceToHost, s));
   HPA_HIP(hipMemcpyAsync(&uncovered, unc.p, 8, hipMemcpyDeviceToHost, s));
-  HPA_HIP(hipStreamSynchronize(s));
+  sync_stream(ctx, s);
   tm.collect();
-  double sumw = 0.0;
+  // the window a lookup searches, averaged over the starts (each start
+  // weighs by the leaf it is routed to)
+  double sumw = 0.0, n_routed = 0.0;
   uint32_t maxw = 0;
   for (uint32_t L = 0; L < NL; ++L) {
     const uint32_t w = elo[L] + ehi[L] + 1;
-    sumw += w;
-    maxw = std::max(maxw, w);
+    sumw += hs[5ull * L] * w;
+    n_routed += hs[5ull * L];
+    if (hs[5ull * L] > 0.0) maxw = std::max(maxw, w);
   }
   lm->st.n_leaves = NL;
   lm->st.train_steps = d.train_steps;
-  lm->st.mean_window = sumw / NL;
+  lm->st.mean_window = n_routed > 0.0 ? sumw / n_routed : 0.0;
   lm->st.max_window = maxw;
   lm->st.uncovered = uncovered;
   if (m->learned) learned_free(m->learned);
@@ -682,6 +687,6 @@ extern "C" hpa_status hpa_learned_grad(hpa_ctx* ctx, const float* d_params, cons
     k_mlp_reduce<<<(NPARAM + 1 + 255) / 256, 256, 0, stream>>>(part.as<float>(), nb, d_grad, nullptr, nullptr, nullptr,
                                                                0, 0.f, 1.f, 1.f);
     HPA_HIP(hipGetLastError());
-    HPA_HIP(hipStreamSynchronize(stream));
+    sync_stream(ctx, stream);
   });
 }

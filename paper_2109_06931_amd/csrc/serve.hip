@@ -429,7 +429,7 @@ extern "C" hpa_status hpa_server_create(hpa_ctx* ctx, const hpa_structure_map* m
       sl.h_err = reinterpret_cast<unsigned int*>(sl.h_stage + S->h_stage_bytes);
       *sl.h_err = 0;
     }
-    HPA_HIP(hipStreamSynchronize(s));
+    sync_stream(ctx, s);
     S->worker = std::thread([S] { S->run(); });
     *out = hold.release();
   });
@@ -534,7 +534,7 @@ extern "C" hpa_status hpa_server_snapshot(hpa_server* S, uint32_t profile, hipSt
     HPA_HIP(hipGetLastError());
     unsigned long long n = 0;
     HPA_HIP(hipMemcpyAsync(&n, tot.p, 8, hipMemcpyDeviceToHost, stream));
-    HPA_HIP(hipStreamSynchronize(stream));
+    sync_stream(ctx, stream);
     const uint64_t n1 = std::max<uint64_t>(n, 1);
     DBuf r_pc(ctx, n1 * 8, stream), r_ctx(ctx, n1 * 4, stream), r_st(ctx, n1, stream), r_w(ctx, n1 * 4, stream);
     k_snap<<<nb, SB, 0, stream>>>(keys, cnts, T, S->pc_keys.as<unsigned long long>(), S->pc_mask, 1,

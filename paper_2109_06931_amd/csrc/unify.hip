@@ -348,7 +348,7 @@ hpa_attribution* records_attribution(hpa_ctx* ctx, const hpa_attribution* a0, co
     exscan_u64(ctx, nrec.as<unsigned long long>(), K, tot.as<unsigned long long>(), s);
     unsigned long long r = 0;
     HPA_HIP(hipMemcpyAsync(&r, tot.p, 8, hipMemcpyDeviceToHost, s));
-    HPA_HIP(hipStreamSynchronize(s));
+    sync_stream(ctx, s);
     R = r;
   }
   const uint64_t R1 = std::max<uint64_t>(R, 1);
@@ -408,7 +408,7 @@ extern "C" hpa_status hpa_unify_profiles(hpa_ctx* ctx, uint32_t n_profiles, cons
     unsigned int e = 0;
     HPA_HIP(hipMemcpyAsync(sizes, tot.p, 16, hipMemcpyDeviceToHost, s));
     HPA_HIP(hipMemcpyAsync(&e, err.p, 4, hipMemcpyDeviceToHost, s));
-    HPA_HIP(hipStreamSynchronize(s));
+    sync_stream(ctx, s);
     if (e) fail(HPA_E_INVAL, "a key of some profile is missing from the union (duplicate or unsorted keys?)");
     const uint64_t nnz = sizes[0], NM = sizes[1];
     R->n_midx = NM;
@@ -460,7 +460,7 @@ extern "C" hpa_status hpa_unify_profiles(hpa_ctx* ctx, uint32_t n_profiles, cons
     }
     unsigned long long nh = 0;
     HPA_HIP(hipMemcpyAsync(&nh, htot.p, 8, hipMemcpyDeviceToHost, s));
-    HPA_HIP(hipStreamSynchronize(s));
+    sync_stream(ctx, s);
     R->n_heads = nh;
     const uint64_t NH1 = std::max<uint64_t>(nh, 1);
     R->pms_off = DBuf(ctx, ((uint64_t)P + 1) * 8, s);
@@ -476,7 +476,7 @@ extern "C" hpa_status hpa_unify_profiles(hpa_ctx* ctx, uint32_t n_profiles, cons
     k_pms_offsets<<<(P + 1 + 255) / 256, 256, 0, s>>>(d_pd.as<ProfDev>(), P, K, head.as<unsigned long long>(), nh,
                                                      R->pms_off.as<uint64_t>(), R->pms_c_off.as<uint64_t>());
     HPA_HIP(hipGetLastError());
-    HPA_HIP(hipStreamSynchronize(s));
+    sync_stream(ctx, s);
     *out = hold.release();
   });
 }
@@ -520,13 +520,13 @@ namespace {
 
 // Write `bytes` of device memory at file offset `off`, through a host bounce
 // buffer of at most `round` bytes per step.
-void write_section(FILE* f, uint64_t off, const void* dev, uint64_t bytes, std::vector<uint8_t>& bounce,
-                   hipStream_t s) {
+void write_section(hpa_ctx* ctx, FILE* f, uint64_t off, const void* dev, uint64_t bytes,
+                   std::vector<uint8_t>& bounce, hipStream_t s) {
   uint64_t done = 0;
   while (done < bytes) {
     const uint64_t k = std::min<uint64_t>(bounce.size(), bytes - done);
     HPA_HIP(hipMemcpyAsync(bounce.data(), static_cast<const uint8_t*>(dev) + done, k, hipMemcpyDeviceToHost, s));
-    HPA_HIP(hipStreamSynchronize(s));
+    sync_stream(ctx, s);
     if (fseeko(f, (off_t)(off + done), SEEK_SET) != 0 || fwrite(bounce.data(), 1, k, f) != k)
       fail(HPA_E_DEVICE, "writing the sparse file failed");
     done += k;
@@ -581,7 +581,7 @@ extern "C" hpa_status hpa_unified_write(const hpa_unified* u, const char* path, 
     if (fwrite(hdr, 8, 8, f) != 8 || fwrite(off.data(), 8, off.size(), f) != off.size())
       fail(HPA_E_DEVICE, "writing the sparse file header failed");
     for (size_t i = 0; i < secs.size(); ++i)
-      if (secs[i].bytes) write_section(f, off[i], secs[i].p, secs[i].bytes, bounce, stream);
+      if (secs[i].bytes) write_section(u->ctx, f, off[i], secs[i].p, secs[i].bytes, bounce, stream);
   });
 }
 

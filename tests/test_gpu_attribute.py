@@ -128,22 +128,36 @@ def test_attribute_small(hpa, hctx, seed, kw):
     (10, dict(n_ctx=6, n_samples=600_000), True),
 ])
 def test_attribute_split_big_contexts(hpa, hctx, seed, kw, fallback):
+    """Contexts over 16,384 samples, on both pipelines.  The dense pipeline
+    cuts them into coordinate-bucket parts (a bucket over 16,384 samples is
+    counted).  A few far pcs in one small context send the same call to the
+    general pipeline, whose split and chunk paths the stage timer shows."""
     kw = dict(kw)
     w = small_config(seed, n_samples=kw.pop("n_samples", 300_000), **kw)
-    hctx.set_timing(True)
-    try:
-        m, om, a, oa = _run(hpa, hctx, w)
-        stages = hctx.timing()
-    finally:
-        hctx.set_timing(False)
-    assert_attribution_equal(a.numpy(), oa, f"split{seed}{kw}")
-    split_in = stages.get("split_plan", {}).get("items_in", 0)
-    if seed == 10:
-        assert split_in == 0
-    else:
-        assert split_in > 0, "no context was split"
-    if fallback:
-        assert stages.get("big_sort", {}).get("items_in", 0) > 0, "no context kept the chunk path"
+    for far in (False, True):
+        if far:
+            hist = np.bincount(w.ctx, minlength=w.n_ctx)
+            smallest = int(np.argmin(np.where(hist > 0, hist, np.iinfo(np.int64).max)))
+            idx = np.flatnonzero(w.ctx == smallest)[:3]
+            w.pc[idx] += np.uint64(1 << 50)
+        hctx.set_timing(True)
+        try:
+            m, om, a, oa = _run(hpa, hctx, w)
+            stages = hctx.timing()
+        finally:
+            hctx.set_timing(False)
+        assert_attribution_equal(a.numpy(), oa, f"split{seed}{kw} far={far}")
+        if not far:
+            assert stages.get("d_split", {}).get("items_out", 0) > 0, "no big context on the dense pipeline"
+            continue
+        assert "d_split" not in stages, "the dense pipeline finished despite far pcs"
+        split_in = stages.get("split_plan", {}).get("items_in", 0)
+        if seed == 10:
+            assert split_in == 0
+        else:
+            assert split_in > 0, "no context was split"
+        if fallback:
+            assert stages.get("big_sort", {}).get("items_in", 0) > 0, "no context kept the chunk path"
 
 
 def test_attribute_config1(hpa, hctx):
@@ -326,3 +340,25 @@ def test_attribute_allocator_returning_null(hpa):
         _run(hpa, c, w)
     assert ei.value.code == hpa.E_NOMEM
     del c
+
+
+def test_attribute_synchronises_once(hpa, hctx):
+    """With dense coordinates and every pc on them, hpa_attribute waits for the
+    stream exactly once (to learn the key count); a pc off the coordinates
+    makes the call redo the work on the general path, which waits more."""
+    w = small_config(23, n_samples=200_000)
+    m = hpa.build_structure_map_workload(hctx, w)
+    pc, cx, st, wt = hpa.samples_to_device(w)
+    torch.cuda.synchronize()
+    n0 = hctx.sync_count()
+    a = hpa.attribute(hctx, m, pc, cx, st, wt, w.n_ctx)
+    assert hctx.sync_count() - n0 == 1
+    om = oracle.build_map_workload(w)
+    assert_attribution_equal(a.numpy(), oracle.attribute(om, w.pc, w.ctx, w.stall, w.weight, w.n_ctx), "dense")
+    w.pc[::9] += np.uint64(1 << 50)
+    pc, cx, st, wt = hpa.samples_to_device(w)
+    torch.cuda.synchronize()
+    n0 = hctx.sync_count()
+    a = hpa.attribute(hctx, m, pc, cx, st, wt, w.n_ctx)
+    assert hctx.sync_count() - n0 > 1
+    assert_attribution_equal(a.numpy(), oracle.attribute(om, w.pc, w.ctx, w.stall, w.weight, w.n_ctx), "far")
