@@ -293,7 +293,12 @@ k_d_scatter(const uint64_t* __restrict__ pc, const uint32_t* __restrict__ ctx, c
       const uint32_t c = w.v[j];
       if (p0 + j >= n || c >= C || !w.tail[j]) continue;
       const uint32_t len = (uint32_t)(lane_id() * DI + j - w.head[j] + 1);
-      sb[w.head[j]] = cbase[c] + atomicAdd(&cursor[c], len);
+      uint32_t b = cbase[c] + atomicAdd(&cursor[c], len);
+      if (b + len > cbase[c + 1]) {  // more samples than the histogram counted: never expected
+        bad_pos = true;
+        b = NONE32;
+      }
+      sb[w.head[j]] = b;
     }
     __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
     __builtin_amdgcn_wave_barrier();
@@ -302,8 +307,9 @@ k_d_scatter(const uint64_t* __restrict__ pc, const uint32_t* __restrict__ ctx, c
     for (int j = 0; j < DI; ++j) {
       const uint32_t c = w.v[j];
       if (p0 + j >= n || c >= C) continue;
-      const uint32_t pos = sb[w.head[j]] + (uint32_t)(lane_id() * DI + j - w.head[j]);
-      if (pos >= cbase[c + 1]) { bad_pos = true; continue; }
+      const uint32_t b = sb[w.head[j]];
+      if (b == NONE32) continue;
+      const uint32_t pos = b + (uint32_t)(lane_id() * DI + j - w.head[j]);
       uint32_t r;
       uint64_t D;
       if (st[j] >= NS) {
@@ -425,64 +431,82 @@ k_d_split(const uint32_t* __restrict__ big_ctx, const uint32_t* __restrict__ big
 // ---------------------------------------------------------------------------
 // plan: greedy packing per tile of contexts
 // ---------------------------------------------------------------------------
-// Thread 0 walks the tile's contexts in order; with `out` null it only counts
-// the units, otherwise it writes them from the tile's first unit on.
-__device__ inline void plan_tile(const uint32_t* s_h, uint32_t c0, uint32_t nt, uint32_t maxc,
-                                 const uint32_t* __restrict__ bidx,
-                                 const DUnit* __restrict__ bunits, const uint32_t* __restrict__ big_slot0,
-                                 const uint32_t* __restrict__ n_bunits, const uint32_t* __restrict__ cbase,
-                                 DUnit* __restrict__ out, uint32_t& n_out) {
-  uint32_t m = 0;
-  uint32_t ucb = c0, samples = 0, nonempty = 0;
-  bool open = false;
-  auto close = [&](uint32_t ce) {
-    if (out) {
-      out[m] = DUnit{cbase[ucb], cbase[ce], ucb, ce, DU_SMALL, 0, 0, 0};
-    }
-    ++m;
-    open = false;
-  };
-  for (uint32_t i = 0; i < nt; ++i) {
-    const uint32_t c = c0 + i, h = s_h[i];
-    if (h > (uint32_t)UT) {
-      if (open) close(c);
-      const uint32_t b = bidx[c];
-      const uint32_t k = n_bunits[b], o = big_slot0[b];
-      for (uint32_t j = 0; j < k; ++j) {
-        if (out) out[m] = bunits[o + j];
-        ++m;
-      }
-      continue;
-    }
-    if (open && ((h > 0 && nonempty == maxc) || samples + h > (uint32_t)UT)) close(c);
-    if (!open) {
-      open = true;
-      ucb = c;
-      samples = 0;
-      nonempty = 0;
-    }
-    samples += h;
-    nonempty += h > 0;
-  }
-  if (open) close(c0 + nt);
-  n_out = m;
-}
+// The tile's context counts (and each big context's number of parts) are
+// staged in LDS.  Thread 0 walks the contexts in order and cuts them into
+// segments: a unit of small contexts, or a big context with its parts.  Then
+// every thread writes the unit descriptors of its segments.  The count launch
+// (tile_off null) only records the tile's unit count.
+constexpr uint32_t SEG_BIG = 0x80000000u;
 
 __global__ void __launch_bounds__(DB)
 k_d_plan(const uint32_t* __restrict__ hist, uint32_t C, uint32_t maxc, const uint32_t* __restrict__ bidx,
          const DUnit* __restrict__ bunits, const uint32_t* __restrict__ big_slot0, const uint32_t* __restrict__ n_bunits,
          const uint32_t* __restrict__ cbase, uint32_t* __restrict__ tile_units, const uint32_t* __restrict__ tile_off,
          DUnit* __restrict__ units) {
-  __shared__ uint32_t s_h[DTILE];
+  __shared__ __align__(16) uint32_t s_h[DTILE];
+  __shared__ uint32_t s_nb[DTILE];          // parts of a big context
+  __shared__ uint32_t s_seg[DTILE + 1];     // segment start context (| SEG_BIG), closed by the tile end
+  __shared__ uint32_t s_useg[DTILE + 1];    // first unit of each segment (tile-relative)
+  __shared__ uint32_t s_nseg;
   const uint32_t c0 = blockIdx.x * DTILE;
   const uint32_t nt = min((uint32_t)DTILE, C - c0);
-  for (uint32_t i = threadIdx.x; i < nt; i += DB) s_h[i] = hist[c0 + i];
+  for (uint32_t i = threadIdx.x; i < (uint32_t)DTILE; i += DB) {
+    const uint32_t h = i < nt ? hist[c0 + i] : 0u;
+    s_h[i] = h;
+    s_nb[i] = h > (uint32_t)UT ? n_bunits[bidx[c0 + i]] : 0u;
+  }
   __syncthreads();
   if (threadIdx.x == 0) {
-    uint32_t m;
-    plan_tile(s_h, c0, nt, maxc, bidx, bunits, big_slot0, n_bunits, cbase, tile_off ? units + tile_off[blockIdx.x] : nullptr,
-              m);
+    uint32_t nseg = 0, m = 0, samples = 0, nonempty = 0;
+    bool open = false;
+    for (uint32_t i0 = 0; i0 < nt; i0 += 4) {
+      const uint4 h4 = *reinterpret_cast<const uint4*>(&s_h[i0]);
+      const uint32_t hv[4] = {h4.x, h4.y, h4.z, h4.w};
+#pragma unroll
+      for (int q = 0; q < 4; ++q) {
+        const uint32_t i = i0 + q, h = hv[q];
+        if (i >= nt) break;
+        if (h > (uint32_t)UT) {
+          if (open) { ++m; open = false; }
+          s_seg[nseg] = i | SEG_BIG;
+          s_useg[nseg] = m;
+          ++nseg;
+          m += s_nb[i];
+          continue;
+        }
+        if (open && ((h > 0 && nonempty == maxc) || samples + h > (uint32_t)UT)) { ++m; open = false; }
+        if (!open) {
+          open = true;
+          samples = 0;
+          nonempty = 0;
+          s_seg[nseg] = i;
+          s_useg[nseg] = m;
+          ++nseg;
+        }
+        samples += h;
+        nonempty += h > 0;
+      }
+    }
+    if (open) ++m;
+    s_seg[nseg] = nt;
+    s_useg[nseg] = m;
+    s_nseg = nseg;
     if (!tile_off) tile_units[blockIdx.x] = m;
+  }
+  __syncthreads();
+  if (!tile_off) return;
+  DUnit* out = units + tile_off[blockIdx.x];
+  const uint32_t nseg = s_nseg;
+  for (uint32_t k = threadIdx.x; k < nseg; k += DB) {
+    const uint32_t sg = s_seg[k], u0 = s_useg[k];
+    const uint32_t i = sg & ~SEG_BIG, c = c0 + i;
+    if (sg & SEG_BIG) {
+      const uint32_t b = bidx[c], o = big_slot0[b];
+      for (uint32_t j = 0; j < s_nb[i]; ++j) out[u0 + j] = bunits[o + j];
+    } else {
+      const uint32_t ce = c0 + (s_seg[k + 1] & ~SEG_BIG);
+      out[u0] = DUnit{cbase[c], cbase[ce], c, ce, DU_SMALL, 0, 0, 0};
+    }
   }
 }
 
@@ -615,6 +639,90 @@ __device__ inline void hot_unit(SortSmem& sm, DUnitSmem& du, const DUnitArgs& a,
   }
 }
 
+// Sort and reduce one SMALL or PART unit of n_u > 0 records with IT items
+// per thread (the least that holds it: a sort pass costs in proportion to the
+// slots it sorts), find its output offset, and write its keys.
+template <bool WEIGHTED, int IT>
+__device__ __forceinline__ void sort_unit(SortSmem& sm, DUnitSmem& du, const DUnitArgs& a, const DUnit& d,
+                                          const uint32_t* __restrict__ rec, const uint32_t* __restrict__ rw,
+                                          uint32_t n_u, uint32_t nl, uint32_t t, unsigned long long& P,
+                                          uint32_t& nU) {
+  using S = BlockRadix<UBLOCK, IT>;
+  const int tid = threadIdx.x;
+  // gather: item i of thread t is record i * UBLOCK + t of the unit, kept
+  // packed as local context << 26 | D << 4 | stall (D < 2^22)
+  uint32_t key[IT], val[IT];
+  uint32_t dmin = 0xFFFFFFFFu, dmax = 0;
+  {
+    uint32_t lo = 0;
+#pragma unroll
+    for (int i = 0; i < IT; ++i) {
+      const uint32_t j = (uint32_t)i * UBLOCK + tid;
+      key[i] = 0;
+      val[i] = 0;
+      if (j < n_u) {
+        uint32_t r = rec[d.s0 + j];
+        if (r == FAR_REC) r = 0;  // the call is redone by the general path
+        uint32_t hi = nl;  // last l with lstart[l] <= j, from the previous item's context on
+        while (hi - lo > 1) {
+          const uint32_t mid = (lo + hi) >> 1;
+          if (du.lstart[mid] <= j) lo = mid;
+          else hi = mid;
+        }
+        key[i] = (lo << 26) | (r & 0x3FFFFFFu);
+        if constexpr (WEIGHTED) val[i] = rw[d.s0 + j];
+        const uint32_t D = (r >> 4) & 0x3FFFFFu;
+        dmin = min(dmin, D);
+        dmax = max(dmax, D);
+      }
+    }
+  }
+  // unit-wide coordinate range: keys are taken relative to its smallest
+  dmin = wave_min(dmin);
+  dmax = wave_max(dmax);
+  if (lane_id() == 0) {
+    atomicMin(&du.red_min, dmin);
+    atomicMax(&du.red_max, dmax);
+  }
+  __syncthreads();
+  dmin = du.red_min;
+  const int pcb = bits_for(du.red_max - dmin);
+  const int kbits = bits_for(nl - 1) + pcb + 4;
+  // the plan keeps local contexts few enough that keys fit 31 bits
+  if (kbits > 31 && tid == 0) atomicOr(&a.info->err, DERR_WIDE);
+  const uint32_t empty = 1u << min(kbits, 31);
+#pragma unroll
+  for (int i = 0; i < IT; ++i) {
+    const uint32_t j = (uint32_t)i * UBLOCK + tid;
+    const uint32_t v = key[i];
+    key[i] = j < n_u ? ((v >> 26) << (pcb + 4)) | ((((v >> 4) & 0x3FFFFFu) - dmin) << 4) | (v & 15u) : empty;
+  }
+  // empty slots sort after every key: kbits + 1 bits, no per-slot test
+  if constexpr (WEIGHTED)
+    S::template sort<1, true>(key, val, val, min(kbits, 31) + 1, (int)n_u, true, sm.buf, sm.cnt, sm.doff);
+  else
+    S::template sort<0, true>(key, val, val, min(kbits, 31) + 1, (int)n_u, true, sm.buf, sm.cnt, sm.doff);
+  uint32_t first;
+  find_heads<uint32_t, IT>(sm, key, n_u, nl, pcb, first, nU);
+  if (tid == 0) du.P = look_back(a.status, t, nU, &a.info->err);
+  __syncthreads();
+  P = du.P;
+  if constexpr (WEIGHTED) weighted_counts<uint32_t, IT>(sm, key, val, n_u, first, a.out.count + P);
+  // consecutive threads take consecutive keys from the compacted copy
+  const uint32_t pmask = (1u << pcb) - 1u;
+  for (uint32_t ui = tid; ui < nU; ui += UBLOCK) {
+    const uint32_t kk = sm.buf[ui];
+    const uint32_t lc = kk >> (pcb + 4);
+    const uint64_t D = dmin + ((kk >> 4) & pmask);
+    const uint64_t o = P + ui;
+    a.out.ctx[o] = du.lctx[lc < nl ? lc : 0];
+    a.out.pc[o] = from_dense(a.dd, D);
+    a.out.stall[o] = (uint8_t)(kk & 15u);
+    if constexpr (!WEIGHTED) a.out.count[o] = (uint32_t)sm.upos[ui + 1] - (uint32_t)sm.upos[ui];
+    a.out.scope[o] = a.dd.scope_of[D];
+  }
+}
+
 template <bool WEIGHTED>
 __global__ void __launch_bounds__(UBLOCK) k_d_units(DUnitArgs a) {
   __shared__ SortSmem sm;
@@ -673,84 +781,18 @@ __global__ void __launch_bounds__(UBLOCK) k_d_units(DUnitArgs a) {
     __syncthreads();
     const uint32_t nl = min(du.nl, (uint32_t)MAXC);
     // gather: item i of thread t is record i * UBLOCK + t of the unit
-    // gather: item i of thread t is record i * UBLOCK + t of the unit, kept
-    // packed as local context << 26 | D << 4 | stall (D < 2^22)
-    uint32_t key[UITEMS], val[UITEMS];
-    uint32_t dmin = 0xFFFFFFFFu, dmax = 0;
-    {
-      uint32_t lo = 0;
-#pragma unroll
-      for (int i = 0; i < UITEMS; ++i) {
-        const uint32_t j = (uint32_t)i * UBLOCK + tid;
-        key[i] = 0;
-        val[i] = 0;
-        if (j < n_u) {
-          uint32_t r = rec[d.s0 + j];
-          if (r == FAR_REC) r = 0;  // the call is redone by the general path
-          uint32_t hi = nl;  // last l with lstart[l] <= j, from the previous item's context on
-          while (hi - lo > 1) {
-            const uint32_t mid = (lo + hi) >> 1;
-            if (du.lstart[mid] <= j) lo = mid;
-            else hi = mid;
-          }
-          key[i] = (lo << 26) | (r & 0x3FFFFFFu);
-          if constexpr (WEIGHTED) val[i] = rw[d.s0 + j];
-          const uint32_t D = (r >> 4) & 0x3FFFFFu;
-          dmin = min(dmin, D);
-          dmax = max(dmax, D);
-        }
-      }
-    }
     unsigned long long P = 0;
-    uint32_t first = 0, nU = 0;
+    uint32_t nU = 0;
     if (n_u == 0) {  // only empty contexts
       if (tid == 0) du.P = look_back(a.status, t, 0, &a.info->err);
       __syncthreads();
       P = du.P;
+    } else if (n_u <= 4u * UBLOCK) {
+      sort_unit<WEIGHTED, 4>(sm, du, a, d, rec, rw, (uint32_t)n_u, nl, t, P, nU);
+    } else if (n_u <= 8u * UBLOCK) {
+      sort_unit<WEIGHTED, 8>(sm, du, a, d, rec, rw, (uint32_t)n_u, nl, t, P, nU);
     } else {
-      // unit-wide coordinate range: keys are taken relative to its smallest
-      dmin = wave_min(dmin);
-      dmax = wave_max(dmax);
-      if (lane_id() == 0) {
-        atomicMin(&du.red_min, dmin);
-        atomicMax(&du.red_max, dmax);
-      }
-      __syncthreads();
-      dmin = du.red_min;
-      const int pcb = bits_for(du.red_max - dmin);
-      const int kbits = bits_for(nl - 1) + pcb + 4;
-      // the plan keeps local contexts few enough that keys fit 31 bits
-      if (kbits > 31 && tid == 0) atomicOr(&a.info->err, DERR_WIDE);
-      const uint32_t empty = 1u << min(kbits, 31);
-#pragma unroll
-      for (int i = 0; i < UITEMS; ++i) {
-        const uint32_t j = (uint32_t)i * UBLOCK + tid;
-        const uint32_t v = key[i];
-        key[i] = j < n_u ? ((v >> 26) << (pcb + 4)) | ((((v >> 4) & 0x3FFFFFu) - dmin) << 4) | (v & 15u) : empty;
-      }
-      // empty slots sort after every key: kbits + 1 bits, no per-slot test
-      if constexpr (WEIGHTED)
-        Sorter::template sort<1, true>(key, val, val, min(kbits, 31) + 1, (int)n_u, true, sm.buf, sm.cnt, sm.doff);
-      else
-        Sorter::template sort<0, true>(key, val, val, min(kbits, 31) + 1, (int)n_u, true, sm.buf, sm.cnt, sm.doff);
-      find_heads<uint32_t>(sm, key, n_u, nl, pcb, first, nU);
-      if (tid == 0) du.P = look_back(a.status, t, nU, &a.info->err);
-      __syncthreads();
-      P = du.P;
-      if constexpr (WEIGHTED) weighted_counts<uint32_t>(sm, key, val, n_u, first, a.out.count + P);
-      // consecutive threads take consecutive keys from the compacted copy
-      const uint32_t pmask = (1u << pcb) - 1u;
-      for (uint32_t ui = tid; ui < nU; ui += UBLOCK) {
-        const uint32_t kk = sm.buf[ui];
-        const uint32_t lc = kk >> (pcb + 4);
-        const uint64_t D = dmin + ((kk >> 4) & pmask);
-        const uint64_t o = P + ui;
-        a.out.ctx[o] = du.lctx[lc < nl ? lc : 0];
-        a.out.pc[o] = from_dense(a.dd, D);
-        a.out.stall[o] = (uint8_t)(kk & 15u);
-        if constexpr (!WEIGHTED) a.out.count[o] = (uint32_t)sm.upos[ui + 1] - (uint32_t)sm.upos[ui];
-        a.out.scope[o] = a.dd.scope_of[D];
-      }
+      sort_unit<WEIGHTED, UITEMS>(sm, du, a, d, rec, rw, (uint32_t)n_u, nl, t, P, nU);
     }
     // context offsets: every context of the unit (empty ones included) starts
     // after the keys of the non-empty contexts before it
