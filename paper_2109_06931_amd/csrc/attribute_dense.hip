@@ -6,18 +6,18 @@
 //   hist      read ctx[] once (16 B per lane): per-context sample counts, one
 //             atomic per run of equal contexts inside a wave's 256 samples.
 //   bases     tile scans over the contexts: each context's first position in
-//             context order, the list of contexts over UT samples ("big").
+//             context order, the list of contexts over DUT samples ("big").
 //   scatter   read pc, ctx, stall (and weight) once; replace the pc by its
 //             dense coordinate D and write the 4-byte record D << 4 | stall
 //             at the sample's position in context order (one atomic per run).
 //   split     one workgroup per big context: a histogram of its records over
 //             coordinate buckets, the buckets packed greedily into parts of at
-//             most UT samples (a bucket over UT samples is a part of its own,
+//             most DUT samples (a bucket over DUT samples is a part of its own,
 //             counted instead of sorted), the records copied into bucket order.
 //             Parts cover increasing coordinate ranges, so their sorted keys,
 //             one after the other, are the context's keys in order.
 //   plan      per tile of 1,024 contexts, consecutive contexts packed greedily
-//             into units of at most UT samples and 64 non-empty contexts; a big
+//             into units of at most DUT samples and 64 non-empty contexts; a big
 //             context contributes its parts.  Units are numbered in context
 //             order.
 //   units     persistent workgroups take units in ticket order: load the
@@ -43,9 +43,13 @@ constexpr int DB = 256;                 // hist / scatter / plan workgroup
 constexpr int DI = 4;                   // samples per lane per step
 constexpr int DCH = WAVE * DI;          // samples per wave step
 constexpr uint32_t FAR_REC = 0xFFFFFFFFu;
-constexpr int DNB = 4096;               // coordinate buckets of a big context
+constexpr int DUB = 512;                // unit workgroup (two fit one compute unit's LDS)
+constexpr int DUI = 16;                 // most items per thread of a unit
+constexpr int DUT = DUB * DUI;          // unit capacity (records); contexts over it are "big"
+using DSmem = SortSmemT<DUB, DUI, false>;
+constexpr int DNB = 8192;               // coordinate buckets of a big context
 constexpr int DTILE = 1024;             // contexts per plan tile
-constexpr int HOT_KEYS = UT;            // counters of a counted part (coordinates x stalls)
+constexpr int HOT_KEYS = DUT;           // counters of a counted part (coordinates x stalls)
 constexpr uint32_t DU_SMALL = 0, DU_PART = 1, DU_HOT = 2;
 constexpr unsigned int DERR_CTX = 1, DERR_STALL = 2, DERR_WIDE = 4, DERR_INTERNAL = 8, DERR_LOOKBACK = 16,
                        DERR_OVERFLOW = 32;
@@ -154,14 +158,14 @@ __global__ void __launch_bounds__(DB) k_d_hist(const uint32_t* __restrict__ ctx,
 // bases: three launches of tile scans over the contexts
 // ---------------------------------------------------------------------------
 // Per tile: samples, big contexts, and the unit slots the big contexts may
-// need (2 * ceil(n / UT) + 1 each: greedy packing leaves no two neighbouring
+// need (2 * ceil(n / DUT) + 1 each: greedy packing leaves no two neighbouring
 // parts that would fit together).
 struct DTileSums {
   unsigned long long n;
   uint32_t big, slots;
 };
 
-__device__ inline uint32_t big_slots(uint32_t n) { return 2u * ((n + UT - 1) / UT) + 1u; }
+__device__ inline uint32_t big_slots(uint32_t n) { return 2u * ((n + DUT - 1) / DUT) + 1u; }
 
 __global__ void __launch_bounds__(DTILE) k_d_tile_sums(const uint32_t* __restrict__ hist, uint32_t C,
                                                        DTileSums* __restrict__ ts) {
@@ -169,7 +173,7 @@ __global__ void __launch_bounds__(DTILE) k_d_tile_sums(const uint32_t* __restric
   __shared__ uint32_t s_b[DTILE / WAVE + 1];
   const uint32_t c = blockIdx.x * DTILE + threadIdx.x;
   const uint32_t h = c < C ? hist[c] : 0u;
-  const bool big = h > (uint32_t)UT;
+  const bool big = h > (uint32_t)DUT;
   unsigned long long tn;
   uint32_t tb, tsl;
   block_excl_scan<DTILE>((unsigned long long)h, s_a, &tn);
@@ -216,7 +220,7 @@ __global__ void __launch_bounds__(DTILE) k_d_bases(const uint32_t* __restrict__ 
   __shared__ uint32_t s_b[DTILE / WAVE + 1];
   const uint32_t c = blockIdx.x * DTILE + threadIdx.x;
   const uint32_t h = c < C ? hist[c] : 0u;
-  const bool big = h > (uint32_t)UT;
+  const bool big = h > (uint32_t)DUT;
   const DTileSums base = ts[blockIdx.x];
   unsigned long long tn;
   uint32_t tb, tsl;
@@ -380,10 +384,10 @@ k_d_split(const uint32_t* __restrict__ big_ctx, const uint32_t* __restrict__ big
   }
   __syncthreads();
   // greedy packing: a part from bucket k reaches the last bucket e with
-  // base[e] - base[k] <= UT (at least bucket k itself)
+  // base[e] - base[k] <= DUT (at least bucket k itself)
   const uint32_t total = s_base[DNB];
   for (int k = threadIdx.x; k < DNB; k += SB) {
-    const uint32_t lim = s_base[k] + (uint32_t)UT;
+    const uint32_t lim = s_base[k] + (uint32_t)DUT;
     uint32_t lo = (uint32_t)k + 1, hi = DNB;  // first e in [k+1, DNB] with base[e] > lim, minus one
     while (lo < hi) {
       const uint32_t mid = (lo + hi + 1) >> 1;
@@ -401,8 +405,8 @@ k_d_split(const uint32_t* __restrict__ big_ctx, const uint32_t* __restrict__ big
     while (k < (uint32_t)DNB && s_base[k] < total) {
       const uint32_t e = s_next[k];
       const uint32_t len = s_base[e] - s_base[k];
-      // a single bucket over UT samples is counted, not sorted
-      const bool hot = len > (uint32_t)UT;
+      // a single bucket over DUT samples is counted, not sorted
+      const bool hot = len > (uint32_t)DUT;
       if (m < cap) {
         bunits[slot0 + m] = DUnit{s0 + s_base[k], s0 + s_base[e], c, c + 1, hot ? DU_HOT : DU_PART, k << bshift, 0, 0};
       } else {
@@ -431,78 +435,127 @@ k_d_split(const uint32_t* __restrict__ big_ctx, const uint32_t* __restrict__ big
 // ---------------------------------------------------------------------------
 // plan: greedy packing per tile of contexts
 // ---------------------------------------------------------------------------
-// The tile's context counts (and each big context's number of parts) are
-// staged in LDS.  Thread 0 walks the contexts in order and cuts them into
-// segments: a unit of small contexts, or a big context with its parts.  Then
-// every thread writes the unit descriptors of its segments.  The count launch
-// (tile_off null) only records the tile's unit count.
+// A unit of small contexts starting at context i takes the longest run of
+// contexts [i, j) with at most DUT records, at most maxc non-empty contexts
+// and at most DUB contexts (the greedy rule, so every constraint is monotone in
+// j); a big context is a segment of its own, with its parts as units.  Every
+// thread finds next[i] for its contexts by binary search over the tile's
+// prefix sums (a big context counts DUT + 1 records, so no unit reaches over
+// it); thread 0 follows the chain from the tile's first context, which visits
+// exactly the segment starts; a scan over the segments gives their first
+// units, and every thread writes the descriptors of its segments.  The count
+// launch (tile_off null) only records the tile's unit count.
 constexpr uint32_t SEG_BIG = 0x80000000u;
+constexpr int PL_PER = DTILE / DB;  // contexts per thread
 
 __global__ void __launch_bounds__(DB)
 k_d_plan(const uint32_t* __restrict__ hist, uint32_t C, uint32_t maxc, const uint32_t* __restrict__ bidx,
          const DUnit* __restrict__ bunits, const uint32_t* __restrict__ big_slot0, const uint32_t* __restrict__ n_bunits,
          const uint32_t* __restrict__ cbase, uint32_t* __restrict__ tile_units, const uint32_t* __restrict__ tile_off,
          DUnit* __restrict__ units) {
-  __shared__ __align__(16) uint32_t s_h[DTILE];
-  __shared__ uint32_t s_nb[DTILE];          // parts of a big context
-  __shared__ uint32_t s_seg[DTILE + 1];     // segment start context (| SEG_BIG), closed by the tile end
-  __shared__ uint32_t s_useg[DTILE + 1];    // first unit of each segment (tile-relative)
+  __shared__ uint32_t s_ps[DTILE + 1];   // records before each context (big ones count DUT + 1)
+  __shared__ uint32_t s_pn[DTILE + 1];   // non-empty contexts before each context
+  __shared__ uint32_t s_next[DTILE];     // end of the segment that would start at each context
+  __shared__ uint32_t s_seg[DTILE + 1];  // segment starts in order (| SEG_BIG), closed by the tile end
+  __shared__ uint32_t s_useg[DTILE + 1]; // first unit of each segment (tile-relative), closed by the count
+  __shared__ uint32_t s_tmp[DB / WAVE + 1];
   __shared__ uint32_t s_nseg;
   const uint32_t c0 = blockIdx.x * DTILE;
   const uint32_t nt = min((uint32_t)DTILE, C - c0);
-  for (uint32_t i = threadIdx.x; i < (uint32_t)DTILE; i += DB) {
-    const uint32_t h = i < nt ? hist[c0 + i] : 0u;
-    s_h[i] = h;
-    s_nb[i] = h > (uint32_t)UT ? n_bunits[bidx[c0 + i]] : 0u;
-  }
-  __syncthreads();
-  if (threadIdx.x == 0) {
-    uint32_t nseg = 0, m = 0, samples = 0, nonempty = 0;
-    bool open = false;
-    for (uint32_t i0 = 0; i0 < nt; i0 += 4) {
-      const uint4 h4 = *reinterpret_cast<const uint4*>(&s_h[i0]);
-      const uint32_t hv[4] = {h4.x, h4.y, h4.z, h4.w};
+  const int tid = threadIdx.x;
+  // prefix sums: each thread owns PL_PER consecutive contexts
+  uint32_t h[PL_PER], ls = 0, ln = 0;
 #pragma unroll
-      for (int q = 0; q < 4; ++q) {
-        const uint32_t i = i0 + q, h = hv[q];
-        if (i >= nt) break;
-        if (h > (uint32_t)UT) {
-          if (open) { ++m; open = false; }
-          s_seg[nseg] = i | SEG_BIG;
-          s_useg[nseg] = m;
-          ++nseg;
-          m += s_nb[i];
-          continue;
-        }
-        if (open && ((h > 0 && nonempty == maxc) || samples + h > (uint32_t)UT)) { ++m; open = false; }
-        if (!open) {
-          open = true;
-          samples = 0;
-          nonempty = 0;
-          s_seg[nseg] = i;
-          s_useg[nseg] = m;
-          ++nseg;
-        }
-        samples += h;
-        nonempty += h > 0;
-      }
-    }
-    if (open) ++m;
-    s_seg[nseg] = nt;
-    s_useg[nseg] = m;
-    s_nseg = nseg;
-    if (!tile_off) tile_units[blockIdx.x] = m;
+  for (int q = 0; q < PL_PER; ++q) {
+    const uint32_t i = tid * PL_PER + q;
+    h[q] = i < nt ? hist[c0 + i] : 0u;
+    ls += h[q] > (uint32_t)DUT ? (uint32_t)DUT + 1 : h[q];
+    ln += h[q] > 0;
+  }
+  uint32_t ts, tn;
+  uint32_t es = block_excl_scan<DB>(ls, s_tmp, &ts);
+  uint32_t en = block_excl_scan<DB>(ln, s_tmp, &tn);
+#pragma unroll
+  for (int q = 0; q < PL_PER; ++q) {
+    const uint32_t i = tid * PL_PER + q;
+    s_ps[i] = es;
+    s_pn[i] = en;
+    es += h[q] > (uint32_t)DUT ? (uint32_t)DUT + 1 : h[q];
+    en += h[q] > 0;
+  }
+  if (tid == 0) {
+    s_ps[DTILE] = ts;
+    s_pn[DTILE] = tn;
   }
   __syncthreads();
-  if (!tile_off) return;
-  DUnit* out = units + tile_off[blockIdx.x];
+#pragma unroll
+  for (int q = 0; q < PL_PER; ++q) {
+    const uint32_t i = tid * PL_PER + q;
+    if (i >= nt) continue;
+    uint32_t j;
+    if (h[q] > (uint32_t)DUT) {
+      j = i + 1;
+    } else {
+      // largest j <= min(nt, i + DUB) with ps[j] - ps[i] <= DUT and pn[j] - pn[i] <= maxc
+      const uint32_t ls_lim = s_ps[i] + (uint32_t)DUT, ln_lim = s_pn[i] + maxc;
+      uint32_t lo = i + 1, hi = min(nt, i + (uint32_t)DUB);
+      while (lo < hi) {
+        const uint32_t mid = (lo + hi + 1) >> 1;
+        if (s_ps[mid] <= ls_lim && s_pn[mid] <= ln_lim) lo = mid;
+        else hi = mid - 1;
+      }
+      j = lo;
+    }
+    s_next[i] = j;
+  }
+  __syncthreads();
+  if (tid == 0) {
+    uint32_t k = 0;
+    for (uint32_t i = 0; i < nt; i = s_next[i]) {
+      const bool big = s_ps[i + 1] - s_ps[i] > (uint32_t)DUT;
+      s_seg[k++] = i | (big ? SEG_BIG : 0u);
+    }
+    s_seg[k] = nt;
+    s_nseg = k;
+  }
+  __syncthreads();
+  // first unit of each segment: a small segment is one unit, a big context
+  // one per part
   const uint32_t nseg = s_nseg;
-  for (uint32_t k = threadIdx.x; k < nseg; k += DB) {
+  {
+    uint32_t cnt[PL_PER], loc = 0;
+#pragma unroll
+    for (int q = 0; q < PL_PER; ++q) {
+      const uint32_t k = tid * PL_PER + q;
+      cnt[q] = 0;
+      if (k < nseg) {
+        const uint32_t sg = s_seg[k];
+        cnt[q] = (sg & SEG_BIG) ? n_bunits[bidx[c0 + (sg & ~SEG_BIG)]] : 1u;
+      }
+      loc += cnt[q];
+    }
+    uint32_t tot;
+    uint32_t e = block_excl_scan<DB>(loc, s_tmp, &tot);
+#pragma unroll
+    for (int q = 0; q < PL_PER; ++q) {
+      const uint32_t k = tid * PL_PER + q;
+      if (k < nseg) s_useg[k] = e;
+      e += cnt[q];
+    }
+    if (tid == 0) {
+      s_useg[nseg] = tot;
+      if (!tile_off) tile_units[blockIdx.x] = tot;
+    }
+  }
+  if (!tile_off) return;
+  __syncthreads();
+  DUnit* out = units + tile_off[blockIdx.x];
+  for (uint32_t k = tid; k < nseg; k += DB) {
     const uint32_t sg = s_seg[k], u0 = s_useg[k];
     const uint32_t i = sg & ~SEG_BIG, c = c0 + i;
     if (sg & SEG_BIG) {
-      const uint32_t b = bidx[c], o = big_slot0[b];
-      for (uint32_t j = 0; j < s_nb[i]; ++j) out[u0 + j] = bunits[o + j];
+      const uint32_t b = bidx[c], o = big_slot0[b], nb = s_useg[k + 1] - u0;
+      for (uint32_t q = 0; q < nb; ++q) out[u0 + q] = bunits[o + q];
     } else {
       const uint32_t ce = c0 + (s_seg[k + 1] & ~SEG_BIG);
       out[u0] = DUnit{cbase[c], cbase[ce], c, ce, DU_SMALL, 0, 0, 0};
@@ -548,11 +601,11 @@ struct DUnitArgs {
 struct DUnitSmem {
   uint32_t lstart[MAXC + 1];  // record offset of each non-empty local context, closed by n_u
   uint32_t lctx[MAXC];        // its context id
-  uint32_t lrank[DTILE];      // per context of the unit: non-empty contexts before it
+  uint32_t lrank[DUB];        // per context of the unit: non-empty contexts before it
   unsigned long long loff[MAXC + 1];
   unsigned long long P;
   uint32_t t, nl, red_min, red_max;
-  uint32_t tmp[UBLOCK / WAVE + 1];
+  uint32_t tmp[DUB / WAVE + 1];
 };
 
 // Publish the unit's key count, find the keys of all units before it, and
@@ -594,14 +647,14 @@ __device__ inline unsigned long long look_back(unsigned long long* status, uint3
 // Counters (coordinate offset, stall) in LDS, then the non-empty ones in
 // order are the part's keys.
 template <bool WEIGHTED>
-__device__ inline void hot_unit(SortSmem& sm, DUnitSmem& du, const DUnitArgs& a, const DUnit& d) {
+__device__ inline void hot_unit(DSmem& sm, DUnitSmem& du, const DUnitArgs& a, const DUnit& d) {
   const int tid = threadIdx.x;
   const uint32_t R = (1u << a.bshift) * NS;  // <= HOT_KEYS (checked on the host)
   uint32_t* cnt = sm.buf;
-  for (uint32_t i = tid; i < R; i += UBLOCK) cnt[i] = 0;
+  for (uint32_t i = tid; i < R; i += DUB) cnt[i] = 0;
   __syncthreads();
   bool ovf = false;
-  for (uint32_t i = d.s0 + tid; i < d.s1; i += UBLOCK) {
+  for (uint32_t i = d.s0 + tid; i < d.s1; i += DUB) {
     const uint32_t r = a.rec2[i];
     if (r == FAR_REC) continue;
     const uint32_t k = (((r >> 4) - d.d0) << 4) | (r & 15u);
@@ -612,15 +665,15 @@ __device__ inline void hot_unit(SortSmem& sm, DUnitSmem& du, const DUnitArgs& a,
   }
   if (ovf) atomicOr(&a.info->err, DERR_OVERFLOW);
   __syncthreads();
-  // compaction: thread t scans its block of R / UBLOCK consecutive counters
-  const uint32_t per = (R + UBLOCK - 1) / UBLOCK;
+  // compaction: thread t scans its block of R / DUB consecutive counters
+  const uint32_t per = (R + DUB - 1) / DUB;
   uint32_t mine = 0;
   for (uint32_t j = 0; j < per; ++j) {
     const uint32_t i = tid * per + j;
     mine += i < R && cnt[i] != 0;
   }
   uint32_t nU;
-  const uint32_t first = block_excl_scan<UBLOCK>(mine, du.tmp, &nU);
+  const uint32_t first = block_excl_scan<DUB>(mine, du.tmp, &nU);
   if (tid == 0) du.P = look_back(a.status, du.t, nU, &a.info->err);
   __syncthreads();
   const unsigned long long P = du.P;
@@ -643,13 +696,13 @@ __device__ inline void hot_unit(SortSmem& sm, DUnitSmem& du, const DUnitArgs& a,
 // per thread (the least that holds it: a sort pass costs in proportion to the
 // slots it sorts), find its output offset, and write its keys.
 template <bool WEIGHTED, int IT>
-__device__ __forceinline__ void sort_unit(SortSmem& sm, DUnitSmem& du, const DUnitArgs& a, const DUnit& d,
+__device__ __forceinline__ void sort_unit(DSmem& sm, DUnitSmem& du, const DUnitArgs& a, const DUnit& d,
                                           const uint32_t* __restrict__ rec, const uint32_t* __restrict__ rw,
                                           uint32_t n_u, uint32_t nl, uint32_t t, unsigned long long& P,
                                           uint32_t& nU) {
-  using S = BlockRadix<UBLOCK, IT>;
+  using S = BlockRadix<DUB, IT>;
   const int tid = threadIdx.x;
-  // gather: item i of thread t is record i * UBLOCK + t of the unit, kept
+  // gather: item i of thread t is record i * DUB + t of the unit, kept
   // packed as local context << 26 | D << 4 | stall (D < 2^22)
   uint32_t key[IT], val[IT];
   uint32_t dmin = 0xFFFFFFFFu, dmax = 0;
@@ -657,7 +710,7 @@ __device__ __forceinline__ void sort_unit(SortSmem& sm, DUnitSmem& du, const DUn
     uint32_t lo = 0;
 #pragma unroll
     for (int i = 0; i < IT; ++i) {
-      const uint32_t j = (uint32_t)i * UBLOCK + tid;
+      const uint32_t j = (uint32_t)i * DUB + tid;
       key[i] = 0;
       val[i] = 0;
       if (j < n_u) {
@@ -693,7 +746,7 @@ __device__ __forceinline__ void sort_unit(SortSmem& sm, DUnitSmem& du, const DUn
   const uint32_t empty = 1u << min(kbits, 31);
 #pragma unroll
   for (int i = 0; i < IT; ++i) {
-    const uint32_t j = (uint32_t)i * UBLOCK + tid;
+    const uint32_t j = (uint32_t)i * DUB + tid;
     const uint32_t v = key[i];
     key[i] = j < n_u ? ((v >> 26) << (pcb + 4)) | ((((v >> 4) & 0x3FFFFFu) - dmin) << 4) | (v & 15u) : empty;
   }
@@ -710,7 +763,7 @@ __device__ __forceinline__ void sort_unit(SortSmem& sm, DUnitSmem& du, const DUn
   if constexpr (WEIGHTED) weighted_counts<uint32_t, IT>(sm, key, val, n_u, first, a.out.count + P);
   // consecutive threads take consecutive keys from the compacted copy
   const uint32_t pmask = (1u << pcb) - 1u;
-  for (uint32_t ui = tid; ui < nU; ui += UBLOCK) {
+  for (uint32_t ui = tid; ui < nU; ui += DUB) {
     const uint32_t kk = sm.buf[ui];
     const uint32_t lc = kk >> (pcb + 4);
     const uint64_t D = dmin + ((kk >> 4) & pmask);
@@ -724,8 +777,8 @@ __device__ __forceinline__ void sort_unit(SortSmem& sm, DUnitSmem& du, const DUn
 }
 
 template <bool WEIGHTED>
-__global__ void __launch_bounds__(UBLOCK) k_d_units(DUnitArgs a) {
-  __shared__ SortSmem sm;
+__global__ void __launch_bounds__(DUB, 4) k_d_units(DUnitArgs a) {
+  __shared__ DSmem sm;
   __shared__ DUnitSmem du;
   const int tid = threadIdx.x;
   // dense windows in LDS once
@@ -758,11 +811,11 @@ __global__ void __launch_bounds__(UBLOCK) k_d_units(DUnitArgs a) {
         du.lctx[0] = d.cb;
       }
     } else {
-      const uint32_t nc = d.ce - d.cb;  // <= DTILE
+      const uint32_t nc = d.ce - d.cb;  // <= DUB
       const uint32_t c = d.cb + tid;
       const uint32_t h = (uint32_t)tid < nc ? a.hist[c] : 0u;
       uint32_t nl;
-      const uint32_t r = block_excl_scan<UBLOCK>(h > 0 ? 1u : 0u, du.tmp, &nl);
+      const uint32_t r = block_excl_scan<DUB>(h > 0 ? 1u : 0u, du.tmp, &nl);
       if ((uint32_t)tid < nc) {
         du.lrank[tid] = r;
         if (h > 0 && r < (uint32_t)MAXC) {
@@ -780,19 +833,18 @@ __global__ void __launch_bounds__(UBLOCK) k_d_units(DUnitArgs a) {
     }
     __syncthreads();
     const uint32_t nl = min(du.nl, (uint32_t)MAXC);
-    // gather: item i of thread t is record i * UBLOCK + t of the unit
     unsigned long long P = 0;
     uint32_t nU = 0;
     if (n_u == 0) {  // only empty contexts
       if (tid == 0) du.P = look_back(a.status, t, 0, &a.info->err);
       __syncthreads();
       P = du.P;
-    } else if (n_u <= 4u * UBLOCK) {
+    } else if (n_u <= 4u * DUB) {
       sort_unit<WEIGHTED, 4>(sm, du, a, d, rec, rw, (uint32_t)n_u, nl, t, P, nU);
-    } else if (n_u <= 8u * UBLOCK) {
+    } else if (n_u <= 8u * DUB) {
       sort_unit<WEIGHTED, 8>(sm, du, a, d, rec, rw, (uint32_t)n_u, nl, t, P, nU);
     } else {
-      sort_unit<WEIGHTED, UITEMS>(sm, du, a, d, rec, rw, (uint32_t)n_u, nl, t, P, nU);
+      sort_unit<WEIGHTED, DUI>(sm, du, a, d, rec, rw, (uint32_t)n_u, nl, t, P, nU);
     }
     // context offsets: every context of the unit (empty ones included) starts
     // after the keys of the non-empty contexts before it
@@ -810,7 +862,7 @@ __global__ void __launch_bounds__(UBLOCK) k_d_units(DUnitArgs a) {
     if (part) {
       if (tid == 0 && d.s0 == a.cbase[d.cb]) a.out.ctx_off[d.cb] = P;
     } else {
-      for (uint32_t i = tid; i < d.ce - d.cb; i += UBLOCK) {
+      for (uint32_t i = tid; i < d.ce - d.cb; i += DUB) {
         const uint32_t r = du.lrank[i];
         a.out.ctx_off[d.cb + i] = P + du.loff[r < nl ? r : nl];
       }
@@ -855,9 +907,9 @@ bool attribute_dense(hpa_ctx* ctx, const hpa_structure_map* map, const hpa_sampl
   uint32_t dbits = 0;
   while (dbits < 64 && ((map->n_dense - 1) >> dbits)) ++dbits;
   const uint32_t maxc = dbits >= 27 ? 1u : std::min<uint32_t>((uint32_t)MAXC, 1u << (27 - dbits));
-  const uint64_t max_big = n / (UT + 1) + 1;
-  // sum over big contexts of 2 * ceil(n_c / UT) + 1 <= 2 * (N / UT + n_big) + n_big
-  const uint64_t max_bslots = 2 * (n / UT) + 3 * max_big + 8;
+  const uint64_t max_big = n / (DUT + 1) + 1;
+  // sum over big contexts of 2 * ceil(n_c / DUT) + 1 <= 2 * (N / DUT + n_big) + n_big
+  const uint64_t max_bslots = 2 * (n / DUT) + 3 * max_big + 8;
   const uint64_t max_units = (uint64_t)C + max_bslots + n_tiles;
   DBuf d_info(ctx, sizeof(DInfo), s), d_hist(ctx, (uint64_t)C * 4, s), d_cbase(ctx, ((uint64_t)C + 1) * 4, s),
       d_cursor(ctx, (uint64_t)C * 4, s), d_bidx(ctx, (uint64_t)C * 4, s),
@@ -956,11 +1008,12 @@ bool attribute_dense(hpa_ctx* ctx, const hpa_structure_map* map, const hpa_sampl
   ua.status = d_status.as<unsigned long long>();
   ua.out = OutDev{A->ctx_id.as<uint32_t>(), A->pc.as<uint64_t>(), A->stall.as<uint8_t>(),
                   A->count.as<unsigned long long>(), A->scope.as<uint32_t>(), A->ctx_offsets.as<uint64_t>()};
-  // one resident workgroup per compute unit (the sort uses most of the LDS)
-  const unsigned ugrid = (unsigned)std::max<uint64_t>(1, std::min<uint64_t>(max_units, (uint64_t)ctx->n_cu));
+  // two resident workgroups per compute unit (each sort takes a little under
+  // half of the LDS): one's memory phases overlap the other's sort
+  const unsigned ugrid = (unsigned)std::max<uint64_t>(1, std::min<uint64_t>(max_units, 2ull * ctx->n_cu));
   tm.begin("units_dense");
-  if (weighted) k_d_units<true><<<ugrid, UBLOCK, 0, s>>>(ua);
-  else k_d_units<false><<<ugrid, UBLOCK, 0, s>>>(ua);
+  if (weighted) k_d_units<true><<<ugrid, DUB, 0, s>>>(ua);
+  else k_d_units<false><<<ugrid, DUB, 0, s>>>(ua);
   HPA_HIP(hipGetLastError());
   tm.end();
   DInfo h{};

@@ -73,27 +73,33 @@ struct ProfMap {
 // ----------------------------------------------------------------------------
 // Shared pieces of the sort workgroups (units and big-context chunks)
 // ----------------------------------------------------------------------------
-struct SortSmem {
+// LDS of a sort workgroup of BLOCK threads sorting up to BLOCK * ITEMS keys;
+// RUNS reserves room for the run list a general-pipeline unit gathers through.
+template <int BLOCK_, int ITEMS_, bool RUNS>
+struct SortSmemT {
+  static constexpr int BLOCK = BLOCK_;
+  using S = BlockRadix<BLOCK_, ITEMS_>;
   // exchange plane of the sort; afterwards the unit's unique keys (keys of at
   // most 32 bits)
-  uint32_t buf[Sorter::BUF_WORDS];
+  uint32_t buf[S::BUF_WORDS];
   union {
-    uint32_t cnt[Sorter::CNT_WORDS];  // radix counter columns during the sort
-    uint16_t upos[UT + 2];            // then: sorted position of every unique key, closed by n_u
-    Run runs[RUN_CAP];                // before the sort: the runs the workgroup gathers through
+    uint32_t cnt[S::CNT_WORDS];            // radix counter columns during the sort
+    uint16_t upos[BLOCK_ * ITEMS_ + 2];    // then: sorted position of every unique key, closed by n_u
+    Run runs[RUNS ? RUN_CAP : 1];          // before the sort: the runs the workgroup gathers through
   };
-  uint32_t doff[Sorter::DOFF_WORDS];
+  uint32_t doff[S::DOFF_WORDS];
   unsigned long long pcmin[MAXC];
   uint32_t ucnt[MAXC + 1];
   unsigned long long red_or, red_max, red_min, red_ref;
-  unsigned long long scan_tmp[UBLOCK / WAVE + 1];
-  uint32_t scan_tmp32[UBLOCK / WAVE + 1];
-  uint32_t last_hi[UBLOCK], last_lo[UBLOCK];
+  unsigned long long scan_tmp[BLOCK_ / WAVE + 1];
+  uint32_t scan_tmp32[BLOCK_ / WAVE + 1];
+  uint32_t last_hi[BLOCK_], last_lo[BLOCK_];
   unsigned long long prefix;
   uint32_t unit, nU;
   uint64_t wlo[DENSE_MAX_WIN], whi[DENSE_MAX_WIN], wd[DENSE_MAX_WIN + 1];  // dense windows
   uint32_t far;  // a sample of the workgroup has no dense coordinate
 };
+using SortSmem = SortSmemT<UBLOCK, UITEMS, true>;
 static_assert(UT < 65536, "16-bit sorted positions");
 
 // One workgroup's samples in registers: pc, (stall | local context << 4), weight.
@@ -210,15 +216,16 @@ __device__ inline void gather(Gathered<WEIGHTED>& g, uint64_t s0, uint64_t n_u, 
 
 // Stage the dense window tables in LDS (the caller synchronises before use)
 // and clear the far flag.
-__device__ inline DenseDev stage_dense(SortSmem& sm, const DenseDev& t) {
+template <class SM>
+__device__ inline DenseDev stage_dense(SM& sm, const DenseDev& t) {
   if (threadIdx.x == 0) sm.far = 0;
-  for (uint32_t i = threadIdx.x; i < t.n_win; i += UBLOCK) {
+  for (uint32_t i = threadIdx.x; i < t.n_win; i += SM::BLOCK) {
     sm.wlo[i] = t.lo[i];
     sm.whi[i] = t.hi[i];
   }
   // a map without dense coordinates has no tables (n_win == 0, null pointers)
   if (t.n_win)
-    for (uint32_t i = threadIdx.x; i <= t.n_win; i += UBLOCK) sm.wd[i] = t.d[i];
+    for (uint32_t i = threadIdx.x; i <= t.n_win; i += SM::BLOCK) sm.wd[i] = t.d[i];
   return DenseDev{sm.wlo, sm.whi, sm.wd, t.scope_of, t.n_win, t.tz};
 }
 
@@ -349,19 +356,20 @@ __device__ inline void key_stats(SortSmem& sm, const Gathered<WEIGHTED>& g, uint
 // the sorted position of every unique key (sm.upos, closed by n_u), the keys
 // themselves compacted into sm.buf when they fit 32 bits, and the number of
 // unique keys per local context.
-template <class K>
-__device__ inline K prev_last(const SortSmem& sm, int tid) {
+template <class K, class SM>
+__device__ inline K prev_last(const SM& sm, int tid) {
   return tid == 0 ? (K)0 : (K)(((uint64_t)sm.last_hi[tid - 1] << 32) | sm.last_lo[tid - 1]);
 }
 
-template <class K, int IT = UITEMS>
-__device__ inline uint32_t find_heads(SortSmem& sm, const K (&key)[IT], uint64_t n_u, uint32_t n_cu, int pcb,
+template <class K, int IT = UITEMS, class SM>
+__device__ inline uint32_t find_heads(SM& sm, const K (&key)[IT], uint64_t n_u, uint32_t n_cu, int pcb,
                                       uint32_t& first_uidx, uint32_t& nU) {
+  constexpr int BLOCK = SM::BLOCK;
   const int tid = threadIdx.x;
   sm.last_lo[tid] = (uint32_t)key[IT - 1];
   sm.last_hi[tid] = (uint32_t)((uint64_t)key[IT - 1] >> 32);
   // sm.ucnt first holds each context's first unique index (NONE32: no keys)
-  for (uint32_t l = tid; l <= n_cu; l += UBLOCK) sm.ucnt[l] = NONE32;
+  for (uint32_t l = tid; l <= n_cu; l += BLOCK) sm.ucnt[l] = NONE32;
   __syncthreads();
   K prev = prev_last<K>(sm, tid);
   uint32_t heads = 0;
@@ -373,7 +381,7 @@ __device__ inline uint32_t find_heads(SortSmem& sm, const K (&key)[IT], uint64_t
     prev = key[i];
   }
   uint32_t tot;
-  const uint32_t ex = block_excl_scan<UBLOCK>(heads, sm.scan_tmp32, &tot);
+  const uint32_t ex = block_excl_scan<BLOCK>(heads, sm.scan_tmp32, &tot);
   first_uidx = ex;
   nU = tot;
   prev = prev_last<K>(sm, tid);
@@ -417,8 +425,8 @@ __device__ inline uint32_t find_heads(SortSmem& sm, const K (&key)[IT], uint64_t
 
 // Weighted counts: every head writes the weight of its run inside its thread;
 // runs continuing from the previous thread are added with one atomic each.
-template <class K, int IT = UITEMS>
-__device__ inline void weighted_counts(const SortSmem& sm, const K (&key)[IT], const uint32_t (&val)[IT],
+template <class K, int IT = UITEMS, class SM>
+__device__ inline void weighted_counts(const SM& sm, const K (&key)[IT], const uint32_t (&val)[IT],
                                        uint64_t n_u, uint32_t first_uidx, unsigned long long* count) {
   const int tid = threadIdx.x;
   K prev = prev_last<K>(sm, tid);
