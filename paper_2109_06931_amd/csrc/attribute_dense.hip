@@ -47,9 +47,8 @@ constexpr int DUB = 512;                // unit workgroup (two fit one compute u
 constexpr int DUI = 16;                 // most items per thread of a unit
 constexpr int DUT = DUB * DUI;          // unit capacity (records); contexts over it are "big"
 using DSmem = SortSmemT<DUB, DUI, false>;
-constexpr int DNB = 8192;               // coordinate buckets of a big context
+constexpr int DNB = 4096;               // coordinate buckets of a big context
 constexpr int DTILE = 1024;             // contexts per plan tile
-constexpr int HOT_KEYS = DUT;           // counters of a counted part (coordinates x stalls)
 constexpr uint32_t DU_SMALL = 0, DU_PART = 1, DU_HOT = 2;
 constexpr unsigned int DERR_CTX = 1, DERR_STALL = 2, DERR_WIDE = 4, DERR_INTERNAL = 8, DERR_LOOKBACK = 16,
                        DERR_OVERFLOW = 32;
@@ -644,51 +643,95 @@ __device__ inline unsigned long long look_back(unsigned long long* status, uint3
 }
 
 // A counted part: one coordinate bucket [d0, d0 + 2^bshift) of one context.
-// Counters (coordinate offset, stall) in LDS, then the non-empty ones in
-// order are the part's keys.
+// Its keys (coordinate offset, stall) are counted in LDS, HOT_CAP counters at
+// a time (a bucket may span several such chunks of its key range); the
+// non-empty counters, in order, are the part's keys.  The first sweep counts
+// the keys of every chunk, so that the part can publish its count; a part of
+// one chunk then writes from the counters it has, a wider one counts each
+// chunk again while writing.
+constexpr uint32_t HOT_CAP = DUT;  // counters in the sort's exchange plane
+
 template <bool WEIGHTED>
-__device__ inline void hot_unit(DSmem& sm, DUnitSmem& du, const DUnitArgs& a, const DUnit& d) {
+__device__ inline uint32_t hot_count(DSmem& sm, DUnitSmem& du, const DUnitArgs& a, const DUnit& d, uint32_t k0,
+                                     uint32_t R, bool& ovf) {
   const int tid = threadIdx.x;
-  const uint32_t R = (1u << a.bshift) * NS;  // <= HOT_KEYS (checked on the host)
   uint32_t* cnt = sm.buf;
-  for (uint32_t i = tid; i < R; i += DUB) cnt[i] = 0;
+  const uint32_t kn = min(HOT_CAP, R - k0);
+  for (uint32_t i = tid; i < kn; i += DUB) cnt[i] = 0;
   __syncthreads();
-  bool ovf = false;
   for (uint32_t i = d.s0 + tid; i < d.s1; i += DUB) {
     const uint32_t r = a.rec2[i];
     if (r == FAR_REC) continue;
     const uint32_t k = (((r >> 4) - d.d0) << 4) | (r & 15u);
     if (k >= R) { ovf = true; continue; }
+    if (k < k0 || k >= k0 + kn) continue;
     const uint32_t w = WEIGHTED ? a.rw2[i] : 1u;
-    const uint32_t old = atomicAdd(&cnt[k], w);
+    const uint32_t old = atomicAdd(&cnt[k - k0], w);
     ovf |= old + w < old;
   }
-  if (ovf) atomicOr(&a.info->err, DERR_OVERFLOW);
   __syncthreads();
-  // compaction: thread t scans its block of R / DUB consecutive counters
-  const uint32_t per = (R + DUB - 1) / DUB;
+  // thread t owns a block of `per` consecutive counters
+  const uint32_t per = (kn + DUB - 1) / DUB;
   uint32_t mine = 0;
   for (uint32_t j = 0; j < per; ++j) {
     const uint32_t i = tid * per + j;
-    mine += i < R && cnt[i] != 0;
+    mine += i < kn && cnt[i] != 0;
   }
-  uint32_t nU;
-  const uint32_t first = block_excl_scan<DUB>(mine, du.tmp, &nU);
+  return mine;
+}
+
+template <bool WEIGHTED>
+__device__ inline void hot_emit(DSmem& sm, const DUnitArgs& a, const DUnit& d, uint32_t k0, uint32_t R,
+                                uint64_t o) {
+  const int tid = threadIdx.x;
+  const uint32_t* cnt = sm.buf;
+  const uint32_t kn = min(HOT_CAP, R - k0);
+  const uint32_t per = (kn + DUB - 1) / DUB;
+  for (uint32_t j = 0; j < per; ++j) {
+    const uint32_t i = tid * per + j;
+    if (i >= kn || cnt[i] == 0) continue;
+    const uint32_t k = k0 + i;
+    const uint64_t D = d.d0 + (k >> 4);
+    a.out.ctx[o] = d.cb;
+    a.out.pc[o] = from_dense(a.dd, D);
+    a.out.stall[o] = (uint8_t)(k & 15u);
+    a.out.count[o] = cnt[i];
+    a.out.scope[o] = a.dd.scope_of[D];
+    ++o;
+  }
+}
+
+template <bool WEIGHTED>
+__device__ inline void hot_unit(DSmem& sm, DUnitSmem& du, const DUnitArgs& a, const DUnit& d) {
+  const int tid = threadIdx.x;
+  const uint32_t R = (1u << a.bshift) * NS;  // the bucket's key range
+  const uint32_t nch = (R + HOT_CAP - 1) / HOT_CAP;
+  bool ovf = false;
+  uint32_t nU = 0, first = 0, mine = 0;
+  for (uint32_t ch = 0; ch < nch; ++ch) {
+    mine = hot_count<WEIGHTED>(sm, du, a, d, ch * HOT_CAP, R, ovf);
+    uint32_t tot;
+    first = block_excl_scan<DUB>(mine, du.tmp, &tot);
+    nU += tot;
+  }
+  if (ovf) atomicOr(&a.info->err, DERR_OVERFLOW);
   if (tid == 0) du.P = look_back(a.status, du.t, nU, &a.info->err);
   __syncthreads();
   const unsigned long long P = du.P;
   if (tid == 0 && d.s0 == a.cbase[d.cb]) a.out.ctx_off[d.cb] = P;
-  uint32_t u = first;
-  for (uint32_t j = 0; j < per; ++j) {
-    const uint32_t i = tid * per + j;
-    if (i >= R || cnt[i] == 0) continue;
-    const uint64_t o = P + u++;
-    const uint64_t D = d.d0 + (i >> 4);
-    a.out.ctx[o] = d.cb;
-    a.out.pc[o] = from_dense(a.dd, D);
-    a.out.stall[o] = (uint8_t)(i & 15u);
-    a.out.count[o] = cnt[i];
-    a.out.scope[o] = a.dd.scope_of[D];
+  if (nch == 1) {  // the counters of the only chunk are still in LDS
+    hot_emit<WEIGHTED>(sm, a, d, 0, R, P + first);
+    return;
+  }
+  uint64_t base = P;
+  for (uint32_t ch = 0; ch < nch; ++ch) {
+    bool o2 = false;
+    mine = hot_count<WEIGHTED>(sm, du, a, d, ch * HOT_CAP, R, o2);
+    uint32_t tot;
+    first = block_excl_scan<DUB>(mine, du.tmp, &tot);
+    hot_emit<WEIGHTED>(sm, a, d, ch * HOT_CAP, R, base + first);
+    base += tot;
+    __syncthreads();  // the next chunk clears the counters
   }
 }
 
@@ -702,32 +745,29 @@ __device__ __forceinline__ void sort_unit(DSmem& sm, DUnitSmem& du, const DUnitA
                                           uint32_t& nU) {
   using S = BlockRadix<DUB, IT>;
   const int tid = threadIdx.x;
-  // gather: item i of thread t is record i * DUB + t of the unit, kept
-  // packed as local context << 26 | D << 4 | stall (D < 2^22)
+  // every record's local context, from the contexts' start offsets, in the
+  // LDS of the radix counters (free until the sort)
+  uint8_t* const lctx_of = reinterpret_cast<uint8_t*>(sm.cnt);
+  for (uint32_t l = 0; l < nl; ++l)
+    for (uint32_t p = du.lstart[l] + tid; p < du.lstart[l + 1]; p += DUB) lctx_of[p] = (uint8_t)l;
+  __syncthreads();
+  // gather: item i of thread t is record i * DUB + t of the unit (coalesced),
+  // kept packed as local context << 26 | D << 4 | stall (D < 2^22)
   uint32_t key[IT], val[IT];
   uint32_t dmin = 0xFFFFFFFFu, dmax = 0;
-  {
-    uint32_t lo = 0;
 #pragma unroll
-    for (int i = 0; i < IT; ++i) {
-      const uint32_t j = (uint32_t)i * DUB + tid;
-      key[i] = 0;
-      val[i] = 0;
-      if (j < n_u) {
-        uint32_t r = rec[d.s0 + j];
-        if (r == FAR_REC) r = 0;  // the call is redone by the general path
-        uint32_t hi = nl;  // last l with lstart[l] <= j, from the previous item's context on
-        while (hi - lo > 1) {
-          const uint32_t mid = (lo + hi) >> 1;
-          if (du.lstart[mid] <= j) lo = mid;
-          else hi = mid;
-        }
-        key[i] = (lo << 26) | (r & 0x3FFFFFFu);
-        if constexpr (WEIGHTED) val[i] = rw[d.s0 + j];
-        const uint32_t D = (r >> 4) & 0x3FFFFFu;
-        dmin = min(dmin, D);
-        dmax = max(dmax, D);
-      }
+  for (int i = 0; i < IT; ++i) {
+    const uint32_t j = (uint32_t)i * DUB + tid;
+    key[i] = 0;
+    val[i] = 0;
+    if (j < n_u) {
+      uint32_t r = rec[d.s0 + j];
+      if (r == FAR_REC) r = 0;  // the call is redone by the general path
+      key[i] = ((uint32_t)lctx_of[j] << 26) | (r & 0x3FFFFFFu);
+      if constexpr (WEIGHTED) val[i] = rw[d.s0 + j];
+      const uint32_t D = (r >> 4) & 0x3FFFFFu;
+      dmin = min(dmin, D);
+      dmax = max(dmax, D);
     }
   }
   // unit-wide coordinate range: keys are taken relative to its smallest
@@ -883,11 +923,8 @@ __global__ void __launch_bounds__(DUB, 4) k_d_units(DUnitArgs a) {
 bool dense_path_fits(const hpa_structure_map* map, const hpa_samples* smp) {
   if (!map->dense || map->n_win == 0 || map->n_win > DENSE_MAX_WIN) return false;
   if (smp->n >= (1ull << 32) - 1 || smp->n_ctx >= (1u << 31)) return false;
-  // a bucket of a big context is counted in LDS: its coordinates times the
-  // stall reasons must fit HOT_KEYS counters, with DNB buckets covering the map
-  uint32_t bshift = 0;
-  while (((map->n_dense - 1) >> bshift) >= (uint64_t)DNB) ++bshift;
-  return ((uint64_t)NS << bshift) <= (uint64_t)HOT_KEYS && map->n_dense < (1ull << 28);
+  // records hold a coordinate in 22 bits
+  return map->n_dense <= (1ull << 22);
 }
 
 // Returns false (nothing written, no error) when a sample's pc has no dense
