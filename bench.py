@@ -240,6 +240,7 @@ def section_learned(hpa, ctx, n_queries):
     hpa.lookup_learned_counted(ctx, m, one, out_l[: one.numel()], cnt)
     ms_t1 = _timed(lambda: hpa.lookup_intervals(ctx, m, one, out_l[: one.numel()], mode=hpa.LOOKUP_LEARNED)) * 1e3
     ct = cnt.cpu().numpy().view("uint64")
+    n_one = one.numel()
     del q, out_p, out_l, one
     torch.cuda.empty_cache()
     b_alg = 12.0 * n_queries
@@ -250,11 +251,11 @@ def section_learned(hpa, ctx, n_queries):
             "plain_frac_hbm": round(b_alg / (ms_plain * 1e-3) / 1e9 / HBM_PEAK_GBPS, 4),
             "learned_frac_hbm": round(b_alg / (ms_learn * 1e-3) / 1e9 / HBM_PEAK_GBPS, 4),
             "root_flop_per_lookup": 2 * (2 * 64 + 64 * 64 + 64),
-            "trained": {"probes_per_lookup": round(float(ct[0]) / len(one) if len(one) else 0, 3),
+            "trained": {"probes_per_lookup": round(float(ct[0]) / n_one if n_one else 0, 3),
                         "fallbacks": int(ct[1]), "mean_window": round(st["mean_window"], 1),
                         "train_mse": st["train_mse"], "train_s": round(train_s, 2),
                         "ms_per_1e8": round(ms_t1, 2)},
-            "untrained": {"probes_per_lookup": round(float(cu[0]) / len(one) if len(one) else 0, 3),
+            "untrained": {"probes_per_lookup": round(float(cu[0]) / n_one if n_one else 0, 3),
                           "fallbacks": int(cu[1]), "mean_window": round(st_untrained["mean_window"], 1),
                           "ms_per_1e8": round(ms_u, 2)},
             "setup_s": round(time.perf_counter() - t0, 1)}
