@@ -343,6 +343,7 @@ k_d_scatter(const uint64_t* __restrict__ pc, const uint32_t* __restrict__ ctx, c
 // ---------------------------------------------------------------------------
 constexpr int SB = 1024;
 constexpr int SB_PER = DNB / SB;  // buckets per thread
+constexpr int SU = 4;             // records per thread in flight
 
 template <bool WEIGHTED>
 __global__ void __launch_bounds__(SB)
@@ -360,11 +361,21 @@ k_d_split(const uint32_t* __restrict__ big_ctx, const uint32_t* __restrict__ big
   const uint32_t s0 = cbase[c], nc = cbase[c + 1] - s0;
   for (int i = threadIdx.x; i < DNB; i += SB) s_cnt[i] = 0;
   __syncthreads();
-  for (uint32_t i = threadIdx.x; i < nc; i += SB) {
-    const uint32_t r = rec[s0 + i];
-    if (r == FAR_REC) continue;
-    const uint32_t k = (r >> 4) >> bshift;
-    atomicAdd(&s_cnt[k < (uint32_t)DNB ? k : DNB - 1], 1u);
+  // SU records per thread are loaded before any is counted, so the loads
+  // overlap
+  for (uint32_t i0 = 0; i0 < nc; i0 += SU * SB) {
+    uint32_t r[SU];
+#pragma unroll
+    for (int u = 0; u < SU; ++u) {
+      const uint32_t i = i0 + (uint32_t)u * SB + threadIdx.x;
+      r[u] = i < nc ? rec[s0 + i] : FAR_REC;
+    }
+#pragma unroll
+    for (int u = 0; u < SU; ++u) {
+      if (r[u] == FAR_REC) continue;
+      const uint32_t k = (r[u] >> 4) >> bshift;
+      atomicAdd(&s_cnt[k < (uint32_t)DNB ? k : DNB - 1], 1u);
+    }
   }
   __syncthreads();
   // bucket bases: each thread scans its SB_PER consecutive buckets
@@ -420,14 +431,23 @@ k_d_split(const uint32_t* __restrict__ big_ctx, const uint32_t* __restrict__ big
   // records into bucket order
   for (int i = threadIdx.x; i < DNB; i += SB) s_cnt[i] = 0;
   __syncthreads();
-  for (uint32_t i = threadIdx.x; i < nc; i += SB) {
-    const uint32_t r = rec[s0 + i];
-    if (r == FAR_REC) continue;
-    uint32_t k = (r >> 4) >> bshift;
-    k = k < (uint32_t)DNB ? k : DNB - 1;
-    const uint32_t p = s_base[k] + atomicAdd(&s_cnt[k], 1u);
-    rec2[s0 + p] = r;
-    if constexpr (WEIGHTED) rw2[s0 + p] = rw[s0 + i];
+  for (uint32_t i0 = 0; i0 < nc; i0 += SU * SB) {
+    uint32_t r[SU], wv[SU];
+#pragma unroll
+    for (int u = 0; u < SU; ++u) {
+      const uint32_t i = i0 + (uint32_t)u * SB + threadIdx.x;
+      r[u] = i < nc ? rec[s0 + i] : FAR_REC;
+      if constexpr (WEIGHTED) wv[u] = i < nc ? rw[s0 + i] : 0u;
+    }
+#pragma unroll
+    for (int u = 0; u < SU; ++u) {
+      if (r[u] == FAR_REC) continue;
+      uint32_t k = (r[u] >> 4) >> bshift;
+      k = k < (uint32_t)DNB ? k : DNB - 1;
+      const uint32_t p = s_base[k] + atomicAdd(&s_cnt[k], 1u);
+      rec2[s0 + p] = r[u];
+      if constexpr (WEIGHTED) rw2[s0 + p] = wv[u];
+    }
   }
 }
 
@@ -608,38 +628,65 @@ struct DUnitSmem {
 };
 
 // Publish the unit's key count, find the keys of all units before it, and
-// publish the inclusive count.  Thread 0 waits; the spin is bounded so that a
-// broken chain ends the kernel with an error instead of hanging it.
+// publish the inclusive count.  Called by every lane of wave 0; lane l reads
+// the word of unit j - l, so one round of loads covers 64 predecessors: the
+// words up to the nearest inclusive one are summed when all of them are
+// there; otherwise the ready words before the first missing one are summed
+// and the window moves past them.  The wait is bounded, so a broken chain ends
+// the kernel with an error instead of hanging it.
 __device__ inline unsigned long long look_back(unsigned long long* status, uint32_t t, unsigned long long agg,
                                                unsigned int* err) {
+  const int lane = lane_id();
   if (t == 0) {
-    __hip_atomic_store(&status[0], LB_INC | agg, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    if (lane == 0) __hip_atomic_store(&status[0], LB_INC | agg, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
     return 0;
   }
-  __hip_atomic_store(&status[t], LB_AGG | agg, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+  if (lane == 0) __hip_atomic_store(&status[t], LB_AGG | agg, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
   unsigned long long excl = 0;
-  uint32_t j = t - 1, spins = 0;
+  long long j = (long long)t - 1;  // newest predecessor not yet summed
+  uint32_t spins = 0;
   while (true) {
-    const unsigned long long s = __hip_atomic_load(&status[j], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    const long long q = j - lane;
+    // before unit 0 stands an inclusive zero (unit 0 is always inclusive, so
+    // the window never needs it; it only keeps the lanes well defined)
+    const unsigned long long s =
+        q >= 0 ? __hip_atomic_load(&status[q], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) : LB_INC;
     const unsigned long long f = s & ~LB_VAL;
-    if (f == 0) {
-      // a unit that waited too long flags the chain as broken, and every
-      // other waiting unit stops at once
-      if (++spins > LB_SPIN_LIMIT ||
-          ((spins & 1023u) == 0 &&
-           (__hip_atomic_load(err, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) & DERR_LOOKBACK))) {
-        atomicOr(err, DERR_LOOKBACK);
-        break;
+    const unsigned long long missing = __ballot(f == 0);
+    const unsigned long long inc = __ballot(f == LB_INC);
+    // lanes 0 .. li hold the words up to the nearest inclusive one (li = 63
+    // when there is none in the window)
+    const int li = inc ? __ffsll((long long)inc) - 1 : WAVE - 1;
+    const unsigned long long need = li == WAVE - 1 ? ~0ull : ((2ull << li) - 1ull);
+    if (missing & need) {
+      const int nr = __ffsll((long long)(missing & need)) - 1;  // first lane without a word
+      if (nr == 0) {
+        if (++spins > LB_SPIN_LIMIT ||
+            ((spins & 1023u) == 0 &&
+             (__hip_atomic_load(err, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) & DERR_LOOKBACK))) {
+          if (lane == 0) atomicOr(err, DERR_LOOKBACK);
+          break;
+        }
+        __builtin_amdgcn_s_sleep(1);
+        continue;
       }
-      __builtin_amdgcn_s_sleep(1);
+      excl += wave_sum(lane < nr ? (s & LB_VAL) : 0ull);
+      j -= nr;
       continue;
     }
-    excl += s & LB_VAL;
-    if (f == LB_INC || j == 0) break;
-    --j;
+    excl += wave_sum(lane <= li ? (s & LB_VAL) : 0ull);
+    if (inc) break;
+    j -= WAVE;
   }
-  __hip_atomic_store(&status[t], LB_INC | (excl + agg), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+  if (lane == 0) __hip_atomic_store(&status[t], LB_INC | (excl + agg), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
   return excl;
+}
+
+// A value every lane holds alike, moved to scalar registers.
+__device__ inline unsigned long long uniform_u64(unsigned long long v) {
+  const uint32_t lo = (uint32_t)__builtin_amdgcn_readfirstlane((int)(uint32_t)v);
+  const uint32_t hi = (uint32_t)__builtin_amdgcn_readfirstlane((int)(uint32_t)(v >> 32));
+  return ((unsigned long long)hi << 32) | lo;
 }
 
 // A counted part: one coordinate bucket [d0, d0 + 2^bshift) of one context.
@@ -659,15 +706,27 @@ __device__ inline uint32_t hot_count(DSmem& sm, DUnitSmem& du, const DUnitArgs& 
   const uint32_t kn = min(HOT_CAP, R - k0);
   for (uint32_t i = tid; i < kn; i += DUB) cnt[i] = 0;
   __syncthreads();
-  for (uint32_t i = d.s0 + tid; i < d.s1; i += DUB) {
-    const uint32_t r = a.rec2[i];
-    if (r == FAR_REC) continue;
-    const uint32_t k = (((r >> 4) - d.d0) << 4) | (r & 15u);
-    if (k >= R) { ovf = true; continue; }
-    if (k < k0 || k >= k0 + kn) continue;
-    const uint32_t w = WEIGHTED ? a.rw2[i] : 1u;
-    const uint32_t old = atomicAdd(&cnt[k - k0], w);
-    ovf |= old + w < old;
+  constexpr int HU = 4;  // records per thread in flight
+  for (uint32_t i0 = d.s0; i0 < d.s1; i0 += HU * DUB) {
+    uint32_t r[HU], wv[HU];
+#pragma unroll
+    for (int u = 0; u < HU; ++u) {
+      const uint32_t i = i0 + (uint32_t)u * DUB + tid;
+      r[u] = i < d.s1 ? a.rec2[i] : FAR_REC;
+      wv[u] = WEIGHTED ? (i < d.s1 ? a.rw2[i] : 0u) : 1u;
+    }
+#pragma unroll
+    for (int u = 0; u < HU; ++u) {
+      if (r[u] == FAR_REC) continue;
+      const uint32_t k = (((r[u] >> 4) - d.d0) << 4) | (r[u] & 15u);
+      if (k >= R) {
+        ovf = true;
+        continue;
+      }
+      if (k < k0 || k >= k0 + kn) continue;
+      const uint32_t old = atomicAdd(&cnt[k - k0], wv[u]);
+      ovf |= old + wv[u] < old;
+    }
   }
   __syncthreads();
   // thread t owns a block of `per` consecutive counters
@@ -715,7 +774,10 @@ __device__ inline void hot_unit(DSmem& sm, DUnitSmem& du, const DUnitArgs& a, co
     nU += tot;
   }
   if (ovf) atomicOr(&a.info->err, DERR_OVERFLOW);
-  if (tid == 0) du.P = look_back(a.status, du.t, nU, &a.info->err);
+  if (tid < WAVE) {
+    const unsigned long long p = look_back(a.status, du.t, nU, &a.info->err);
+    if (tid == 0) du.P = p;
+  }
   __syncthreads();
   const unsigned long long P = du.P;
   if (tid == 0 && d.s0 == a.cbase[d.cb]) a.out.ctx_off[d.cb] = P;
@@ -797,22 +859,78 @@ __device__ __forceinline__ void sort_unit(DSmem& sm, DUnitSmem& du, const DUnitA
     S::template sort<0, true>(key, val, val, min(kbits, 31) + 1, (int)n_u, true, sm.buf, sm.cnt, sm.doff);
   uint32_t first;
   find_heads<uint32_t, IT>(sm, key, n_u, nl, pcb, first, nU);
-  if (tid == 0) du.P = look_back(a.status, t, nU, &a.info->err);
+  if (tid < WAVE) {
+    const unsigned long long p = look_back(a.status, t, nU, &a.info->err);
+    if (tid == 0) du.P = p;
+  }
   __syncthreads();
   P = du.P;
   if constexpr (WEIGHTED) weighted_counts<uint32_t, IT>(sm, key, val, n_u, first, a.out.count + P);
-  // consecutive threads take consecutive keys from the compacted copy
+  // consecutive threads take consecutive keys from the compacted copy, OB
+  // keys per thread at a time: all their scope labels are requested before
+  // the first store, so the gathers overlap.  The output bases are made
+  // uniform so that every store addresses with a 32-bit offset, and the
+  // outputs, not read again here, bypass the caches.
+  constexpr int OB = 8;
   const uint32_t pmask = (1u << pcb) - 1u;
-  for (uint32_t ui = tid; ui < nU; ui += DUB) {
-    const uint32_t kk = sm.buf[ui];
-    const uint32_t lc = kk >> (pcb + 4);
-    const uint64_t D = dmin + ((kk >> 4) & pmask);
-    const uint64_t o = P + ui;
-    a.out.ctx[o] = du.lctx[lc < nl ? lc : 0];
-    a.out.pc[o] = from_dense(a.dd, D);
-    a.out.stall[o] = (uint8_t)(kk & 15u);
-    if constexpr (!WEIGHTED) a.out.count[o] = (uint32_t)sm.upos[ui + 1] - (uint32_t)sm.upos[ui];
-    a.out.scope[o] = a.dd.scope_of[D];
+  const unsigned long long Pu = uniform_u64(P);
+  uint32_t* const octx = a.out.ctx + Pu;
+  uint64_t* const opc = a.out.pc + Pu;
+  uint8_t* const ostall = a.out.stall + Pu;
+  unsigned long long* const ocnt = a.out.count + Pu;
+  uint32_t* const oscope = a.out.scope + Pu;
+  // the windows the unit's coordinates can fall in; up to WR of them are
+  // held in registers (their first coordinates and pc bases), so a key's pc
+  // needs no search
+  constexpr int WR = 4;
+  const uint32_t w0 = last_le(a.dd.d, a.dd.n_win, (uint64_t)dmin);
+  const uint32_t w1 = last_le(a.dd.d, a.dd.n_win, (uint64_t)du.red_max);
+  const bool few = w1 - w0 < (uint32_t)WR;
+  uint32_t wfirst[WR];
+  uint64_t wbase[WR];  // pc of coordinate 0 if the window extended down to it
+#pragma unroll
+  for (int q = 0; q < WR; ++q) {
+    const uint32_t w = min(w0 + (uint32_t)q, w1);
+    wfirst[q] = q == 0 ? 0u : (w0 + (uint32_t)q <= w1 ? (uint32_t)a.dd.d[w] : 0xFFFFFFFFu);
+    wbase[q] = a.dd.lo[w] - (a.dd.d[w] << a.dd.tz);
+  }
+  for (uint32_t u0 = 0; u0 < nU; u0 += OB * DUB) {
+    // every read stays inside the exchange plane (nU <= DUT = 2 * OB * DUB)
+    // and inside the scope table (a slot past nU reads coordinate dmin), so
+    // no read needs a branch
+    static_assert(DUT % (OB * DUB) == 0, "batches tile the unit");
+    uint32_t kk[OB], sc[OB];
+#pragma unroll
+    for (int j = 0; j < OB; ++j) kk[j] = sm.buf[u0 + (uint32_t)j * DUB + tid];
+#pragma unroll
+    for (int j = 0; j < OB; ++j) {
+      const uint32_t ui = u0 + (uint32_t)j * DUB + tid;
+      sc[j] = a.dd.scope_of[dmin + (ui < nU ? (kk[j] >> 4) & pmask : 0u)];
+    }
+#pragma unroll
+    for (int j = 0; j < OB; ++j) {
+      const uint32_t ui = u0 + (uint32_t)j * DUB + tid;
+      if (ui < nU) {
+        const uint32_t lc = kk[j] >> (pcb + 4);
+        const uint32_t D = dmin + ((kk[j] >> 4) & pmask);
+        uint64_t pc;
+        if (few) {
+          uint64_t b = wbase[0];
+#pragma unroll
+          for (int q = 1; q < WR; ++q) b = D >= wfirst[q] ? wbase[q] : b;
+          pc = b + ((uint64_t)D << a.dd.tz);
+        } else {
+          pc = from_dense(a.dd, D);
+        }
+        __builtin_nontemporal_store(du.lctx[lc < nl ? lc : 0], &octx[ui]);
+        __builtin_nontemporal_store(pc, &opc[ui]);
+        __builtin_nontemporal_store((uint8_t)(kk[j] & 15u), &ostall[ui]);
+        if constexpr (!WEIGHTED)
+          __builtin_nontemporal_store((unsigned long long)((uint32_t)sm.upos[ui + 1] - (uint32_t)sm.upos[ui]),
+                                      &ocnt[ui]);
+        __builtin_nontemporal_store(sc[j], &oscope[ui]);
+      }
+    }
   }
 }
 
@@ -876,7 +994,10 @@ __global__ void __launch_bounds__(DUB, 4) k_d_units(DUnitArgs a) {
     unsigned long long P = 0;
     uint32_t nU = 0;
     if (n_u == 0) {  // only empty contexts
-      if (tid == 0) du.P = look_back(a.status, t, 0, &a.info->err);
+      if (tid < WAVE) {
+        const unsigned long long p = look_back(a.status, t, 0, &a.info->err);
+        if (tid == 0) du.P = p;
+      }
       __syncthreads();
       P = du.P;
     } else if (n_u <= 4u * DUB) {

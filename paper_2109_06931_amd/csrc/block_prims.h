@@ -27,6 +27,24 @@ __device__ inline uint32_t wave_incl_scan_u32(uint32_t v) {
   return v;
 }
 
+// The same scan over N independent values, one DPP step for all of them
+// before the next, so that no step waits on the one just before it.
+template <int N>
+__device__ inline void wave_incl_scan_u32_n(uint32_t (&v)[N]) {
+#pragma unroll
+  for (int k = 0; k < N; ++k) v[k] += (uint32_t)__builtin_amdgcn_update_dpp(0, (int)v[k], 0x111, 0xF, 0xF, true);
+#pragma unroll
+  for (int k = 0; k < N; ++k) v[k] += (uint32_t)__builtin_amdgcn_update_dpp(0, (int)v[k], 0x112, 0xF, 0xF, true);
+#pragma unroll
+  for (int k = 0; k < N; ++k) v[k] += (uint32_t)__builtin_amdgcn_update_dpp(0, (int)v[k], 0x114, 0xF, 0xF, true);
+#pragma unroll
+  for (int k = 0; k < N; ++k) v[k] += (uint32_t)__builtin_amdgcn_update_dpp(0, (int)v[k], 0x118, 0xF, 0xF, true);
+#pragma unroll
+  for (int k = 0; k < N; ++k) v[k] += (uint32_t)__builtin_amdgcn_update_dpp(0, (int)v[k], 0x142, 0xA, 0xF, false);
+#pragma unroll
+  for (int k = 0; k < N; ++k) v[k] += (uint32_t)__builtin_amdgcn_update_dpp(0, (int)v[k], 0x143, 0xC, 0xF, false);
+}
+
 __device__ inline uint32_t wave_last_u32(uint32_t v) { return (uint32_t)__builtin_amdgcn_readlane((int)v, WAVE - 1); }
 
 template <class T>
@@ -116,16 +134,19 @@ __device__ inline T block_excl_scan(T v, T* s_tmp, T* total) {
 // never exceeds ITEMS - 1 <= 15); the 16 counts, widened to 16-bit pairs in 8
 // columns, are scanned over each wave's lanes in registers; the wave
 // totals, scanned over the waves and offset by the scanned digit totals, give
-// each thread its own table of where its keys of each digit start; each
-// item's new position is that start plus the running count, and the key is
-// written there in the exchange plane and read back blocked.
+// each thread its own table in LDS of where its keys of each digit start (one
+// word per digit, at digit * BLOCK + thread, so a wave's accesses fall in
+// distinct banks); each item takes its new position from its digit's word
+// with an LDS fetch-and-add, in item order, so equal digits keep their order
+// without any count in registers, and the key is written there in the
+// exchange plane and read back blocked.
 template <int BLOCK, int ITEMS>
 struct BlockRadix {
   static constexpr int T = BLOCK * ITEMS;
   static constexpr int NW = BLOCK / WAVE;
   static constexpr int BUF_WORDS = T + T / 32;  // exchange plane, padded every 32 words
-  static constexpr int CNT_WORDS = 8 * BLOCK;   // 8 columns of 16-bit digit pairs
-  static constexpr int DOFF_WORDS = 8 * NW;     // per wave: the 8 column totals, then their offsets
+  static constexpr int CNT_WORDS = 16 * BLOCK;  // per digit, one position word per thread
+  static constexpr int DOFF_WORDS = 8 * NW;     // per wave: the 8 column totals
   static_assert(T < 65536, "16-bit counters");
   static_assert(ITEMS >= 2 && ITEMS <= 16, "4-bit per-thread counters hold ITEMS - 1");
 
@@ -156,62 +177,67 @@ struct BlockRadix {
       uint64_t h = 0;
 #pragma unroll
       for (int i = 0; i < ITEMS - 1; ++i)
-        if (HPA_VALID(i)) h += 1ull << (((key[i] >> shift) & 15u) * 4);
-      const uint32_t dl = HPA_VALID(ITEMS - 1) ? (key[ITEMS - 1] >> shift) & 15u : 16u;
+        if (HPA_VALID(i)) h += 1ull << (__builtin_amdgcn_ubfe(key[i], (uint32_t)shift, 4u) * 4);
+      const uint32_t dl = HPA_VALID(ITEMS - 1) ? __builtin_amdgcn_ubfe(key[ITEMS - 1], (uint32_t)shift, 4u) : 16u;
       // 2. widen to 16-bit pairs (column k holds digits 2k low and 2k+1
       //    high) and scan every column over the wave's lanes in registers;
       //    the wave totals go to LDS
-      uint32_t ex[8];
+      uint32_t ex[8], inc[8];
 #pragma unroll
       for (int k = 0; k < 8; ++k) {
         const uint32_t w = (uint32_t)(h >> (8 * k));
-        uint32_t col = (w & 0xFu) | ((w & 0xF0u) << 12);
-        if ((dl >> 1) == (uint32_t)k) col += 1u << ((dl & 1u) * 16);
-        const uint32_t inc = wave_incl_scan_u32(col);
-        ex[k] = inc - col;
-        if (lane_id() == WAVE - 1) s_doff[wave_id() * 8 + k] = inc;
+        ex[k] = (w & 0xFu) | ((w & 0xF0u) << 12);
+        if ((dl >> 1) == (uint32_t)k) ex[k] += 1u << ((dl & 1u) * 16);
+        inc[k] = ex[k];
+      }
+      wave_incl_scan_u32_n(inc);
+#pragma unroll
+      for (int k = 0; k < 8; ++k) {
+        ex[k] = inc[k] - ex[k];
+        if (lane_id() == WAVE - 1) s_doff[wave_id() * 8 + k] = inc[k];
       }
       __syncthreads();
-      // 3. wave 0, lane k < 8 takes column k: the exclusive prefix over the
-      //    waves, plus the offsets of digits 2k and 2k+1 (an exclusive scan of
-      //    the 16 digit totals, as pairs over lanes 0..7), back in place.
+      // 3. every wave derives its own column offsets from all the wave
+      //    totals (no second barrier): lane k < 8 sums column k over all
+      //    waves and over the waves before its own; the exclusive scan of
+      //    the 16 digit totals, as pairs over lanes 0..7, gives the digit
+      //    offsets; lane k's packed offsets reach every lane by readlane.
       //    Halves never carry: every count is below T < 65536.
-      if (tid < WAVE) {
+      uint32_t dof[8];
+      {
         const int k = lane_id();
-        uint32_t tot = 0;
-        if (k < 8)
-#pragma unroll
-          for (int w = 0; w < NW; ++w) tot += s_doff[w * 8 + k];
-        const uint32_t pair = k < 8 ? (tot & 0xFFFFu) + (tot >> 16) : 0u;
-        const uint32_t lo = wave_incl_scan_u32(pair) - pair;
-        const uint32_t base = lo | ((lo + (tot & 0xFFFFu)) << 16);
+        uint32_t tot = 0, below = 0;
         if (k < 8) {
-          uint32_t run = base;
 #pragma unroll
           for (int w = 0; w < NW; ++w) {
             const uint32_t t = s_doff[w * 8 + k];
-            s_doff[w * 8 + k] = run;
-            run += t;
+            tot += t;
+            below += w < wave_id() ? t : 0u;
           }
         }
-      }
-      __syncthreads();
-      // every thread's own column table: digit offset + wave prefix + lane
-      // prefix (read back only by the same thread)
+        const uint32_t pair = k < 8 ? (tot & 0xFFFFu) + (tot >> 16) : 0u;
+        const uint32_t lo = wave_incl_scan_u32(pair) - pair;
+        const uint32_t mine = (lo | ((lo + (tot & 0xFFFFu)) << 16)) + below;
 #pragma unroll
-      for (int k = 0; k < 8; ++k) s_cnt[k * BLOCK + tid] = s_doff[wave_id() * 8 + k] + ex[k];
-      // 4. positions: digit offset + thread prefix + running count.  The
-      // digits are extracted again rather than kept from step 1: holding 2 x
-      // ITEMS values across the scans costs more registers than the shifts.
+        for (int j = 0; j < 8; ++j) dof[j] = (uint32_t)__builtin_amdgcn_readlane((int)mine, j);
+      }
+      // every thread's own table: digit offset + wave prefix + lane prefix,
+      // one word per digit (used only by the same thread)
+#pragma unroll
+      for (int k = 0; k < 8; ++k) {
+        const uint32_t v = dof[k] + ex[k];
+        s_cnt[(2 * k) * BLOCK + tid] = v & 0xFFFFu;
+        s_cnt[(2 * k + 1) * BLOCK + tid] = v >> 16;
+      }
+      // 4. positions: each item fetches its digit's word and advances it.
+      // The digits are extracted again rather than kept from step 1: holding
+      // 2 x ITEMS values across the scans costs more registers than the
+      // shifts.
 #pragma unroll
       for (int i = 0; i < ITEMS; ++i) asm volatile("" : "+v"(key[i]));
-      uint64_t r = 0;
       auto position = [&](int i) -> uint32_t {
-        const uint32_t d = (key[i] >> shift) & 15u;
-        const uint32_t pre = (s_cnt[(d >> 1) * BLOCK + tid] >> ((d & 1) * 16)) & 0xFFFFu;
-        const uint32_t p = pre + ((uint32_t)(r >> (d * 4)) & 15u);
-        if (i < ITEMS - 1) r += 1ull << (d * 4);
-        return p;
+        const uint32_t d = __builtin_amdgcn_ubfe(key[i], (uint32_t)shift, 4u);
+        return atomicAdd(&s_cnt[d * BLOCK + tid], 1u);
       };
       if constexpr (NV == 0) {
         // one plane: write each key as soon as its position is known

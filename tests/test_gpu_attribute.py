@@ -118,6 +118,21 @@ def test_attribute_small(hpa, hctx, seed, kw):
     assert_attribution_equal(a.numpy(), oa, f"small{seed}{kw}")
 
 
+@pytest.mark.parametrize("seed,n_bins,weighted", [
+    # one address window per binary: a unit whose keys fall in up to four
+    # windows finds a key's window among registers, more windows take the
+    # search over the window table; few contexts, so units span all windows
+    (12, 3, False),
+    (13, 7, False),
+    (14, 7, True),
+    (15, 12, False),
+])
+def test_attribute_many_windows(hpa, hctx, seed, n_bins, weighted):
+    w = small_config(seed, n_samples=250_000, n_ctx=40, n_bins=n_bins, weighted=weighted)
+    m, om, a, oa = _run(hpa, hctx, w)
+    assert_attribution_equal(a.numpy(), oa, f"windows{n_bins}")
+
+
 @pytest.mark.parametrize("seed,kw,fallback", [
     # contexts of ~37k samples: most are cut into parts by coordinate range,
     # a few keep the chunk path (one coordinate bucket over 16,384 samples)
