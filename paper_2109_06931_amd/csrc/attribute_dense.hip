@@ -31,6 +31,7 @@
 // the instruction grid) is counted; the caller then runs the general path.
 #include <algorithm>
 #include <memory>
+#include <type_traits>
 
 #include "block_prims.h"
 #include "hpa_internal.h"
@@ -341,9 +342,30 @@ k_d_scatter(const uint64_t* __restrict__ pc, const uint32_t* __restrict__ ctx, c
 // ---------------------------------------------------------------------------
 // split of big contexts (one workgroup each)
 // ---------------------------------------------------------------------------
-constexpr int SB = 1024;
+constexpr int SB = 512;
 constexpr int SB_PER = DNB / SB;  // buckets per thread
-constexpr int SU = 4;             // records per thread in flight
+constexpr int SU_H = 16;          // records per thread in flight while counting
+constexpr int SU_C = 8;           // ... while copying
+
+// The end of the greedy part that starts at bucket k: the last bucket end e
+// in [k + 1, DNB] with base[e] <= base[k] + DUT, and at least k + 1 (a single
+// bucket over DUT samples).  base is non-decreasing, so the test holds on a
+// prefix of the range: wave 0 probes it 64-ary in two rounds (every lane
+// gets the answer).
+__device__ inline uint32_t part_end(const uint32_t* s_base, uint32_t k) {
+  static_assert(DNB <= WAVE * WAVE, "two 64-ary rounds cover the buckets");
+  const int lane = lane_id();
+  const uint32_t lim = s_base[k] + (uint32_t)DUT;
+  const uint32_t lo = k + 1, n = (uint32_t)DNB - lo + 1;  // candidates lo .. DNB
+  const uint32_t st = (n + WAVE - 1) / WAVE;                  // <= WAVE
+  uint32_t idx = lo + (uint32_t)lane * st;
+  unsigned long long m = __ballot(idx <= (uint32_t)DNB && s_base[idx <= (uint32_t)DNB ? idx : DNB] <= lim);
+  if (m == 0) return lo;  // bucket k alone is over DUT
+  const uint32_t j0 = lo + (uint32_t)(63 - __clzll((long long)m)) * st;  // last probe that holds
+  idx = j0 + (uint32_t)lane;
+  m = __ballot((uint32_t)lane < st && idx <= (uint32_t)DNB && s_base[idx <= (uint32_t)DNB ? idx : DNB] <= lim);
+  return j0 + (uint32_t)(63 - __clzll((long long)m));
+}
 
 template <bool WEIGHTED>
 __global__ void __launch_bounds__(SB)
@@ -353,7 +375,6 @@ k_d_split(const uint32_t* __restrict__ big_ctx, const uint32_t* __restrict__ big
           uint32_t* __restrict__ n_bunits, DInfo* __restrict__ info) {
   __shared__ uint32_t s_cnt[DNB];   // bucket counts, then cursors
   __shared__ uint32_t s_base[DNB + 1];
-  __shared__ uint32_t s_next[DNB];
   __shared__ uint32_t s_tmp[SB / WAVE + 1];
   const uint32_t b = blockIdx.x;
   if (b >= info->n_big) return;
@@ -361,17 +382,17 @@ k_d_split(const uint32_t* __restrict__ big_ctx, const uint32_t* __restrict__ big
   const uint32_t s0 = cbase[c], nc = cbase[c + 1] - s0;
   for (int i = threadIdx.x; i < DNB; i += SB) s_cnt[i] = 0;
   __syncthreads();
-  // SU records per thread are loaded before any is counted, so the loads
+  // SU_H records per thread are loaded before any is counted, so the loads
   // overlap
-  for (uint32_t i0 = 0; i0 < nc; i0 += SU * SB) {
-    uint32_t r[SU];
+  for (uint32_t i0 = 0; i0 < nc; i0 += SU_H * SB) {
+    uint32_t r[SU_H];
 #pragma unroll
-    for (int u = 0; u < SU; ++u) {
+    for (int u = 0; u < SU_H; ++u) {
       const uint32_t i = i0 + (uint32_t)u * SB + threadIdx.x;
       r[u] = i < nc ? rec[s0 + i] : FAR_REC;
     }
 #pragma unroll
-    for (int u = 0; u < SU; ++u) {
+    for (int u = 0; u < SU_H; ++u) {
       if (r[u] == FAR_REC) continue;
       const uint32_t k = (r[u] >> 4) >> bshift;
       atomicAdd(&s_cnt[k < (uint32_t)DNB ? k : DNB - 1], 1u);
@@ -393,54 +414,44 @@ k_d_split(const uint32_t* __restrict__ big_ctx, const uint32_t* __restrict__ big
     if (threadIdx.x == 0) s_base[DNB] = tot;
   }
   __syncthreads();
-  // greedy packing: a part from bucket k reaches the last bucket e with
-  // base[e] - base[k] <= DUT (at least bucket k itself)
+  // greedy packing along the chain of part ends (wave 0); parts start at
+  // non-empty buckets, and empty buckets before a part's first records join
+  // it.  The other waves clear the cursors meanwhile.
   const uint32_t total = s_base[DNB];
-  for (int k = threadIdx.x; k < DNB; k += SB) {
-    const uint32_t lim = s_base[k] + (uint32_t)DUT;
-    uint32_t lo = (uint32_t)k + 1, hi = DNB;  // first e in [k+1, DNB] with base[e] > lim, minus one
-    while (lo < hi) {
-      const uint32_t mid = (lo + hi + 1) >> 1;
-      if (s_base[mid] <= lim) lo = mid;
-      else hi = mid - 1;
-    }
-    s_next[k] = lo;  // exclusive end bucket of the part starting at k
-  }
-  __syncthreads();
-  if (threadIdx.x == 0) {
+  if (threadIdx.x < WAVE) {
     const uint32_t slot0 = big_slot0[b], cap = big_slots(nc);
     uint32_t k = 0, m = 0;
-    // parts start at non-empty buckets; empty buckets before a part's first
-    // records join it
     while (k < (uint32_t)DNB && s_base[k] < total) {
-      const uint32_t e = s_next[k];
+      const uint32_t e = part_end(s_base, k);
       const uint32_t len = s_base[e] - s_base[k];
       // a single bucket over DUT samples is counted, not sorted
       const bool hot = len > (uint32_t)DUT;
-      if (m < cap) {
-        bunits[slot0 + m] = DUnit{s0 + s_base[k], s0 + s_base[e], c, c + 1, hot ? DU_HOT : DU_PART, k << bshift, 0, 0};
-      } else {
-        atomicOr(&info->err, DERR_INTERNAL);
+      if (threadIdx.x == 0) {
+        if (m < cap) {
+          bunits[slot0 + m] = DUnit{s0 + s_base[k], s0 + s_base[e], c, c + 1, hot ? DU_HOT : DU_PART, k << bshift, 0, 0};
+        } else {
+          atomicOr(&info->err, DERR_INTERNAL);
+        }
       }
       ++m;
       k = e;
     }
-    n_bunits[b] = m < cap ? m : cap;
+    if (threadIdx.x == 0) n_bunits[b] = m < cap ? m : cap;
+  } else {
+    for (int i = threadIdx.x - WAVE; i < DNB; i += SB - WAVE) s_cnt[i] = 0;
   }
   __syncthreads();
   // records into bucket order
-  for (int i = threadIdx.x; i < DNB; i += SB) s_cnt[i] = 0;
-  __syncthreads();
-  for (uint32_t i0 = 0; i0 < nc; i0 += SU * SB) {
-    uint32_t r[SU], wv[SU];
+  for (uint32_t i0 = 0; i0 < nc; i0 += SU_C * SB) {
+    uint32_t r[SU_C], wv[SU_C];
 #pragma unroll
-    for (int u = 0; u < SU; ++u) {
+    for (int u = 0; u < SU_C; ++u) {
       const uint32_t i = i0 + (uint32_t)u * SB + threadIdx.x;
       r[u] = i < nc ? rec[s0 + i] : FAR_REC;
       if constexpr (WEIGHTED) wv[u] = i < nc ? rw[s0 + i] : 0u;
     }
 #pragma unroll
-    for (int u = 0; u < SU; ++u) {
+    for (int u = 0; u < SU_C; ++u) {
       if (r[u] == FAR_REC) continue;
       uint32_t k = (r[u] >> 4) >> bshift;
       k = k < (uint32_t)DNB ? k : DNB - 1;
@@ -614,34 +625,52 @@ struct DUnitArgs {
   DenseDev dd;
   DInfo* info;
   unsigned long long* status;  // per unit: look-back word
+  // per workgroup, two slots of DUT keys (one for the unit being sorted, one
+  // for the unit waiting to be written) and their counts (u16 unweighted,
+  // u64 weighted)
+  uint32_t* stage_key;
+  void* stage_cnt;
   OutDev out;
 };
 
+// A sorted unit whose keys wait in a staging slot for their offset.
+struct DPend {
+  DUnit d;
+  uint32_t t, nU, dmin, dmax, nl, slot;
+  bool valid;
+};
+
 struct DUnitSmem {
-  uint32_t lstart[MAXC + 1];  // record offset of each non-empty local context, closed by n_u
-  uint32_t lctx[MAXC];        // its context id
-  uint32_t lrank[DUB];        // per context of the unit: non-empty contexts before it
-  unsigned long long loff[MAXC + 1];
+  DPend pend[2];                 // per slot: the unit staged there (kept in LDS, not registers)
+  uint32_t lstart[MAXC + 1];     // record offset of each non-empty local context, closed by n_u
+  uint32_t lctx[2][MAXC];        // per slot: context id of each local context
+  uint8_t lrank[2][DUB];         // per slot and context of the unit: non-empty contexts before it
+  unsigned long long loff[2][MAXC + 1];  // per slot: keys of the local contexts before each
   unsigned long long P;
   uint32_t t, nl, red_min, red_max;
   uint32_t tmp[DUB / WAVE + 1];
 };
 
-// Publish the unit's key count, find the keys of all units before it, and
-// publish the inclusive count.  Called by every lane of wave 0; lane l reads
-// the word of unit j - l, so one round of loads covers 64 predecessors: the
-// words up to the nearest inclusive one are summed when all of them are
-// there; otherwise the ready words before the first missing one are summed
-// and the window moves past them.  The wait is bounded, so a broken chain ends
-// the kernel with an error instead of hanging it.
+// Decoupled look-back over the units' key counts, in two halves: a unit
+// publishes its count as soon as it knows it, and finds its offset (the keys
+// of all units before it) only when it is about to write, one unit later, so
+// that predecessors slower than itself rarely keep it waiting.  Unit 0 is
+// inclusive at once.
+__device__ inline void publish_count(unsigned long long* status, uint32_t t, unsigned long long agg) {
+  __hip_atomic_store(&status[t], (t == 0 ? LB_INC : LB_AGG) | agg, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+
+// Called by every lane of wave 0 after publish_count(t); lane l reads the
+// word of unit j - l, so one round of loads covers 64 predecessors: the words
+// up to the nearest inclusive one are summed when all of them are there;
+// otherwise the ready words before the first missing one are summed and the
+// window moves past them.  Publishes the unit's inclusive count.  The wait is
+// bounded, so a broken chain ends the kernel with an error instead of hanging
+// it.
 __device__ inline unsigned long long look_back(unsigned long long* status, uint32_t t, unsigned long long agg,
                                                unsigned int* err) {
   const int lane = lane_id();
-  if (t == 0) {
-    if (lane == 0) __hip_atomic_store(&status[0], LB_INC | agg, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-    return 0;
-  }
-  if (lane == 0) __hip_atomic_store(&status[t], LB_AGG | agg, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+  if (t == 0) return 0;
   unsigned long long excl = 0;
   long long j = (long long)t - 1;  // newest predecessor not yet summed
   uint32_t spins = 0;
@@ -687,6 +716,12 @@ __device__ inline unsigned long long uniform_u64(unsigned long long v) {
   const uint32_t lo = (uint32_t)__builtin_amdgcn_readfirstlane((int)(uint32_t)v);
   const uint32_t hi = (uint32_t)__builtin_amdgcn_readfirstlane((int)(uint32_t)(v >> 32));
   return ((unsigned long long)hi << 32) | lo;
+}
+
+// The last unit closes the context offsets and reports the key count.
+__device__ inline void close_units(const DUnitArgs& a, unsigned long long end) {
+  a.out.ctx_off[a.C] = end;
+  a.info->total_keys = end;
 }
 
 // A counted part: one coordinate bucket [d0, d0 + 2^bshift) of one context.
@@ -760,8 +795,10 @@ __device__ inline void hot_emit(DSmem& sm, const DUnitArgs& a, const DUnit& d, u
   }
 }
 
+// A counted part publishes its count and waits for its offset at once (its
+// keys live in the counters, not in a staging slot).
 template <bool WEIGHTED>
-__device__ inline void hot_unit(DSmem& sm, DUnitSmem& du, const DUnitArgs& a, const DUnit& d) {
+__device__ inline void hot_unit(DSmem& sm, DUnitSmem& du, const DUnitArgs& a, const DUnit& d, uint32_t n_units) {
   const int tid = threadIdx.x;
   const uint32_t R = (1u << a.bshift) * NS;  // the bucket's key range
   const uint32_t nch = (R + HOT_CAP - 1) / HOT_CAP;
@@ -775,12 +812,14 @@ __device__ inline void hot_unit(DSmem& sm, DUnitSmem& du, const DUnitArgs& a, co
   }
   if (ovf) atomicOr(&a.info->err, DERR_OVERFLOW);
   if (tid < WAVE) {
+    if (tid == 0) publish_count(a.status, du.t, nU);
     const unsigned long long p = look_back(a.status, du.t, nU, &a.info->err);
     if (tid == 0) du.P = p;
   }
   __syncthreads();
   const unsigned long long P = du.P;
   if (tid == 0 && d.s0 == a.cbase[d.cb]) a.out.ctx_off[d.cb] = P;
+  if (tid == 0 && du.t == n_units - 1) close_units(a, P + nU);
   if (nch == 1) {  // the counters of the only chunk are still in LDS
     hot_emit<WEIGHTED>(sm, a, d, 0, R, P + first);
     return;
@@ -797,14 +836,25 @@ __device__ inline void hot_unit(DSmem& sm, DUnitSmem& du, const DUnitArgs& a, co
   }
 }
 
+template <bool WEIGHTED>
+__device__ inline uint32_t* slot_keys(const DUnitArgs& a, uint32_t slot) {
+  return a.stage_key + ((uint64_t)blockIdx.x * 2 + slot) * DUT;
+}
+template <bool WEIGHTED>
+__device__ inline auto slot_counts(const DUnitArgs& a, uint32_t slot) {
+  using C = typename std::conditional<WEIGHTED, unsigned long long, uint16_t>::type;
+  return static_cast<C*>(a.stage_cnt) + ((uint64_t)blockIdx.x * 2 + slot) * DUT;
+}
+
 // Sort and reduce one SMALL or PART unit of n_u > 0 records with IT items
 // per thread (the least that holds it: a sort pass costs in proportion to the
-// slots it sorts), find its output offset, and write its keys.
+// slots it sorts), publish its key count, and stage its unique keys and
+// counts in the slot.
 template <bool WEIGHTED, int IT>
 __device__ __forceinline__ void sort_unit(DSmem& sm, DUnitSmem& du, const DUnitArgs& a, const DUnit& d,
                                           const uint32_t* __restrict__ rec, const uint32_t* __restrict__ rw,
-                                          uint32_t n_u, uint32_t nl, uint32_t t, unsigned long long& P,
-                                          uint32_t& nU) {
+                                          uint32_t n_u, uint32_t nl, uint32_t t, uint32_t slot, uint32_t& nU,
+                                          uint32_t& dmin_out, uint32_t& dmax_out) {
   using S = BlockRadix<DUB, IT>;
   const int tid = threadIdx.x;
   // every record's local context, from the contexts' start offsets, in the
@@ -841,6 +891,8 @@ __device__ __forceinline__ void sort_unit(DSmem& sm, DUnitSmem& du, const DUnitA
   }
   __syncthreads();
   dmin = du.red_min;
+  dmin_out = dmin;
+  dmax_out = du.red_max;
   const int pcb = bits_for(du.red_max - dmin);
   const int kbits = bits_for(nl - 1) + pcb + 4;
   // the plan keeps local contexts few enough that keys fit 31 bits
@@ -859,32 +911,53 @@ __device__ __forceinline__ void sort_unit(DSmem& sm, DUnitSmem& du, const DUnitA
     S::template sort<0, true>(key, val, val, min(kbits, 31) + 1, (int)n_u, true, sm.buf, sm.cnt, sm.doff);
   uint32_t first;
   find_heads<uint32_t, IT>(sm, key, n_u, nl, pcb, first, nU);
+  if (tid == 0) publish_count(a.status, t, nU);
+  // stage the compacted keys and their counts (consecutive threads take
+  // consecutive keys)
+  uint32_t* const skey = slot_keys<WEIGHTED>(a, slot);
+  for (uint32_t ui = tid; ui < nU; ui += DUB) skey[ui] = sm.buf[ui];
+  if constexpr (WEIGHTED) {
+    weighted_counts<uint32_t, IT>(sm, key, val, n_u, first, slot_counts<true>(a, slot));
+  } else {
+    uint16_t* const scnt = slot_counts<false>(a, slot);
+    for (uint32_t ui = tid; ui < nU; ui += DUB) scnt[ui] = (uint16_t)(sm.upos[ui + 1] - sm.upos[ui]);
+  }
+}
+
+// Find the waiting unit's offset and write its keys from the staging slot,
+// then the offsets of its contexts.  OB keys per thread at a time: their
+// staged keys, then all their scope labels, are requested before the first
+// store, so the loads overlap.  The output bases are made uniform so that
+// every store addresses with a 32-bit offset, and the outputs, not read again
+// here, bypass the caches.
+template <bool WEIGHTED>
+__device__ inline void flush_unit(DUnitSmem& du, const DUnitArgs& a, uint32_t slot, uint32_t n_units) {
+  const int tid = threadIdx.x;
+  const DPend pd = du.pend[slot];
+  if (!pd.valid) return;
   if (tid < WAVE) {
-    const unsigned long long p = look_back(a.status, t, nU, &a.info->err);
+    const unsigned long long p = look_back(a.status, pd.t, pd.nU, &a.info->err);
     if (tid == 0) du.P = p;
   }
   __syncthreads();
-  P = du.P;
-  if constexpr (WEIGHTED) weighted_counts<uint32_t, IT>(sm, key, val, n_u, first, a.out.count + P);
-  // consecutive threads take consecutive keys from the compacted copy, OB
-  // keys per thread at a time: all their scope labels are requested before
-  // the first store, so the gathers overlap.  The output bases are made
-  // uniform so that every store addresses with a 32-bit offset, and the
-  // outputs, not read again here, bypass the caches.
-  constexpr int OB = 8;
+  const unsigned long long P = uniform_u64(du.P);
+  const uint32_t nU = pd.nU, dmin = pd.dmin;
+  const uint32_t* const skey = slot_keys<WEIGHTED>(a, pd.slot);
+  const auto scnt = slot_counts<WEIGHTED>(a, pd.slot);
+  const int pcb = bits_for(pd.dmax - dmin);
   const uint32_t pmask = (1u << pcb) - 1u;
-  const unsigned long long Pu = uniform_u64(P);
-  uint32_t* const octx = a.out.ctx + Pu;
-  uint64_t* const opc = a.out.pc + Pu;
-  uint8_t* const ostall = a.out.stall + Pu;
-  unsigned long long* const ocnt = a.out.count + Pu;
-  uint32_t* const oscope = a.out.scope + Pu;
+  uint32_t* const octx = a.out.ctx + P;
+  uint64_t* const opc = a.out.pc + P;
+  uint8_t* const ostall = a.out.stall + P;
+  unsigned long long* const ocnt = a.out.count + P;
+  uint32_t* const oscope = a.out.scope + P;
+  const uint32_t* const lctx = du.lctx[pd.slot];
   // the windows the unit's coordinates can fall in; up to WR of them are
   // held in registers (their first coordinates and pc bases), so a key's pc
   // needs no search
   constexpr int WR = 4;
   const uint32_t w0 = last_le(a.dd.d, a.dd.n_win, (uint64_t)dmin);
-  const uint32_t w1 = last_le(a.dd.d, a.dd.n_win, (uint64_t)du.red_max);
+  const uint32_t w1 = last_le(a.dd.d, a.dd.n_win, (uint64_t)pd.dmax);
   const bool few = w1 - w0 < (uint32_t)WR;
   uint32_t wfirst[WR];
   uint64_t wbase[WR];  // pc of coordinate 0 if the window extended down to it
@@ -894,14 +967,17 @@ __device__ __forceinline__ void sort_unit(DSmem& sm, DUnitSmem& du, const DUnitA
     wfirst[q] = q == 0 ? 0u : (w0 + (uint32_t)q <= w1 ? (uint32_t)a.dd.d[w] : 0xFFFFFFFFu);
     wbase[q] = a.dd.lo[w] - (a.dd.d[w] << a.dd.tz);
   }
+  constexpr int OB = 4;
   for (uint32_t u0 = 0; u0 < nU; u0 += OB * DUB) {
-    // every read stays inside the exchange plane (nU <= DUT = 2 * OB * DUB)
-    // and inside the scope table (a slot past nU reads coordinate dmin), so
-    // no read needs a branch
-    static_assert(DUT % (OB * DUB) == 0, "batches tile the unit");
+    using CT = typename std::conditional<WEIGHTED, unsigned long long, uint32_t>::type;
     uint32_t kk[OB], sc[OB];
+    CT cn[OB];
 #pragma unroll
-    for (int j = 0; j < OB; ++j) kk[j] = sm.buf[u0 + (uint32_t)j * DUB + tid];
+    for (int j = 0; j < OB; ++j) {
+      const uint32_t ui = u0 + (uint32_t)j * DUB + tid;
+      kk[j] = ui < nU ? skey[ui] : 0u;
+      cn[j] = ui < nU ? (CT)scnt[ui] : (CT)0;
+    }
 #pragma unroll
     for (int j = 0; j < OB; ++j) {
       const uint32_t ui = u0 + (uint32_t)j * DUB + tid;
@@ -922,16 +998,27 @@ __device__ __forceinline__ void sort_unit(DSmem& sm, DUnitSmem& du, const DUnitA
         } else {
           pc = from_dense(a.dd, D);
         }
-        __builtin_nontemporal_store(du.lctx[lc < nl ? lc : 0], &octx[ui]);
+        __builtin_nontemporal_store(lctx[lc < pd.nl ? lc : 0], &octx[ui]);
         __builtin_nontemporal_store(pc, &opc[ui]);
         __builtin_nontemporal_store((uint8_t)(kk[j] & 15u), &ostall[ui]);
-        if constexpr (!WEIGHTED)
-          __builtin_nontemporal_store((unsigned long long)((uint32_t)sm.upos[ui + 1] - (uint32_t)sm.upos[ui]),
-                                      &ocnt[ui]);
+        __builtin_nontemporal_store((unsigned long long)cn[j], &ocnt[ui]);
         __builtin_nontemporal_store(sc[j], &oscope[ui]);
       }
     }
   }
+  // context offsets: every context of the unit (empty ones included) starts
+  // after the keys of the non-empty contexts before it
+  const DUnit& d = pd.d;
+  if (d.kind == DU_PART) {
+    if (tid == 0 && d.s0 == a.cbase[d.cb]) a.out.ctx_off[d.cb] = P;
+  } else {
+    for (uint32_t i = tid; i < d.ce - d.cb; i += DUB) {
+      const uint32_t r = du.lrank[pd.slot][i];
+      a.out.ctx_off[d.cb + i] = P + du.loff[pd.slot][r < pd.nl ? r : pd.nl];
+    }
+  }
+  if (tid == 0 && pd.t == n_units - 1) close_units(a, P + nU);
+  __syncthreads();  // the slot's tables are rebuilt by the next unit but one
 }
 
 template <bool WEIGHTED>
@@ -943,6 +1030,8 @@ __global__ void __launch_bounds__(DUB, 4) k_d_units(DUnitArgs a) {
   a.dd = stage_dense(sm, a.dd);
   __syncthreads();
   const uint32_t n_units = a.info->n_units;
+  if (tid == 0) du.pend[0].valid = du.pend[1].valid = false;
+  uint32_t slot = 0;
   while (true) {
     if (tid == 0) du.t = atomicAdd(&a.info->ticket, 1u);
     __syncthreads();
@@ -950,7 +1039,9 @@ __global__ void __launch_bounds__(DUB, 4) k_d_units(DUnitArgs a) {
     if (t >= n_units) break;
     const DUnit d = a.units[t];
     if (d.kind == DU_HOT) {
-      hot_unit<WEIGHTED>(sm, du, a, d);
+      flush_unit<WEIGHTED>(du, a, slot ^ 1u, n_units);
+      if (tid == 0) du.pend[slot ^ 1u].valid = false;
+      hot_unit<WEIGHTED>(sm, du, a, d, n_units);
       __syncthreads();
       continue;
     }
@@ -966,7 +1057,7 @@ __global__ void __launch_bounds__(DUB, 4) k_d_units(DUnitArgs a) {
         du.nl = 1;
         du.lstart[0] = 0;
         du.lstart[1] = (uint32_t)n_u;
-        du.lctx[0] = d.cb;
+        du.lctx[slot][0] = d.cb;
       }
     } else {
       const uint32_t nc = d.ce - d.cb;  // <= DUB
@@ -975,10 +1066,10 @@ __global__ void __launch_bounds__(DUB, 4) k_d_units(DUnitArgs a) {
       uint32_t nl;
       const uint32_t r = block_excl_scan<DUB>(h > 0 ? 1u : 0u, du.tmp, &nl);
       if ((uint32_t)tid < nc) {
-        du.lrank[tid] = r;
+        du.lrank[slot][tid] = (uint8_t)min(r, (uint32_t)MAXC);
         if (h > 0 && r < (uint32_t)MAXC) {
           du.lstart[r] = a.cbase[c] - d.s0;
-          du.lctx[r] = c;
+          du.lctx[slot][r] = c;
         }
       }
       if (tid == 0) {
@@ -991,49 +1082,31 @@ __global__ void __launch_bounds__(DUB, 4) k_d_units(DUnitArgs a) {
     }
     __syncthreads();
     const uint32_t nl = min(du.nl, (uint32_t)MAXC);
-    unsigned long long P = 0;
-    uint32_t nU = 0;
+    uint32_t nU = 0, dmin = 0, dmax = 0;
     if (n_u == 0) {  // only empty contexts
-      if (tid < WAVE) {
-        const unsigned long long p = look_back(a.status, t, 0, &a.info->err);
-        if (tid == 0) du.P = p;
-      }
-      __syncthreads();
-      P = du.P;
+      if (tid == 0) publish_count(a.status, t, 0);
     } else if (n_u <= 4u * DUB) {
-      sort_unit<WEIGHTED, 4>(sm, du, a, d, rec, rw, (uint32_t)n_u, nl, t, P, nU);
+      sort_unit<WEIGHTED, 4>(sm, du, a, d, rec, rw, (uint32_t)n_u, nl, t, slot, nU, dmin, dmax);
     } else if (n_u <= 8u * DUB) {
-      sort_unit<WEIGHTED, 8>(sm, du, a, d, rec, rw, (uint32_t)n_u, nl, t, P, nU);
+      sort_unit<WEIGHTED, 8>(sm, du, a, d, rec, rw, (uint32_t)n_u, nl, t, slot, nU, dmin, dmax);
     } else {
-      sort_unit<WEIGHTED, DUI>(sm, du, a, d, rec, rw, (uint32_t)n_u, nl, t, P, nU);
+      sort_unit<WEIGHTED, DUI>(sm, du, a, d, rec, rw, (uint32_t)n_u, nl, t, slot, nU, dmin, dmax);
     }
-    // context offsets: every context of the unit (empty ones included) starts
-    // after the keys of the non-empty contexts before it
-    if (tid < MAXC + 1) {
-      // du.loff[l] = keys of local contexts before l (sm.ucnt holds keys per local context)
+    // keys before each local context (sm.ucnt holds keys per local context;
+    // wave 0 wrote it and reads it here)
+    if (tid < WAVE) {
       const uint32_t l = (uint32_t)tid;
       const uint32_t v = n_u > 0 && l < nl ? sm.ucnt[l] : 0u;
-      if (tid < WAVE) {
-        const uint32_t inc = wave_incl_scan(v);
-        du.loff[l] = inc - v;
-        if (l == WAVE - 1) du.loff[MAXC] = inc;
-      }
+      const uint32_t inc = wave_incl_scan(v);
+      du.loff[slot][l] = inc - v;
+      if (l == WAVE - 1) du.loff[slot][MAXC] = inc;
     }
-    __syncthreads();
-    if (part) {
-      if (tid == 0 && d.s0 == a.cbase[d.cb]) a.out.ctx_off[d.cb] = P;
-    } else {
-      for (uint32_t i = tid; i < d.ce - d.cb; i += DUB) {
-        const uint32_t r = du.lrank[i];
-        a.out.ctx_off[d.cb + i] = P + du.loff[r < nl ? r : nl];
-      }
-    }
-    if (tid == 0 && t == n_units - 1) {
-      a.out.ctx_off[a.C] = P + nU;
-      a.info->total_keys = P + nU;
-    }
-    __syncthreads();
+    if (tid == 0) du.pend[slot] = DPend{d, t, nU, dmin, dmax, nl, slot, true};
+    // the previous unit's offset is due by now: write it, and this unit waits
+    flush_unit<WEIGHTED>(du, a, slot ^ 1u, n_units);
+    slot ^= 1u;
   }
+  flush_unit<WEIGHTED>(du, a, slot ^ 1u, n_units);
 }
 
 }  // namespace
@@ -1169,6 +1242,11 @@ bool attribute_dense(hpa_ctx* ctx, const hpa_structure_map* map, const hpa_sampl
   // two resident workgroups per compute unit (each sort takes a little under
   // half of the LDS): one's memory phases overlap the other's sort
   const unsigned ugrid = (unsigned)std::max<uint64_t>(1, std::min<uint64_t>(max_units, 2ull * ctx->n_cu));
+  // two staging slots of DUT keys per workgroup
+  const uint64_t n_slots = 2ull * ugrid * DUT;
+  DBuf d_skey(ctx, n_slots * 4, s), d_scnt(ctx, n_slots * (weighted ? 8 : 2), s);
+  ua.stage_key = d_skey.as<uint32_t>();
+  ua.stage_cnt = d_scnt.p;
   tm.begin("units_dense");
   if (weighted) k_d_units<true><<<ugrid, DUB, 0, s>>>(ua);
   else k_d_units<false><<<ugrid, DUB, 0, s>>>(ua);

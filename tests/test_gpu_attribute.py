@@ -118,6 +118,20 @@ def test_attribute_small(hpa, hctx, seed, kw):
     assert_attribution_equal(a.numpy(), oa, f"small{seed}{kw}")
 
 
+@pytest.mark.parametrize("weighted", [False, True])
+def test_attribute_last_unit_counted(hpa, hctx, weighted):
+    # the last context is big and all its samples sit on one pc: its only
+    # part is a counted one, and it is the last unit, which closes the
+    # context offsets and reports the key count
+    w = tiny_random_case(7, n_funcs=5, n_samples=30_000, n_ctx=2, weighted=weighted)
+    w.ctx[:] = 1
+    w.ctx[:50] = 0
+    w.pc[50:] = np.max(w.pc[w.ctx == 1])
+    m, om, a, oa = _run(hpa, hctx, w)
+    assert a.n_keys == len(oa.ctx) > 0
+    assert_attribution_equal(a.numpy(), oa, "last unit counted")
+
+
 @pytest.mark.parametrize("seed,n_bins,weighted", [
     # one address window per binary: a unit whose keys fall in up to four
     # windows finds a key's window among registers, more windows take the
