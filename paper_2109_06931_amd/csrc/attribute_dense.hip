@@ -626,10 +626,10 @@ struct DUnitArgs {
   DInfo* info;
   unsigned long long* status;  // per unit: look-back word
   // per workgroup, two slots of DUT keys (one for the unit being sorted, one
-  // for the unit waiting to be written) and their counts (u16 unweighted,
-  // u64 weighted)
-  uint32_t* stage_key;
-  void* stage_cnt;
+  // for the unit waiting to be written): key | count << 32 unweighted; the
+  // key, with the u64 counts in stage_cnt, weighted
+  unsigned long long* stage_key;
+  unsigned long long* stage_cnt;
   OutDev out;
 };
 
@@ -642,6 +642,10 @@ struct DPend {
 
 struct DUnitSmem {
   DPend pend[2];                 // per slot: the unit staged there (kept in LDS, not registers)
+  // the unit claimed next and its descriptor (its context bases and records
+  // are fetched into LDS while the previous unit is written out)
+  DUnit d;
+  uint32_t cbpf[DUB + 1];        // context bases of the unit's contexts (small units), closed by the next
   uint32_t lstart[MAXC + 1];     // record offset of each non-empty local context, closed by n_u
   uint32_t lctx[2][MAXC];        // per slot: context id of each local context
   uint8_t lrank[2][DUB];         // per slot and context of the unit: non-empty contexts before it
@@ -717,6 +721,18 @@ __device__ inline unsigned long long uniform_u64(unsigned long long v) {
   const uint32_t hi = (uint32_t)__builtin_amdgcn_readfirstlane((int)(uint32_t)(v >> 32));
   return ((unsigned long long)hi << 32) | lo;
 }
+
+// Copy n words from global memory into LDS without passing through
+// registers (the LDS DMA of global_load_lds): wave w moves the 64-word chunks
+// w, w + 8, ...; lane l the word l of each.  The copy is complete once the
+// issuing waves have waited for their vector memory counter.
+__device__ inline void lds_fetch(uint32_t* lds_dst, const uint32_t* src, uint32_t n) {
+  const uint32_t l = (uint32_t)lane_id();
+  for (uint32_t c = (uint32_t)wave_id(); c * WAVE < n; c += DUB / WAVE)
+    if (c * WAVE + l < n) __builtin_amdgcn_global_load_lds(src + c * WAVE + l, lds_dst + c * WAVE, 4, 0, 0);
+}
+
+__device__ inline void wait_vmem() { __builtin_amdgcn_s_waitcnt(0x0F70); }  // vmcnt(0) only
 
 // The last unit closes the context offsets and reports the key count.
 __device__ inline void close_units(const DUnitArgs& a, unsigned long long end) {
@@ -836,14 +852,11 @@ __device__ inline void hot_unit(DSmem& sm, DUnitSmem& du, const DUnitArgs& a, co
   }
 }
 
-template <bool WEIGHTED>
-__device__ inline uint32_t* slot_keys(const DUnitArgs& a, uint32_t slot) {
+__device__ inline unsigned long long* slot_keys(const DUnitArgs& a, uint32_t slot) {
   return a.stage_key + ((uint64_t)blockIdx.x * 2 + slot) * DUT;
 }
-template <bool WEIGHTED>
-__device__ inline auto slot_counts(const DUnitArgs& a, uint32_t slot) {
-  using C = typename std::conditional<WEIGHTED, unsigned long long, uint16_t>::type;
-  return static_cast<C*>(a.stage_cnt) + ((uint64_t)blockIdx.x * 2 + slot) * DUT;
+__device__ inline unsigned long long* slot_counts(const DUnitArgs& a, uint32_t slot) {
+  return a.stage_cnt + ((uint64_t)blockIdx.x * 2 + slot) * DUT;
 }
 
 // Sort and reduce one SMALL or PART unit of n_u > 0 records with IT items
@@ -863,17 +876,24 @@ __device__ __forceinline__ void sort_unit(DSmem& sm, DUnitSmem& du, const DUnitA
   for (uint32_t l = 0; l < nl; ++l)
     for (uint32_t p = du.lstart[l] + tid; p < du.lstart[l + 1]; p += DUB) lctx_of[p] = (uint8_t)l;
   __syncthreads();
-  // gather: item i of thread t is record i * DUB + t of the unit (coalesced),
-  // kept packed as local context << 26 | D << 4 | stall (D < 2^22)
+  // gather: item i of thread t is record i * DUB + t of the unit, kept packed
+  // as local context << 26 | D << 4 | stall (D < 2^22).  Unweighted records
+  // were fetched into the exchange plane while the previous unit was written;
+  // weighted ones are read from global memory here (coalesced).
   uint32_t key[IT], val[IT];
   uint32_t dmin = 0xFFFFFFFFu, dmax = 0;
+  // (the thread index is hidden from the optimiser here, so that the slot
+  // indices are recomputed per unit instead of being hoisted out of the unit
+  // loop, where they would be held, or spilled, for the whole kernel)
+  uint32_t tq = (uint32_t)tid;
+  asm volatile("" : "+v"(tq));
 #pragma unroll
   for (int i = 0; i < IT; ++i) {
-    const uint32_t j = (uint32_t)i * DUB + tid;
     key[i] = 0;
     val[i] = 0;
+    const uint32_t j = (uint32_t)i * DUB + tq;
     if (j < n_u) {
-      uint32_t r = rec[d.s0 + j];
+      uint32_t r = WEIGHTED ? rec[d.s0 + j] : sm.buf[j];
       if (r == FAR_REC) r = 0;  // the call is redone by the general path
       key[i] = ((uint32_t)lctx_of[j] << 26) | (r & 0x3FFFFFFu);
       if constexpr (WEIGHTED) val[i] = rw[d.s0 + j];
@@ -900,7 +920,7 @@ __device__ __forceinline__ void sort_unit(DSmem& sm, DUnitSmem& du, const DUnitA
   const uint32_t empty = 1u << min(kbits, 31);
 #pragma unroll
   for (int i = 0; i < IT; ++i) {
-    const uint32_t j = (uint32_t)i * DUB + tid;
+    const uint32_t j = (uint32_t)i * DUB + tq;
     const uint32_t v = key[i];
     key[i] = j < n_u ? ((v >> 26) << (pcb + 4)) | ((((v >> 4) & 0x3FFFFFu) - dmin) << 4) | (v & 15u) : empty;
   }
@@ -914,24 +934,18 @@ __device__ __forceinline__ void sort_unit(DSmem& sm, DUnitSmem& du, const DUnitA
   if (tid == 0) publish_count(a.status, t, nU);
   // stage the compacted keys and their counts (consecutive threads take
   // consecutive keys)
-  uint32_t* const skey = slot_keys<WEIGHTED>(a, slot);
-  for (uint32_t ui = tid; ui < nU; ui += DUB) skey[ui] = sm.buf[ui];
+  unsigned long long* const skey = slot_keys(a, slot);
   if constexpr (WEIGHTED) {
-    weighted_counts<uint32_t, IT>(sm, key, val, n_u, first, slot_counts<true>(a, slot));
+    for (uint32_t ui = tid; ui < nU; ui += DUB) skey[ui] = sm.buf[ui];
+    weighted_counts<uint32_t, IT>(sm, key, val, n_u, first, slot_counts(a, slot));
   } else {
-    uint16_t* const scnt = slot_counts<false>(a, slot);
-    for (uint32_t ui = tid; ui < nU; ui += DUB) scnt[ui] = (uint16_t)(sm.upos[ui + 1] - sm.upos[ui]);
+    for (uint32_t ui = tid; ui < nU; ui += DUB)
+      skey[ui] = sm.buf[ui] | ((unsigned long long)(sm.upos[ui + 1] - sm.upos[ui]) << 32);
   }
 }
 
-// Find the waiting unit's offset and write its keys from the staging slot,
-// then the offsets of its contexts.  OB keys per thread at a time: their
-// staged keys, then all their scope labels, are requested before the first
-// store, so the loads overlap.  The output bases are made uniform so that
-// every store addresses with a 32-bit offset, and the outputs, not read again
-// here, bypass the caches.
-template <bool WEIGHTED>
-__device__ inline void flush_unit(DUnitSmem& du, const DUnitArgs& a, uint32_t slot, uint32_t n_units) {
+// Find the waiting unit's offset (the only wait on other workgroups) ...
+__device__ inline void flush_offset(DUnitSmem& du, const DUnitArgs& a, uint32_t slot) {
   const int tid = threadIdx.x;
   const DPend pd = du.pend[slot];
   if (!pd.valid) return;
@@ -940,10 +954,21 @@ __device__ inline void flush_unit(DUnitSmem& du, const DUnitArgs& a, uint32_t sl
     if (tid == 0) du.P = p;
   }
   __syncthreads();
+}
+
+// ... then write its keys from the staging slot (flush_offset has set
+// du.P), then the offsets of its contexts.  The output bases are made
+// uniform so that every store addresses with a 32-bit offset, and the
+// outputs, not read again here, bypass the caches.
+template <bool WEIGHTED>
+__device__ inline void flush_write(DUnitSmem& du, const DUnitArgs& a, uint32_t slot, uint32_t n_units) {
+  const int tid = threadIdx.x;
+  const DPend pd = du.pend[slot];
+  if (!pd.valid) return;
   const unsigned long long P = uniform_u64(du.P);
   const uint32_t nU = pd.nU, dmin = pd.dmin;
-  const uint32_t* const skey = slot_keys<WEIGHTED>(a, pd.slot);
-  const auto scnt = slot_counts<WEIGHTED>(a, pd.slot);
+  const unsigned long long* const skey = slot_keys(a, pd.slot);
+  const unsigned long long* const scnt = slot_counts(a, pd.slot);
   const int pcb = bits_for(pd.dmax - dmin);
   const uint32_t pmask = (1u << pcb) - 1u;
   uint32_t* const octx = a.out.ctx + P;
@@ -967,28 +992,40 @@ __device__ inline void flush_unit(DUnitSmem& du, const DUnitArgs& a, uint32_t sl
     wfirst[q] = q == 0 ? 0u : (w0 + (uint32_t)q <= w1 ? (uint32_t)a.dd.d[w] : 0xFFFFFFFFu);
     wbase[q] = a.dd.lo[w] - (a.dd.d[w] << a.dd.tz);
   }
-  constexpr int OB = 4;
+  // OB keys per thread per sweep: their staged keys and counts, then their
+  // scope labels, are all requested before the sweep's first store (a row j
+  // is read only when the unit has keys there, a condition the whole
+  // workgroup shares; a slot past nU reads coordinate dmin)
+  constexpr int OB = 8;
+  uint32_t tq = (uint32_t)tid;  // hidden from the optimiser, as in the gather
+  asm volatile("" : "+v"(tq));
   for (uint32_t u0 = 0; u0 < nU; u0 += OB * DUB) {
-    using CT = typename std::conditional<WEIGHTED, unsigned long long, uint32_t>::type;
-    uint32_t kk[OB], sc[OB];
-    CT cn[OB];
+    uint64_t sk[OB];
+    uint32_t sc[OB];
+    unsigned long long wc[WEIGHTED ? OB : 1];
 #pragma unroll
     for (int j = 0; j < OB; ++j) {
-      const uint32_t ui = u0 + (uint32_t)j * DUB + tid;
-      kk[j] = ui < nU ? skey[ui] : 0u;
-      cn[j] = ui < nU ? (CT)scnt[ui] : (CT)0;
+      sk[j] = 0;
+      if constexpr (WEIGHTED) wc[j] = 0;
+      if (u0 + (uint32_t)j * DUB < nU) {
+        sk[j] = skey[u0 + (uint32_t)j * DUB + tq];
+        if constexpr (WEIGHTED) wc[j] = scnt[u0 + (uint32_t)j * DUB + tq];
+      }
     }
 #pragma unroll
     for (int j = 0; j < OB; ++j) {
-      const uint32_t ui = u0 + (uint32_t)j * DUB + tid;
-      sc[j] = a.dd.scope_of[dmin + (ui < nU ? (kk[j] >> 4) & pmask : 0u)];
+      sc[j] = 0;
+      const uint32_t ui = u0 + (uint32_t)j * DUB + tq;
+      if (u0 + (uint32_t)j * DUB < nU)
+        sc[j] = a.dd.scope_of[dmin + (ui < nU ? ((uint32_t)sk[j] >> 4) & pmask : 0u)];
     }
 #pragma unroll
     for (int j = 0; j < OB; ++j) {
-      const uint32_t ui = u0 + (uint32_t)j * DUB + tid;
+      const uint32_t ui = u0 + (uint32_t)j * DUB + tq;
       if (ui < nU) {
-        const uint32_t lc = kk[j] >> (pcb + 4);
-        const uint32_t D = dmin + ((kk[j] >> 4) & pmask);
+        const uint32_t kk = (uint32_t)sk[j];
+        const uint32_t lc = kk >> (pcb + 4);
+        const uint32_t D = dmin + ((kk >> 4) & pmask);
         uint64_t pc;
         if (few) {
           uint64_t b = wbase[0];
@@ -1000,8 +1037,8 @@ __device__ inline void flush_unit(DUnitSmem& du, const DUnitArgs& a, uint32_t sl
         }
         __builtin_nontemporal_store(lctx[lc < pd.nl ? lc : 0], &octx[ui]);
         __builtin_nontemporal_store(pc, &opc[ui]);
-        __builtin_nontemporal_store((uint8_t)(kk[j] & 15u), &ostall[ui]);
-        __builtin_nontemporal_store((unsigned long long)cn[j], &ocnt[ui]);
+        __builtin_nontemporal_store((uint8_t)(kk & 15u), &ostall[ui]);
+        __builtin_nontemporal_store(WEIGHTED ? wc[j] : (unsigned long long)(sk[j] >> 32), &ocnt[ui]);
         __builtin_nontemporal_store(sc[j], &oscope[ui]);
       }
     }
@@ -1021,6 +1058,31 @@ __device__ inline void flush_unit(DUnitSmem& du, const DUnitArgs& a, uint32_t sl
   __syncthreads();  // the slot's tables are rebuilt by the next unit but one
 }
 
+// Fetch what unit `dn` (number tn) needs into LDS before its turn: the bases
+// of its contexts (small units) and, unweighted, its records (into the
+// exchange plane, which is free between one unit's staging and the next
+// unit's sort).  A counted part reads its records itself.
+template <bool WEIGHTED>
+__device__ inline void prefetch_unit(DSmem& sm, DUnitSmem& du, const DUnitArgs& a, const DUnit& dn, uint32_t tn,
+                                     uint32_t n_units) {
+  if (tn >= n_units || dn.kind == DU_HOT) return;
+  if (dn.kind != DU_PART) lds_fetch(du.cbpf, a.cbase + dn.cb, dn.ce - dn.cb + 1);
+  if constexpr (!WEIGHTED) lds_fetch(sm.buf, (dn.kind == DU_PART ? a.rec2 : a.rec) + dn.s0, dn.s1 - dn.s0);
+}
+
+// Claim the next unit and read its descriptor (into du.t, du.d).  Called
+// only when the workgroup has published the key count of every unit it
+// holds, so that no other workgroup can be kept waiting on a unit claimed
+// here while this one waits in turn.
+__device__ inline void claim_unit(DUnitSmem& du, const DUnitArgs& a, uint32_t n_units) {
+  if (threadIdx.x == 0) {
+    const uint32_t t = atomicAdd(&a.info->ticket, 1u);
+    du.t = t;
+    if (t < n_units) du.d = a.units[t];
+  }
+  __syncthreads();
+}
+
 template <bool WEIGHTED>
 __global__ void __launch_bounds__(DUB, 4) k_d_units(DUnitArgs a) {
   __shared__ DSmem sm;
@@ -1028,85 +1090,99 @@ __global__ void __launch_bounds__(DUB, 4) k_d_units(DUnitArgs a) {
   const int tid = threadIdx.x;
   // dense windows in LDS once
   a.dd = stage_dense(sm, a.dd);
-  __syncthreads();
   const uint32_t n_units = a.info->n_units;
   if (tid == 0) du.pend[0].valid = du.pend[1].valid = false;
+  claim_unit(du, a, n_units);
+  prefetch_unit<WEIGHTED>(sm, du, a, du.d, du.t, n_units);
+  wait_vmem();
+  __syncthreads();
   uint32_t slot = 0;
   while (true) {
-    if (tid == 0) du.t = atomicAdd(&a.info->ticket, 1u);
-    __syncthreads();
     const uint32_t t = du.t;
     if (t >= n_units) break;
-    const DUnit d = a.units[t];
+    const DUnit d = du.d;
     if (d.kind == DU_HOT) {
-      flush_unit<WEIGHTED>(du, a, slot ^ 1u, n_units);
+      flush_offset(du, a, slot ^ 1u);
+      flush_write<WEIGHTED>(du, a, slot ^ 1u, n_units);
       if (tid == 0) du.pend[slot ^ 1u].valid = false;
       hot_unit<WEIGHTED>(sm, du, a, d, n_units);
-      __syncthreads();
-      continue;
-    }
-    const bool part = d.kind == DU_PART;
-    const uint32_t* rec = part ? a.rec2 : a.rec;
-    const uint32_t* rw = part ? a.rw2 : a.rw;
-    const uint64_t n_u = d.s1 - d.s0;
-    // the unit's non-empty contexts and every context's rank among them
-    if (part) {
-      if (tid == 0) {
-        du.red_min = 0xFFFFFFFFu;
-        du.red_max = 0;
-        du.nl = 1;
-        du.lstart[0] = 0;
-        du.lstart[1] = (uint32_t)n_u;
-        du.lctx[slot][0] = d.cb;
-      }
+      __syncthreads();  // the counters are free for the next unit's records
+      claim_unit(du, a, n_units);
+      prefetch_unit<WEIGHTED>(sm, du, a, du.d, du.t, n_units);
     } else {
-      const uint32_t nc = d.ce - d.cb;  // <= DUB
-      const uint32_t c = d.cb + tid;
-      const uint32_t h = (uint32_t)tid < nc ? a.hist[c] : 0u;
-      uint32_t nl;
-      const uint32_t r = block_excl_scan<DUB>(h > 0 ? 1u : 0u, du.tmp, &nl);
-      if ((uint32_t)tid < nc) {
-        du.lrank[slot][tid] = (uint8_t)min(r, (uint32_t)MAXC);
-        if (h > 0 && r < (uint32_t)MAXC) {
-          du.lstart[r] = a.cbase[c] - d.s0;
-          du.lctx[slot][r] = c;
+      const bool part = d.kind == DU_PART;
+      const uint32_t* rec = part ? a.rec2 : a.rec;
+      const uint32_t* rw = part ? a.rw2 : a.rw;
+      const uint64_t n_u = d.s1 - d.s0;
+      // the unit's non-empty contexts and every context's rank among them
+      if (part) {
+        if (tid == 0) {
+          du.red_min = 0xFFFFFFFFu;
+          du.red_max = 0;
+          du.nl = 1;
+          du.lstart[0] = 0;
+          du.lstart[1] = (uint32_t)n_u;
+          du.lctx[slot][0] = d.cb;
+        }
+      } else {
+        const uint32_t nc = d.ce - d.cb;  // <= DUB
+        const uint32_t c = d.cb + tid;
+        const uint32_t cb0 = (uint32_t)tid < nc ? du.cbpf[tid] : 0u;
+        const uint32_t h = (uint32_t)tid < nc ? du.cbpf[tid + 1] - cb0 : 0u;
+        uint32_t nl;
+        const uint32_t r = block_excl_scan<DUB>(h > 0 ? 1u : 0u, du.tmp, &nl);
+        if ((uint32_t)tid < nc) {
+          du.lrank[slot][tid] = (uint8_t)min(r, (uint32_t)MAXC);
+          if (h > 0 && r < (uint32_t)MAXC) {
+            du.lstart[r] = cb0 - d.s0;
+            du.lctx[slot][r] = c;
+          }
+        }
+        if (tid == 0) {
+          du.red_min = 0xFFFFFFFFu;
+          du.red_max = 0;
+          du.nl = nl;
+          if (nl > (uint32_t)MAXC) atomicOr(&a.info->err, DERR_INTERNAL);
+          du.lstart[nl < (uint32_t)MAXC ? nl : MAXC] = (uint32_t)n_u;
         }
       }
-      if (tid == 0) {
-        du.red_min = 0xFFFFFFFFu;
-        du.red_max = 0;
-        du.nl = nl;
-        if (nl > (uint32_t)MAXC) atomicOr(&a.info->err, DERR_INTERNAL);
-        du.lstart[nl < (uint32_t)MAXC ? nl : MAXC] = (uint32_t)n_u;
+      __syncthreads();
+      const uint32_t nl = min(du.nl, (uint32_t)MAXC);
+      uint32_t nU = 0, dmin = 0, dmax = 0;
+      if (n_u == 0) {  // only empty contexts
+        if (tid == 0) publish_count(a.status, t, 0);
+      } else if (n_u <= 4u * DUB) {
+        sort_unit<WEIGHTED, 4>(sm, du, a, d, rec, rw, (uint32_t)n_u, nl, t, slot, nU, dmin, dmax);
+      } else if (n_u <= 8u * DUB) {
+        sort_unit<WEIGHTED, 8>(sm, du, a, d, rec, rw, (uint32_t)n_u, nl, t, slot, nU, dmin, dmax);
+      } else {
+        sort_unit<WEIGHTED, DUI>(sm, du, a, d, rec, rw, (uint32_t)n_u, nl, t, slot, nU, dmin, dmax);
       }
+      // keys before each local context (sm.ucnt holds keys per local
+      // context; wave 0 wrote it and reads it here)
+      if (tid < WAVE) {
+        const uint32_t l = (uint32_t)tid;
+        const uint32_t v = n_u > 0 && l < nl ? sm.ucnt[l] : 0u;
+        const uint32_t inc = wave_incl_scan(v);
+        du.loff[slot][l] = inc - v;
+        if (l == WAVE - 1) du.loff[slot][MAXC] = inc;
+      }
+      if (tid == 0) du.pend[slot] = DPend{d, t, nU, dmin, dmax, nl, slot, true};
+      // the previous unit's offset is due by now; once it is known, every
+      // unit held here has published its count: claim the next unit and
+      // fetch its data while the previous unit is written
+      flush_offset(du, a, slot ^ 1u);
+      claim_unit(du, a, n_units);
+      prefetch_unit<WEIGHTED>(sm, du, a, du.d, du.t, n_units);
+      flush_write<WEIGHTED>(du, a, slot ^ 1u, n_units);
+      slot ^= 1u;
     }
+    // the fetches have landed
+    wait_vmem();
     __syncthreads();
-    const uint32_t nl = min(du.nl, (uint32_t)MAXC);
-    uint32_t nU = 0, dmin = 0, dmax = 0;
-    if (n_u == 0) {  // only empty contexts
-      if (tid == 0) publish_count(a.status, t, 0);
-    } else if (n_u <= 4u * DUB) {
-      sort_unit<WEIGHTED, 4>(sm, du, a, d, rec, rw, (uint32_t)n_u, nl, t, slot, nU, dmin, dmax);
-    } else if (n_u <= 8u * DUB) {
-      sort_unit<WEIGHTED, 8>(sm, du, a, d, rec, rw, (uint32_t)n_u, nl, t, slot, nU, dmin, dmax);
-    } else {
-      sort_unit<WEIGHTED, DUI>(sm, du, a, d, rec, rw, (uint32_t)n_u, nl, t, slot, nU, dmin, dmax);
-    }
-    // keys before each local context (sm.ucnt holds keys per local context;
-    // wave 0 wrote it and reads it here)
-    if (tid < WAVE) {
-      const uint32_t l = (uint32_t)tid;
-      const uint32_t v = n_u > 0 && l < nl ? sm.ucnt[l] : 0u;
-      const uint32_t inc = wave_incl_scan(v);
-      du.loff[slot][l] = inc - v;
-      if (l == WAVE - 1) du.loff[slot][MAXC] = inc;
-    }
-    if (tid == 0) du.pend[slot] = DPend{d, t, nU, dmin, dmax, nl, slot, true};
-    // the previous unit's offset is due by now: write it, and this unit waits
-    flush_unit<WEIGHTED>(du, a, slot ^ 1u, n_units);
-    slot ^= 1u;
   }
-  flush_unit<WEIGHTED>(du, a, slot ^ 1u, n_units);
+  flush_offset(du, a, slot ^ 1u);
+  flush_write<WEIGHTED>(du, a, slot ^ 1u, n_units);
 }
 
 }  // namespace
@@ -1244,9 +1320,9 @@ bool attribute_dense(hpa_ctx* ctx, const hpa_structure_map* map, const hpa_sampl
   const unsigned ugrid = (unsigned)std::max<uint64_t>(1, std::min<uint64_t>(max_units, 2ull * ctx->n_cu));
   // two staging slots of DUT keys per workgroup
   const uint64_t n_slots = 2ull * ugrid * DUT;
-  DBuf d_skey(ctx, n_slots * 4, s), d_scnt(ctx, n_slots * (weighted ? 8 : 2), s);
-  ua.stage_key = d_skey.as<uint32_t>();
-  ua.stage_cnt = d_scnt.p;
+  DBuf d_skey(ctx, n_slots * 8, s), d_scnt(ctx, weighted ? n_slots * 8 : 0, s);
+  ua.stage_key = d_skey.as<unsigned long long>();
+  ua.stage_cnt = d_scnt.as<unsigned long long>();
   tm.begin("units_dense");
   if (weighted) k_d_units<true><<<ugrid, DUB, 0, s>>>(ua);
   else k_d_units<false><<<ugrid, DUB, 0, s>>>(ua);

@@ -88,12 +88,12 @@ struct SortSmemT {
     Run runs[RUNS ? RUN_CAP : 1];          // before the sort: the runs the workgroup gathers through
   };
   uint32_t doff[S::DOFF_WORDS];
-  unsigned long long pcmin[MAXC];
+  unsigned long long pcmin[RUNS ? MAXC : 1];  // (general units only)
   uint32_t ucnt[MAXC + 1];
   unsigned long long red_or, red_max, red_min, red_ref;
   unsigned long long scan_tmp[BLOCK_ / WAVE + 1];
   uint32_t scan_tmp32[BLOCK_ / WAVE + 1];
-  uint32_t last_hi[BLOCK_], last_lo[BLOCK_];
+  uint32_t last_hi[RUNS ? BLOCK_ : 1], last_lo[BLOCK_];  // high words for 64-bit keys (general units only)
   unsigned long long prefix;
   uint32_t unit, nU;
   uint64_t wlo[DENSE_MAX_WIN], whi[DENSE_MAX_WIN], wd[DENSE_MAX_WIN + 1];  // dense windows
@@ -358,7 +358,8 @@ __device__ inline void key_stats(SortSmem& sm, const Gathered<WEIGHTED>& g, uint
 // unique keys per local context.
 template <class K, class SM>
 __device__ inline K prev_last(const SM& sm, int tid) {
-  return tid == 0 ? (K)0 : (K)(((uint64_t)sm.last_hi[tid - 1] << 32) | sm.last_lo[tid - 1]);
+  if constexpr (sizeof(K) == 4) return tid == 0 ? (K)0 : (K)sm.last_lo[tid - 1];
+  else return tid == 0 ? (K)0 : (K)(((uint64_t)sm.last_hi[tid - 1] << 32) | sm.last_lo[tid - 1]);
 }
 
 template <class K, int IT = UITEMS, class SM>
@@ -367,7 +368,7 @@ __device__ inline uint32_t find_heads(SM& sm, const K (&key)[IT], uint64_t n_u, 
   constexpr int BLOCK = SM::BLOCK;
   const int tid = threadIdx.x;
   sm.last_lo[tid] = (uint32_t)key[IT - 1];
-  sm.last_hi[tid] = (uint32_t)((uint64_t)key[IT - 1] >> 32);
+  if constexpr (sizeof(K) == 8) sm.last_hi[tid] = (uint32_t)((uint64_t)key[IT - 1] >> 32);
   // sm.ucnt first holds each context's first unique index (NONE32: no keys)
   for (uint32_t l = tid; l <= n_cu; l += BLOCK) sm.ucnt[l] = NONE32;
   __syncthreads();
