@@ -87,22 +87,28 @@ struct WaveRuns {
   bool tail[DI];
 };
 
+// Exclusive max-scan over the 64 lanes with DPP moves only (identity -1):
+// row shifts by 1, 2, 4 and 8 scan each row of 16 lanes, row broadcasts of
+// lanes 15 and 31 carry the row maxima, and a whole-wave shift by one lane
+// makes the scan exclusive.  Every lane must be active.
 __device__ inline int wave_excl_max_i(int x) {
-  // exclusive max-scan over lanes (-1 for lane 0)
-  int r = __shfl_up(x, 1, WAVE);
-  if (lane_id() == 0) r = -1;
-#pragma unroll
-  for (int d = 1; d < WAVE; d <<= 1) {
-    const int o = __shfl_up(r, d, WAVE);
-    if (lane_id() >= d) r = max(r, o);
-  }
-  return r;
+  x = max(x, __builtin_amdgcn_update_dpp(-1, x, 0x111, 0xF, 0xF, false));  // row_shr:1
+  x = max(x, __builtin_amdgcn_update_dpp(-1, x, 0x112, 0xF, 0xF, false));  // row_shr:2
+  x = max(x, __builtin_amdgcn_update_dpp(-1, x, 0x114, 0xF, 0xF, false));  // row_shr:4
+  x = max(x, __builtin_amdgcn_update_dpp(-1, x, 0x118, 0xF, 0xF, false));  // row_shr:8
+  x = max(x, __builtin_amdgcn_update_dpp(-1, x, 0x142, 0xA, 0xF, false));  // row_bcast:15
+  x = max(x, __builtin_amdgcn_update_dpp(-1, x, 0x143, 0xC, 0xF, false));  // row_bcast:31
+  return __builtin_amdgcn_update_dpp(-1, x, 0x138, 0xF, 0xF, false);        // wave_shr:1
 }
 
+// Runs of equal contexts in a wave's DI * 64 consecutive samples (lane l
+// holds samples DI * l .. DI * l + DI - 1): each sample's run head and
+// whether it ends its run.  The neighbours' values come by whole-wave DPP
+// shifts (lane 0 and lane 63 see none).
 __device__ inline void wave_runs(WaveRuns& w) {
   const int lane = lane_id();
-  const uint32_t prev = __shfl_up(w.v[DI - 1], 1, WAVE);
-  const uint32_t next = __shfl_down(w.v[0], 1, WAVE);
+  const uint32_t prev = (uint32_t)__builtin_amdgcn_update_dpp(0, (int)w.v[DI - 1], 0x138, 0xF, 0xF, false);  // wave_shr:1
+  const uint32_t next = (uint32_t)__builtin_amdgcn_update_dpp(0, (int)w.v[0], 0x130, 0xF, 0xF, false);       // wave_shl:1
   int hp = -1;
 #pragma unroll
   for (int j = 0; j < DI; ++j) {
@@ -262,33 +268,47 @@ k_d_scatter(const uint64_t* __restrict__ pc, const uint32_t* __restrict__ ctx, c
   const uint64_t steps = (n + DCH - 1) / DCH;
   unsigned int far = 0;
   bool bad_stall = false, bad_pos = false;
-  for (uint64_t k = (uint64_t)blockIdx.x * (DB / WAVE) + wave_id(); k < steps; k += nw) {
-    const uint64_t p0 = k * DCH + (uint64_t)lane_id() * DI;
-    WaveRuns w;
-    load_ctx4<VEC>(ctx, n, p0, w.v);
-    // the other fields' loads go out before the run analysis
+  // a wave step's fields; the next step's loads are issued before this
+  // step's reservations, so their latencies overlap
+  struct StepIn {
+    uint32_t v[DI];
     uint64_t q[DI];
-    uint32_t st[DI], wt[DI];
+    uint32_t s4;
+    uint32_t wt[WEIGHTED ? DI : 1];
+  };
+  auto load_step = [&](uint64_t k, StepIn& in) {
+    const uint64_t p0 = k * DCH + (uint64_t)lane_id() * DI;
+    load_ctx4<VEC>(ctx, n, p0, in.v);
     if (VEC && p0 + DI <= n) {
       const ulonglong2 a = *reinterpret_cast<const ulonglong2*>(pc + p0);
       const ulonglong2 b = *reinterpret_cast<const ulonglong2*>(pc + p0 + 2);
-      q[0] = a.x; q[1] = a.y; q[2] = b.x; q[3] = b.y;
-      const uint32_t s4 = *reinterpret_cast<const uint32_t*>(stall + p0);
-#pragma unroll
-      for (int j = 0; j < DI; ++j) st[j] = (s4 >> (8 * j)) & 0xFFu;
+      in.q[0] = a.x; in.q[1] = a.y; in.q[2] = b.x; in.q[3] = b.y;
+      in.s4 = *reinterpret_cast<const uint32_t*>(stall + p0);
       if constexpr (WEIGHTED) {
         const uint4 ww = *reinterpret_cast<const uint4*>(weight + p0);
-        wt[0] = ww.x; wt[1] = ww.y; wt[2] = ww.z; wt[3] = ww.w;
+        in.wt[0] = ww.x; in.wt[1] = ww.y; in.wt[2] = ww.z; in.wt[3] = ww.w;
       }
     } else {
+      in.s4 = 0;
 #pragma unroll
       for (int j = 0; j < DI; ++j) {
         const bool ok = p0 + j < n;
-        q[j] = ok ? pc[p0 + j] : 0ull;
-        st[j] = ok ? stall[p0 + j] : 0u;
-        if constexpr (WEIGHTED) wt[j] = ok ? weight[p0 + j] : 0u;
+        in.q[j] = ok ? pc[p0 + j] : 0ull;
+        in.s4 |= (ok ? (uint32_t)stall[p0 + j] : 0u) << (8 * j);
+        if constexpr (WEIGHTED) in.wt[j] = ok ? weight[p0 + j] : 0u;
       }
     }
+  };
+  uint64_t k = (uint64_t)blockIdx.x * (DB / WAVE) + wave_id();
+  StepIn cur;
+  if (k < steps) load_step(k, cur);
+  for (; k < steps; k += nw) {
+    StepIn nxt;
+    if (k + nw < steps) load_step(k + nw, nxt);
+    const uint64_t p0 = k * DCH + (uint64_t)lane_id() * DI;
+    WaveRuns w;
+#pragma unroll
+    for (int j = 0; j < DI; ++j) w.v[j] = cur.v[j];
     wave_runs(w);
     // one reservation per run, by its last position; its base is left in LDS
     // at the run's head for the other positions of the run
@@ -314,22 +334,24 @@ k_d_scatter(const uint64_t* __restrict__ pc, const uint32_t* __restrict__ ctx, c
       const uint32_t b = sb[w.head[j]];
       if (b == NONE32) continue;
       const uint32_t pos = b + (uint32_t)(lane_id() * DI + j - w.head[j]);
+      const uint32_t stj = (cur.s4 >> (8 * j)) & 0xFFu;
       uint32_t r;
       uint64_t D;
-      if (st[j] >= NS) {
+      if (stj >= NS) {
         bad_stall = true;
         r = 0;
-      } else if (to_dense(t, q[j], D)) {
-        r = ((uint32_t)D << 4) | st[j];
+      } else if (to_dense(t, cur.q[j], D)) {
+        r = ((uint32_t)D << 4) | stj;
       } else {
         r = FAR_REC;
         ++far;
       }
       rec[pos] = r;
-      if constexpr (WEIGHTED) rw[pos] = wt[j];
+      if constexpr (WEIGHTED) rw[pos] = cur.wt[j];
     }
     // the LDS bases of this step are read before the next step writes them
     __builtin_amdgcn_wave_barrier();
+    cur = nxt;
   }
   far = wave_sum(far);
   if (lane_id() == 0) {
@@ -1316,8 +1338,11 @@ bool attribute_dense(hpa_ctx* ctx, const hpa_structure_map* map, const hpa_sampl
   ua.out = OutDev{A->ctx_id.as<uint32_t>(), A->pc.as<uint64_t>(), A->stall.as<uint8_t>(),
                   A->count.as<unsigned long long>(), A->scope.as<uint32_t>(), A->ctx_offsets.as<uint64_t>()};
   // two resident workgroups per compute unit (each sort takes a little under
-  // half of the LDS): one's memory phases overlap the other's sort
-  const unsigned ugrid = (unsigned)std::max<uint64_t>(1, std::min<uint64_t>(max_units, 2ull * ctx->n_cu));
+  // half of the LDS): one's memory phases overlap the other's sort.  Small
+  // inputs take fewer workgroups (about one per DUT / 2 samples), which also
+  // bounds the staging slots below.
+  const unsigned ugrid = (unsigned)std::max<uint64_t>(
+      1, std::min<uint64_t>({max_units, 2ull * ctx->n_cu, (n + DUT / 2 - 1) / (DUT / 2)}));
   // two staging slots of DUT keys per workgroup
   const uint64_t n_slots = 2ull * ugrid * DUT;
   DBuf d_skey(ctx, n_slots * 8, s), d_scnt(ctx, weighted ? n_slots * 8 : 0, s);
