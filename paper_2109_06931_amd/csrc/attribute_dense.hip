@@ -649,8 +649,10 @@ struct DUnitArgs {
   unsigned long long* status;  // per unit: look-back word
   // per workgroup, two slots of DUT keys (one for the unit being sorted, one
   // for the unit waiting to be written): key | count << 32 unweighted; the
-  // key, with the u64 counts in stage_cnt, weighted
-  unsigned long long* stage_key;
+  // keys, with their counts as u16 (a unit's count is at most DUT) or, with
+  // weights, as u64
+  uint32_t* stage_key;
+  uint16_t* stage_c16;
   unsigned long long* stage_cnt;
   OutDev out;
 };
@@ -749,7 +751,8 @@ __device__ inline unsigned long long uniform_u64(unsigned long long v) {
 // w, w + 8, ...; lane l the word l of each.  The copy is complete once the
 // issuing waves have waited for their vector memory counter.
 __device__ inline void lds_fetch(uint32_t* lds_dst, const uint32_t* src, uint32_t n) {
-  const uint32_t l = (uint32_t)lane_id();
+  uint32_t l = (uint32_t)lane_id();
+  asm volatile("" : "+v"(l));  // keep the per-lane addresses out of the caller's loop invariants
   for (uint32_t c = (uint32_t)wave_id(); c * WAVE < n; c += DUB / WAVE)
     if (c * WAVE + l < n) __builtin_amdgcn_global_load_lds(src + c * WAVE + l, lds_dst + c * WAVE, 4, 0, 0);
 }
@@ -874,12 +877,7 @@ __device__ inline void hot_unit(DSmem& sm, DUnitSmem& du, const DUnitArgs& a, co
   }
 }
 
-__device__ inline unsigned long long* slot_keys(const DUnitArgs& a, uint32_t slot) {
-  return a.stage_key + ((uint64_t)blockIdx.x * 2 + slot) * DUT;
-}
-__device__ inline unsigned long long* slot_counts(const DUnitArgs& a, uint32_t slot) {
-  return a.stage_cnt + ((uint64_t)blockIdx.x * 2 + slot) * DUT;
-}
+__device__ inline uint64_t slot_base(uint32_t slot) { return ((uint64_t)blockIdx.x * 2 + slot) * DUT; }
 
 // Sort and reduce one SMALL or PART unit of n_u > 0 records with IT items
 // per thread (the least that holds it: a sort pass costs in proportion to the
@@ -956,13 +954,13 @@ __device__ __forceinline__ void sort_unit(DSmem& sm, DUnitSmem& du, const DUnitA
   if (tid == 0) publish_count(a.status, t, nU);
   // stage the compacted keys and their counts (consecutive threads take
   // consecutive keys)
-  unsigned long long* const skey = slot_keys(a, slot);
+  uint32_t* const skey = a.stage_key + slot_base(slot);
+  for (uint32_t ui = tid; ui < nU; ui += DUB) skey[ui] = sm.buf[ui];
   if constexpr (WEIGHTED) {
-    for (uint32_t ui = tid; ui < nU; ui += DUB) skey[ui] = sm.buf[ui];
-    weighted_counts<uint32_t, IT>(sm, key, val, n_u, first, slot_counts(a, slot));
+    weighted_counts<uint32_t, IT>(sm, key, val, n_u, first, a.stage_cnt + slot_base(slot));
   } else {
-    for (uint32_t ui = tid; ui < nU; ui += DUB)
-      skey[ui] = sm.buf[ui] | ((unsigned long long)(sm.upos[ui + 1] - sm.upos[ui]) << 32);
+    uint16_t* const sc16 = a.stage_c16 + slot_base(slot);
+    for (uint32_t ui = tid; ui < nU; ui += DUB) sc16[ui] = (uint16_t)(sm.upos[ui + 1] - sm.upos[ui]);
   }
 }
 
@@ -989,8 +987,9 @@ __device__ inline void flush_write(DUnitSmem& du, const DUnitArgs& a, uint32_t s
   if (!pd.valid) return;
   const unsigned long long P = uniform_u64(du.P);
   const uint32_t nU = pd.nU, dmin = pd.dmin;
-  const unsigned long long* const skey = slot_keys(a, pd.slot);
-  const unsigned long long* const scnt = slot_counts(a, pd.slot);
+  const uint32_t* const skey = a.stage_key + slot_base(pd.slot);
+  const uint16_t* const sc16 = a.stage_c16 + slot_base(pd.slot);
+  const unsigned long long* const scnt = a.stage_cnt + slot_base(pd.slot);
   const int pcb = bits_for(pd.dmax - dmin);
   const uint32_t pmask = (1u << pcb) - 1u;
   uint32_t* const octx = a.out.ctx + P;
@@ -1022,16 +1021,18 @@ __device__ inline void flush_write(DUnitSmem& du, const DUnitArgs& a, uint32_t s
   uint32_t tq = (uint32_t)tid;  // hidden from the optimiser, as in the gather
   asm volatile("" : "+v"(tq));
   for (uint32_t u0 = 0; u0 < nU; u0 += OB * DUB) {
-    uint64_t sk[OB];
+    uint32_t sk[OB];
     uint32_t sc[OB];
-    unsigned long long wc[WEIGHTED ? OB : 1];
+    typename std::conditional<WEIGHTED, unsigned long long, uint32_t>::type wc[OB];
 #pragma unroll
     for (int j = 0; j < OB; ++j) {
       sk[j] = 0;
-      if constexpr (WEIGHTED) wc[j] = 0;
+      wc[j] = 0;
       if (u0 + (uint32_t)j * DUB < nU) {
-        sk[j] = skey[u0 + (uint32_t)j * DUB + tq];
-        if constexpr (WEIGHTED) wc[j] = scnt[u0 + (uint32_t)j * DUB + tq];
+        const uint32_t ui = u0 + (uint32_t)j * DUB + tq;
+        sk[j] = skey[ui];
+        if constexpr (WEIGHTED) wc[j] = scnt[ui];
+        else wc[j] = sc16[ui];
       }
     }
 #pragma unroll
@@ -1039,13 +1040,13 @@ __device__ inline void flush_write(DUnitSmem& du, const DUnitArgs& a, uint32_t s
       sc[j] = 0;
       const uint32_t ui = u0 + (uint32_t)j * DUB + tq;
       if (u0 + (uint32_t)j * DUB < nU)
-        sc[j] = a.dd.scope_of[dmin + (ui < nU ? ((uint32_t)sk[j] >> 4) & pmask : 0u)];
+        sc[j] = a.dd.scope_of[dmin + (ui < nU ? (sk[j] >> 4) & pmask : 0u)];
     }
 #pragma unroll
     for (int j = 0; j < OB; ++j) {
       const uint32_t ui = u0 + (uint32_t)j * DUB + tq;
       if (ui < nU) {
-        const uint32_t kk = (uint32_t)sk[j];
+        const uint32_t kk = sk[j];
         const uint32_t lc = kk >> (pcb + 4);
         const uint32_t D = dmin + ((kk >> 4) & pmask);
         uint64_t pc;
@@ -1060,7 +1061,7 @@ __device__ inline void flush_write(DUnitSmem& du, const DUnitArgs& a, uint32_t s
         __builtin_nontemporal_store(lctx[lc < pd.nl ? lc : 0], &octx[ui]);
         __builtin_nontemporal_store(pc, &opc[ui]);
         __builtin_nontemporal_store((uint8_t)(kk & 15u), &ostall[ui]);
-        __builtin_nontemporal_store(WEIGHTED ? wc[j] : (unsigned long long)(sk[j] >> 32), &ocnt[ui]);
+        __builtin_nontemporal_store((unsigned long long)wc[j], &ocnt[ui]);
         __builtin_nontemporal_store(sc[j], &oscope[ui]);
       }
     }
@@ -1345,9 +1346,10 @@ bool attribute_dense(hpa_ctx* ctx, const hpa_structure_map* map, const hpa_sampl
       1, std::min<uint64_t>({max_units, 2ull * ctx->n_cu, (n + DUT / 2 - 1) / (DUT / 2)}));
   // two staging slots of DUT keys per workgroup
   const uint64_t n_slots = 2ull * ugrid * DUT;
-  DBuf d_skey(ctx, n_slots * 8, s), d_scnt(ctx, weighted ? n_slots * 8 : 0, s);
-  ua.stage_key = d_skey.as<unsigned long long>();
-  ua.stage_cnt = d_scnt.as<unsigned long long>();
+  DBuf d_skey(ctx, n_slots * 4, s), d_scnt(ctx, n_slots * (weighted ? 8 : 2), s);
+  ua.stage_key = d_skey.as<uint32_t>();
+  ua.stage_c16 = weighted ? nullptr : d_scnt.as<uint16_t>();
+  ua.stage_cnt = weighted ? d_scnt.as<unsigned long long>() : nullptr;
   tm.begin("units_dense");
   if (weighted) k_d_units<true><<<ugrid, DUB, 0, s>>>(ua);
   else k_d_units<false><<<ugrid, DUB, 0, s>>>(ua);

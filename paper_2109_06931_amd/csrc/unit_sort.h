@@ -409,7 +409,10 @@ __device__ inline uint32_t find_heads(SM& sm, const K (&key)[IT], uint64_t n_u, 
   // converts entry l, and only thread l reads it afterwards
   static_assert(MAXC <= WAVE, "one lane per local context");
   if (tid < WAVE) {
-    const uint32_t l = (uint32_t)tid;
+    // (the lane index is hidden from the optimiser so that the shuffle
+    // sources are computed here, not hoisted out of a caller's loop)
+    uint32_t l = (uint32_t)tid;
+    asm volatile("" : "+v"(l));
     const uint32_t st = l < n_cu ? sm.ucnt[l] : NONE32;
     uint32_t suf = st;
     for (uint32_t d = 1; d < (uint32_t)WAVE; d <<= 1) {
