@@ -56,21 +56,70 @@ __device__ __forceinline__ void features(const Norm& nm, uint64_t q, float& x0, 
   x1 = (float)(t & ((1ull << nm.sh) - 1ull)) * nm.inv_lo;
 }
 
-// The root's output for one input, in a fixed order of fused multiply-adds.
-// Every kernel that routes a key calls this one function, so training-time
-// windows and lookups see bit-identical values.
-__device__ __forceinline__ float root_forward(const float* __restrict__ P, float x0, float x1) {
-  float h1[NH];
-#pragma unroll
-  for (int k = 0; k < NH; ++k) h1[k] = fmaxf(fmaf(P[P_W1 + 2 * k + 1], x1, fmaf(P[P_W1 + 2 * k], x0, P[P_B1 + k])), 0.f);
-  float y = P[P_B3];
-  for (int j = 0; j < NH; ++j) {
-    float a = P[P_B2 + j];
-#pragma unroll
-    for (int k = 0; k < NH; ++k) a = fmaf(P[P_W2 + NH * j + k], h1[k], a);
-    y = fmaf(P[P_W3 + j], fmaxf(a, 0.f), y);
+// The root's parameters, staged in LDS by every kernel that routes keys: the
+// first layer as (w_x0, w_x1, bias, 0) per hidden unit, the second layer
+// transposed (k-major, so that the 32 lanes reading one input k for 32
+// outputs hit 32 banks), then its biases, the output weights and bias.
+struct RootLds {
+  float4 w1b1[NH];
+  float w2t[NH * NH];  // w2t[k * NH + j] = W2[j][k]
+  float b2[NH], w3[NH];
+  float b3;
+};
+
+__device__ inline void stage_root(RootLds& R, const float* __restrict__ P) {
+  for (int k = threadIdx.x; k < NH; k += blockDim.x)
+    R.w1b1[k] = make_float4(P[P_W1 + 2 * k], P[P_W1 + 2 * k + 1], P[P_B1 + k], 0.f);
+  for (int i = threadIdx.x; i < NH * NH; i += blockDim.x) R.w2t[(i % NH) * NH + i / NH] = P[P_W2 + i];
+  for (int k = threadIdx.x; k < NH; k += blockDim.x) {
+    R.b2[k] = P[P_B2 + k];
+    R.w3[k] = P[P_W3 + k];
   }
-  return y;
+  if (threadIdx.x == 0) R.b3 = P[P_B3];
+}
+
+typedef float mfma_acc16 __attribute__((ext_vector_type(16)));
+
+// The root's output for the 64 keys of a wave (one per lane), on the matrix
+// cores: the 64 x 64 hidden layer is a product of W2 with the first layer's
+// outputs for 32 keys at a time (v_mfma_f32_32x32x2f32, two 32-row tiles, K
+// in steps of 2).  In a step lane l supplies W2[row l % 32][k] and the first
+// layer's unit k for key l % 32, with k = 2s + l / 32; after the last step
+// its register r holds hidden row 8 (r / 4) + 4 (l / 32) + r % 4 of that key.
+// The output layer then sums the lane's rows, and the two lanes of a key add
+// their halves.  Every lane of the wave must call it.  Every kernel that
+// routes a key calls this one function, so training-time windows and lookups
+// see bit-identical values.
+__device__ inline float route_wave(const RootLds& R, float x0, float x1) {
+  const int l = lane_id(), h = l >> 5, n = l & 31;
+  float y_own = 0.f;
+#pragma unroll 1
+  for (int g = 0; g < 2; ++g) {
+    // the keys of lanes 32g .. 32g + 31, at both lane halves
+    const float gx0 = __shfl(x0, g * 32 + n, WAVE), gx1 = __shfl(x1, g * 32 + n, WAVE);
+    float part = 0.f;
+#pragma unroll 1
+    for (int tile = 0; tile < 2; ++tile) {
+      mfma_acc16 acc = {};
+#pragma unroll 2
+      for (int s = 0; s < NH / 2; ++s) {
+        const int k = 2 * s + h;
+        const float4 wb = R.w1b1[k];
+        const float b = fmaxf(fmaf(wb.y, gx1, fmaf(wb.x, gx0, wb.z)), 0.f);
+        acc = __builtin_amdgcn_mfma_f32_32x32x2f32(R.w2t[k * NH + 32 * tile + n], b, acc, 0, 0, 0);
+      }
+#pragma unroll
+      for (int r = 0; r < 16; ++r) {
+        const int m = 32 * tile + 8 * (r / 4) + 4 * h + (r % 4);
+        part = fmaf(R.w3[m], fmaxf(acc[r] + R.b2[m], 0.f), part);
+      }
+    }
+    const float other = __shfl_xor(part, 32, WAVE);
+    // the same sum in both lanes of a key: the lower half's part first
+    const float y = (h == 0 ? part + other : other + part) + R.b3;
+    if (h == g) y_own = y;
+  }
+  return y_own;
 }
 
 __device__ __forceinline__ uint32_t leaf_of_output(float y, uint32_t n_leaf) {
@@ -264,15 +313,20 @@ __global__ void k_make_rows(const uint64_t* __restrict__ start, uint64_t M, uint
 // ---------------------------------------------------------------------------
 constexpr int RB = 256;
 
-__global__ void __launch_bounds__(RB)
+__global__ void __launch_bounds__(RB, 4)
 k_route(const uint64_t* __restrict__ start, uint64_t M, Norm nm, const float* __restrict__ P, uint32_t n_leaf,
         uint16_t* __restrict__ leaf_of, unsigned long long* __restrict__ base) {
+  __shared__ RootLds R;
+  stage_root(R, P);
+  __syncthreads();
   const uint64_t i = (uint64_t)blockIdx.x * RB + threadIdx.x;
-  if (i >= M) return;
-  const uint64_t q = start[i];
+  // every lane routes (the wave computes together); lanes past M route the
+  // last start and write nothing
+  const uint64_t q = start[i < M ? i : M - 1];
   float x0, x1;
   features(nm, q, x0, x1);
-  const uint32_t L = leaf_of_output(root_forward(P, x0, x1), n_leaf);
+  const uint32_t L = leaf_of_output(route_wave(R, x0, x1), n_leaf);
+  if (i >= M) return;
   leaf_of[i] = (uint16_t)L;
   atomicMin(&base[L], (unsigned long long)q);
 }
@@ -315,28 +369,34 @@ __global__ void k_leaf_fit(const double* __restrict__ sums, uint32_t n_leaf, flo
 // i - 1): route, predict, and widen its leaf's window to cover the rank.
 // Misses larger than cap are left uncovered (counted): their queries take the
 // fallback search.
-__global__ void __launch_bounds__(RB)
+__global__ void __launch_bounds__(RB, 4)
 k_leaf_windows(const uint64_t* __restrict__ start, uint64_t M, Norm nm, const float* __restrict__ P, uint32_t n_leaf,
                const uint16_t* __restrict__ leaf_of, const unsigned long long* __restrict__ base,
                const float* __restrict__ slope, const float* __restrict__ icpt, uint32_t cap,
                unsigned int* __restrict__ elo, unsigned int* __restrict__ ehi,
                unsigned long long* __restrict__ uncovered) {
+  __shared__ RootLds R;
+  stage_root(R, P);
+  __syncthreads();
   const uint64_t i = (uint64_t)blockIdx.x * RB + threadIdx.x;
   unsigned long long miss = 0;
+  // the key just below each start is routed by the whole wave (lanes without
+  // one route a stand-in and ignore it)
+  uint32_t L1;
+  {
+    const uint64_t iq = i < M ? i : M - 1;
+    const uint64_t q1 = start[iq] - (iq > 0 ? 1 : 0);
+    float x0, x1;
+    features(nm, q1, x0, x1);
+    L1 = leaf_of_output(route_wave(R, x0, x1), n_leaf);
+  }
   if (i < M) {
     const uint64_t* bs = reinterpret_cast<const uint64_t*>(base);
     for (int k = 0; k < 2; ++k) {
       if (k == 1 && i == 0) break;
       const uint64_t q = k == 0 ? start[i] : start[i] - 1;
       const uint64_t rank = k == 0 ? i : i - 1;
-      uint32_t L;
-      if (k == 0) {
-        L = leaf_of[i];
-      } else {
-        float x0, x1;
-        features(nm, q, x0, x1);
-        L = leaf_of_output(root_forward(P, x0, x1), n_leaf);
-      }
+      const uint32_t L = k == 0 ? (uint32_t)leaf_of[i] : L1;
       const uint64_t pred = leaf_predict(bs, slope, icpt, L, q, M);
       if (pred >= rank) {
         const uint64_t d = pred - rank;
@@ -356,10 +416,10 @@ k_leaf_windows(const uint64_t* __restrict__ start, uint64_t M, Norm nm, const fl
 // ---------------------------------------------------------------------------
 // lookup
 // ---------------------------------------------------------------------------
-constexpr int LB = 256;
+constexpr int LB = 512;
 
 template <bool STATS>
-__global__ void __launch_bounds__(LB)
+__global__ void __launch_bounds__(LB, 3)
 k_lookup_learned(const uint64_t* __restrict__ start, const uint64_t* __restrict__ end, uint64_t M, Norm nm,
                  const float* __restrict__ P, uint32_t n_leaf, const uint64_t* __restrict__ lbase,
                  const float* __restrict__ slope, const float* __restrict__ icpt, const uint32_t* __restrict__ elo,
@@ -367,22 +427,30 @@ k_lookup_learned(const uint64_t* __restrict__ start, const uint64_t* __restrict_
                  const uint64_t* __restrict__ pc, uint64_t n, uint32_t* __restrict__ out,
                  unsigned long long* __restrict__ stats) {
   __shared__ uint64_t s_top[4096];
+  __shared__ RootLds R;
   for (uint32_t i = threadIdx.x; i < top_n; i += LB) s_top[i] = top[i];
+  stage_root(R, P);
   __syncthreads();
   const uint64_t s_last = start[M - 1];
   unsigned long long probes = 0, fallbacks = 0;
   const uint64_t stride = (uint64_t)gridDim.x * LB;
-  for (uint64_t t = (uint64_t)blockIdx.x * LB + threadIdx.x; t < n; t += stride) {
-    const uint64_t q = pc[t];
+  // whole waves go round the loop together, since every lane routes
+  const uint64_t t0 = (uint64_t)blockIdx.x * LB + threadIdx.x - (uint64_t)lane_id();
+  for (uint64_t tw = t0; tw < n; tw += stride) {
+    const uint64_t t = tw + (uint64_t)lane_id();
+    const bool live = t < n;
+    const uint64_t q = pc[live ? t : n - 1];
+    float x0, x1;
+    features(nm, q < nm.s0 ? nm.s0 : q, x0, x1);
+    const float y = route_wave(R, x0, x1);
+    if (!live) continue;
     uint64_t ans;  // last i with start[i] <= q, or M when q < start[0]
     if (q < nm.s0) {
       ans = M;
     } else if (q >= s_last) {
       ans = M - 1;
     } else {
-      float x0, x1;
-      features(nm, q, x0, x1);
-      const uint32_t L = leaf_of_output(root_forward(P, x0, x1), n_leaf);
+      const uint32_t L = leaf_of_output(y, n_leaf);
       const uint64_t pred = leaf_predict(lbase, slope, icpt, L, q, M);
       const uint64_t lo0 = pred > elo[L] ? pred - elo[L] : 0;
       uint64_t hi0 = pred + ehi[L];
