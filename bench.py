@@ -345,7 +345,7 @@ def section_serve(hpa, ctx, seconds):
         pool.append(hpa.sample_buffer(w.pc[lo:lo + n], w.ctx[lo:lo + n], w.stall[lo:lo + n]))
         lo += n
     sizes = np.array([b.n_samples * 13 for b in pool], dtype=np.float64)
-    srv = hpa.Server(ctx, m, n_profiles=512, n_ctx=w.n_ctx, table_slots=1 << 16, n_slots=6,
+    srv = hpa.Server(ctx, m, n_profiles=512, n_ctx=w.n_ctx, table_slots=1 << 22, n_slots=6,
                      max_batch_bytes=64 << 20, hbm_budget=200 * 10 ** 9)
     rows = []
     for rate_gbs in (1.0, 5.0, 20.0):
