@@ -923,8 +923,8 @@ __device__ __forceinline__ void sort_unit(DSmem& sm, DUnitSmem& du, const DUnitA
     }
   }
   // unit-wide coordinate range: keys are taken relative to its smallest
-  dmin = wave_min(dmin);
-  dmax = wave_max(dmax);
+  dmin = wave_min_u32(dmin);
+  dmax = wave_max_u32(dmax);
   if (lane_id() == 0) {
     atomicMin(&du.red_min, dmin);
     atomicMax(&du.red_max, dmax);
@@ -955,12 +955,18 @@ __device__ __forceinline__ void sort_unit(DSmem& sm, DUnitSmem& du, const DUnitA
   // stage the compacted keys and their counts (consecutive threads take
   // consecutive keys)
   uint32_t* const skey = a.stage_key + slot_base(slot);
-  for (uint32_t ui = tid; ui < nU; ui += DUB) skey[ui] = sm.buf[ui];
   if constexpr (WEIGHTED) {
+    for (uint32_t ui = tid; ui < nU; ui += DUB) skey[ui] = sm.buf[ui];
     weighted_counts<uint32_t, IT>(sm, key, val, n_u, first, a.stage_cnt + slot_base(slot));
-  } else {
+  } else if (tid >= WAVE) {
+    // waves 1.. stage; wave 0 goes on to the look-back and the claim, whose
+    // loads would otherwise wait behind these stores (a wave's memory
+    // operations complete in order)
     uint16_t* const sc16 = a.stage_c16 + slot_base(slot);
-    for (uint32_t ui = tid; ui < nU; ui += DUB) sc16[ui] = (uint16_t)(sm.upos[ui + 1] - sm.upos[ui]);
+    for (uint32_t ui = tid - WAVE; ui < nU; ui += DUB - WAVE) {
+      skey[ui] = sm.buf[ui];
+      sc16[ui] = (uint16_t)(sm.upos[ui + 1] - sm.upos[ui]);
+    }
   }
 }
 
@@ -1186,7 +1192,7 @@ __global__ void __launch_bounds__(DUB, 4) k_d_units(DUnitArgs a) {
       if (tid < WAVE) {
         const uint32_t l = (uint32_t)tid;
         const uint32_t v = n_u > 0 && l < nl ? sm.ucnt[l] : 0u;
-        const uint32_t inc = wave_incl_scan(v);
+        const uint32_t inc = wave_incl_scan_u32(v);
         du.loff[slot][l] = inc - v;
         if (l == WAVE - 1) du.loff[slot][MAXC] = inc;
       }

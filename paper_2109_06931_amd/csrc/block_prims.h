@@ -45,6 +45,31 @@ __device__ inline void wave_incl_scan_u32_n(uint32_t (&v)[N]) {
   for (int k = 0; k < N; ++k) v[k] += (uint32_t)__builtin_amdgcn_update_dpp(0, (int)v[k], 0x143, 0xC, 0xF, false);
 }
 
+// Minimum and maximum over the 64 lanes of a wave for 32-bit values, with the
+// DPP steps of wave_incl_scan_u32: a lane whose source is out of its row, and a
+// row the mask leaves out, keep their own value, which leaves a minimum or
+// maximum unchanged.  Lane 63 ends with the wave's result; every lane gets it.
+// Every lane must be active.
+__device__ inline uint32_t wave_min_u32(uint32_t v) {
+  v = min(v, (uint32_t)__builtin_amdgcn_update_dpp((int)v, (int)v, 0x111, 0xF, 0xF, false));
+  v = min(v, (uint32_t)__builtin_amdgcn_update_dpp((int)v, (int)v, 0x112, 0xF, 0xF, false));
+  v = min(v, (uint32_t)__builtin_amdgcn_update_dpp((int)v, (int)v, 0x114, 0xF, 0xF, false));
+  v = min(v, (uint32_t)__builtin_amdgcn_update_dpp((int)v, (int)v, 0x118, 0xF, 0xF, false));
+  v = min(v, (uint32_t)__builtin_amdgcn_update_dpp((int)v, (int)v, 0x142, 0xA, 0xF, false));
+  v = min(v, (uint32_t)__builtin_amdgcn_update_dpp((int)v, (int)v, 0x143, 0xC, 0xF, false));
+  return (uint32_t)__builtin_amdgcn_readlane((int)v, WAVE - 1);
+}
+
+__device__ inline uint32_t wave_max_u32(uint32_t v) {
+  v = max(v, (uint32_t)__builtin_amdgcn_update_dpp((int)v, (int)v, 0x111, 0xF, 0xF, false));
+  v = max(v, (uint32_t)__builtin_amdgcn_update_dpp((int)v, (int)v, 0x112, 0xF, 0xF, false));
+  v = max(v, (uint32_t)__builtin_amdgcn_update_dpp((int)v, (int)v, 0x114, 0xF, 0xF, false));
+  v = max(v, (uint32_t)__builtin_amdgcn_update_dpp((int)v, (int)v, 0x118, 0xF, 0xF, false));
+  v = max(v, (uint32_t)__builtin_amdgcn_update_dpp((int)v, (int)v, 0x142, 0xA, 0xF, false));
+  v = max(v, (uint32_t)__builtin_amdgcn_update_dpp((int)v, (int)v, 0x143, 0xC, 0xF, false));
+  return (uint32_t)__builtin_amdgcn_readlane((int)v, WAVE - 1);
+}
+
 __device__ inline uint32_t wave_last_u32(uint32_t v) { return (uint32_t)__builtin_amdgcn_readlane((int)v, WAVE - 1); }
 
 template <class T>
@@ -93,8 +118,11 @@ __device__ inline T wave_or(T v) {
 }
 
 // Exclusive scan over the workgroup; returns the thread's exclusive prefix and
-// writes the total to *total.  s_tmp needs BLOCK / WAVE + 1 entries.  Contains
-// barriers: every thread of the block must call it.
+// writes the total to *total.  Each wave scans its lanes and publishes its
+// total in s_tmp (BLOCK / WAVE entries); after one barrier every thread adds
+// the totals of the waves before its own (no serial pass by one thread); a
+// second barrier lets the next call reuse s_tmp.  Contains barriers: every
+// thread of the block must call it.
 template <int BLOCK, class T>
 __device__ inline T block_excl_scan(T v, T* s_tmp, T* total) {
   constexpr int NW = BLOCK / WAVE;
@@ -103,21 +131,17 @@ __device__ inline T block_excl_scan(T v, T* s_tmp, T* total) {
   else inc = wave_incl_scan(v);
   if (lane_id() == WAVE - 1) s_tmp[wave_id()] = inc;
   __syncthreads();
-  if (threadIdx.x == 0) {
-    T run = 0;
+  const int w = wave_id();
+  T before = 0, all = 0;
 #pragma unroll
-    for (int w = 0; w < NW; ++w) {
-      T t = s_tmp[w];
-      s_tmp[w] = run;
-      run += t;
-    }
-    s_tmp[NW] = run;
+  for (int i = 0; i < NW; ++i) {
+    const T t = s_tmp[i];
+    all += t;
+    before += i < w ? t : (T)0;
   }
+  *total = all;
   __syncthreads();
-  T r = s_tmp[wave_id()] + inc - v;
-  *total = s_tmp[NW];
-  __syncthreads();
-  return r;
+  return before + inc - v;
 }
 
 // LSD radix sort of up to BLOCK * ITEMS keys held in registers, 4-bit digits.
