@@ -648,9 +648,8 @@ struct DUnitArgs {
   DInfo* info;
   unsigned long long* status;  // per unit: look-back word
   // per workgroup, two slots of DUT keys (one for the unit being sorted, one
-  // for the unit waiting to be written): key | count << 32 unweighted; the
-  // keys, with their counts as u16 (a unit's count is at most DUT) or, with
-  // weights, as u64
+  // for the unit waiting to be written): the keys as u32, with their counts
+  // as u16 (a unit's count is at most DUT) or, with weights, as u64
   uint32_t* stage_key;
   uint16_t* stage_c16;
   unsigned long long* stage_cnt;
