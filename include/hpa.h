@@ -372,10 +372,14 @@ typedef struct hpa_batch hpa_batch;
 
 /* Attribute many profiles at once.  `samples` holds every profile's records
  * back to back in profile order (device SoA as for hpa_attribute; n is the
- * total, n_ctx is ignored).  Profiles are grouped into rounds of consecutive
- * profiles; in a round the contexts of all profiles are numbered globally and
- * every stage of the attribution runs once for the whole round (each unit of
- * the sort holds contexts of one profile and uses that profile's map).  Each
+ * total, n_ctx is ignored).  Profiles are grouped into rounds; in a round the
+ * contexts of all profiles are numbered globally and every stage of the
+ * attribution runs once for the whole round (each unit of the sort holds
+ * contexts of one profile and uses that profile's map).  When the profiles
+ * share at most 64 maps, with at least two profiles per map on average, each
+ * round holds profiles of one map (their records gathered into round buffers
+ * when they are not adjacent) and runs the dense pipeline when the map has
+ * dense coordinates; otherwise rounds are runs of consecutive profiles.  Each
  * profile's result equals hpa_attribute on its own records, byte for byte.
  * Synchronises `stream` a fixed number of times per round.  Errors: as
  * hpa_attribute (HPA_E_INVAL also when the profiles' counts do not add up to

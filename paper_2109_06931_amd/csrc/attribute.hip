@@ -1796,6 +1796,51 @@ k_rebase(const uint64_t* __restrict__ ctx_off, const uint32_t* __restrict__ cbas
   if (blockIdx.x == 0 && threadIdx.x == 0) first_key[P] = ctx_off[cbase[P]];
 }
 
+// A round of profiles that share one map, gathered: record i of the round is
+// record src[p] + (i - doff[p]) of the batch arrays for the profile p that
+// holds it; its global context, and (when the profiles are not adjacent in
+// the batch arrays, pc_out set) its pc, stall and weight, go to contiguous
+// round arrays.
+__global__ void __launch_bounds__(256)
+k_gather_round(const uint64_t* __restrict__ pc, const uint32_t* __restrict__ ctx, const uint8_t* __restrict__ stall,
+               const uint32_t* __restrict__ weight, uint64_t n, const uint64_t* __restrict__ doff,
+               const uint64_t* __restrict__ src, const uint32_t* __restrict__ cbase, uint32_t P,
+               uint32_t* __restrict__ g, uint64_t* __restrict__ pc_out, uint8_t* __restrict__ st_out,
+               uint32_t* __restrict__ wt_out, PlanInfo* __restrict__ info) {
+  for (uint64_t i = (uint64_t)blockIdx.x * 256 + threadIdx.x; i < n; i += (uint64_t)gridDim.x * 256) {
+    uint32_t lo = 0, hi = P;  // last profile with doff <= i
+    while (hi - lo > 1) {
+      const uint32_t mid = (lo + hi) >> 1;
+      if (doff[mid] <= i) lo = mid;
+      else hi = mid;
+    }
+    const uint64_t j = src[lo] + (i - doff[lo]);
+    const uint32_t c = ctx[j];
+    if (c >= cbase[lo + 1] - cbase[lo]) {
+      atomicOr(&info->err, (uint32_t)ERR_CTX);
+      g[i] = 0;
+    } else {
+      g[i] = cbase[lo] + c;
+    }
+    if (pc_out) {
+      pc_out[i] = pc[j];
+      st_out[i] = stall[j];
+      if (wt_out) wt_out[i] = weight[j];
+    }
+  }
+}
+
+// Keys of the dense pipeline name global contexts: make them local to their
+// profile (the general pipeline writes them local already).
+__global__ void __launch_bounds__(256)
+k_localize_ctx(uint32_t* __restrict__ key_ctx, uint64_t n_keys, const uint32_t* __restrict__ cprof,
+               const uint32_t* __restrict__ cbase) {
+  for (uint64_t k = (uint64_t)blockIdx.x * 256 + threadIdx.x; k < n_keys; k += (uint64_t)gridDim.x * 256) {
+    const uint32_t c = key_ctx[k];
+    key_ctx[k] = c - cbase[cprof[c]];
+  }
+}
+
 }  // namespace
 }  // namespace hpa
 
@@ -1882,7 +1927,121 @@ void run_round(hpa_ctx* ctx, const hpa_profile_desc* pd, const hpa_samples* smp,
   sync_stream(ctx, s);
   const uint32_t ri = (uint32_t)B->rounds.size();
   for (uint32_t i = 0; i < P; ++i)
-    B->prof.push_back(hpa_batch::Prof{ri, pd[r.p0 + i].n_ctx, k0[i], k0[i + 1] - k0[i], (uint64_t)cbase[i] + i});
+    B->prof[r.p0 + i] = hpa_batch::Prof{ri, pd[r.p0 + i].n_ctx, k0[i], k0[i + 1] - k0[i], (uint64_t)cbase[i] + i};
+  B->rounds.push_back(std::move(R));
+  B->info.total_keys += k0[P];
+}
+
+// Batches whose profiles share a few maps are taken map by map: the profiles
+// of one map (in batch order) form rounds of their own, and a round whose map
+// has dense coordinates runs the dense pipeline over the profiles' global
+// contexts (falling back to the general pipeline, as a single call does, when
+// a pc has no dense coordinate); other rounds run the general pipeline.
+// Returns false, and leaves the batch to rounds of consecutive profiles, when
+// the maps are too many for grouping to pay (more than 64, or fewer than two
+// profiles per map).
+bool group_by_map(const hpa_profile_desc* pd, uint32_t n_profiles, std::vector<uint32_t>& order) {
+  std::vector<const hpa_structure_map*> maps;
+  for (uint32_t p = 0; p < n_profiles; ++p) {
+    const hpa_structure_map* m = pd[p].map;
+    if (std::find(maps.begin(), maps.end(), m) == maps.end()) {
+      if (maps.size() == 64) return false;
+      maps.push_back(m);
+    }
+  }
+  if (2 * maps.size() > n_profiles) return false;
+  order.clear();
+  for (const hpa_structure_map* m : maps)
+    for (uint32_t p = 0; p < n_profiles; ++p)
+      if (pd[p].map == m) order.push_back(p);
+  return true;
+}
+
+// One round of profiles `ids` (one map, batch order within it).
+void run_round_grouped(hpa_ctx* ctx, const hpa_profile_desc* pd, const hpa_samples* smp,
+                       const std::vector<uint32_t>& ids, const std::vector<uint64_t>& soff_all, hipStream_t s,
+                       const Knobs& kn, hpa_batch* B) {
+  const uint32_t P = (uint32_t)ids.size();
+  const hpa_structure_map* map = pd[ids[0]].map;
+  std::vector<ProfMap> pm(P);
+  std::vector<uint32_t> cbase(P + 1);
+  std::vector<uint64_t> doff(P + 1), src(P);
+  uint64_t G = 0, n = 0;
+  bool adjacent = true;
+  for (uint32_t i = 0; i < P; ++i) {
+    const uint32_t p = ids[i];
+    cbase[i] = (uint32_t)G;
+    doff[i] = n;
+    src[i] = soff_all[p];
+    if (i > 0 && soff_all[ids[i - 1] + 1] != soff_all[p]) adjacent = false;
+    pm[i].dd = DenseDev{map->win_lo.as<uint64_t>(), map->win_hi.as<uint64_t>(), map->win_d.as<uint64_t>(),
+                        map->scope_of.as<uint32_t>(), map->n_win, map->dense_tz};
+    pm[i].md = MapDev{map->start.as<uint64_t>(), map->end.as<uint64_t>(), map->scope.as<uint32_t>(), map->n_iv};
+    pm[i].ctx_base = (uint32_t)G;
+    pm[i].dense = map->dense ? 1 : 0;
+    G += pd[p].n_ctx;
+    n += pd[p].n_samples;
+  }
+  cbase[P] = (uint32_t)G;
+  doff[P] = n;
+  const uint64_t s0 = soff_all[ids[0]];
+  DBuf d_pm = upload(ctx, pm, s), d_cbase = upload(ctx, cbase, s), d_doff = upload(ctx, doff, s),
+       d_src = upload(ctx, src, s);
+  DBuf d_cprof(ctx, std::max<uint64_t>(G, 1) * 4, s);
+  k_fill_cprof<<<grid_for(G, 256, ctx->n_cu * 8), 256, 0, s>>>(d_cbase.as<uint32_t>(), P, (uint32_t)G,
+                                                               d_cprof.as<uint32_t>());
+  const bool weighted = smp->weight != nullptr;
+  DBuf d_g(ctx, std::max<uint64_t>(n, 1) * 4, s), d_info(ctx, sizeof(PlanInfo), s);
+  DBuf d_pc, d_st, d_wt;
+  if (!adjacent) {
+    d_pc = DBuf(ctx, std::max<uint64_t>(n, 1) * 8, s);
+    d_st = DBuf(ctx, std::max<uint64_t>(n, 1), s);
+    if (weighted) d_wt = DBuf(ctx, std::max<uint64_t>(n, 1) * 4, s);
+  }
+  HPA_HIP(hipMemsetAsync(d_info.p, 0, sizeof(PlanInfo), s));
+  if (n)
+    k_gather_round<<<grid_for(n, 256, ctx->n_cu * 16), 256, 0, s>>>(
+        smp->pc, smp->ctx, smp->stall, smp->weight, n, d_doff.as<uint64_t>(), d_src.as<uint64_t>(),
+        d_cbase.as<uint32_t>(), P, d_g.as<uint32_t>(), adjacent ? nullptr : d_pc.as<uint64_t>(),
+        adjacent ? nullptr : d_st.as<uint8_t>(), adjacent || !weighted ? nullptr : d_wt.as<uint32_t>(),
+        d_info.as<PlanInfo>());
+  HPA_HIP(hipGetLastError());
+  PlanInfo info{};
+  HPA_HIP(hipMemcpyAsync(&info, d_info.p, sizeof(info), hipMemcpyDeviceToHost, s));
+  sync_stream(ctx, s);
+  if (info.err & ERR_CTX) fail(HPA_E_INVAL, "a sample's ctx is not below its profile's n_ctx");
+  hpa_samples rs{adjacent ? smp->pc + s0 : d_pc.as<uint64_t>(), d_g.as<uint32_t>(),
+                 adjacent ? smp->stall + s0 : d_st.as<uint8_t>(),
+                 !weighted ? nullptr : (adjacent ? smp->weight + s0 : d_wt.as<uint32_t>()), n, (uint32_t)G};
+  auto* A = new hpa_attribution();
+  std::unique_ptr<hpa_attribution> hold(A);
+  A->ctx = ctx;
+  A->stream = s;
+  A->map = map;
+  A->n_ctx = (uint32_t)G;
+  if (n > 0 && dense_path_fits(map, &rs) && attribute_dense(ctx, map, &rs, s, A)) {
+    if (A->n_keys)
+      k_localize_ctx<<<grid_for(A->n_keys, 256, ctx->n_cu * 16), 256, 0, s>>>(
+          A->ctx_id.as<uint32_t>(), A->n_keys, d_cprof.as<uint32_t>(), d_cbase.as<uint32_t>());
+    HPA_HIP(hipGetLastError());
+  } else {
+    BatchRun br{d_pm.as<ProfMap>(), d_cprof.as<uint32_t>()};
+    attribute_impl(ctx, map, &br, &rs, s, kn, A);
+  }
+  hpa_batch::Round R;
+  R.a = hold.release();
+  R.rebased = DBuf(ctx, ((uint64_t)G + P) * 8, s);
+  DBuf d_k0(ctx, ((uint64_t)P + 1) * 8, s);
+  k_rebase<<<grid_for(G + P, 256, ctx->n_cu * 8), 256, 0, s>>>(R.a->ctx_offsets.as<uint64_t>(),
+                                                               d_cbase.as<uint32_t>(), P, d_k0.as<uint64_t>(),
+                                                               R.rebased.as<uint64_t>());
+  HPA_HIP(hipGetLastError());
+  std::vector<uint64_t> k0(P + 1);
+  HPA_HIP(hipMemcpyAsync(k0.data(), d_k0.p, (P + 1) * 8, hipMemcpyDeviceToHost, s));
+  sync_stream(ctx, s);
+  const uint32_t ri = (uint32_t)B->rounds.size();
+  for (uint32_t i = 0; i < P; ++i)
+    B->prof[ids[i]] = hpa_batch::Prof{ri, pd[ids[i]].n_ctx, k0[i], k0[i + 1] - k0[i], (uint64_t)cbase[i] + i};
   B->rounds.push_back(std::move(R));
   B->info.total_keys += k0[P];
 }
@@ -1927,6 +2086,7 @@ extern "C" hpa_status hpa_attribute_batched(hpa_ctx* ctx, uint32_t n_profiles, c
     auto* B = new hpa_batch();
     std::unique_ptr<hpa_batch> hold(B);
     B->ctx = ctx;
+    B->prof.resize(n_profiles);
     Knobs kn;
     if (o.merge_rounds <= 3 && opts) kn.merge_rounds = o.merge_rounds;
     if (o.scan_wg_per_cu) kn.scan_wg_per_cu = o.scan_wg_per_cu;
@@ -1966,8 +2126,28 @@ extern "C" hpa_status hpa_attribute_batched(hpa_ctx* ctx, uint32_t n_profiles, c
         ctx->tuned_scan_wg = kn.scan_wg_per_cu;
       }
     }
-    for (const RoundPlan& r : plan) run_round(ctx, pd, smp, r, soff, s, kn, B, true);
-    B->info.n_rounds = (uint32_t)plan.size();
+    std::vector<uint32_t> order;
+    if (group_by_map(pd, n_profiles, order)) {
+      // rounds of one map each, up to `cap` samples and 2^31 contexts
+      std::vector<uint32_t> ids;
+      uint64_t ns = 0, nc = 0;
+      for (uint32_t k = 0; k <= n_profiles; ++k) {
+        const uint32_t p = k < n_profiles ? order[k] : 0u;
+        if (!ids.empty() && (k == n_profiles || pd[p].map != pd[ids[0]].map || ns + pd[p].n_samples > cap ||
+                             nc + pd[p].n_ctx >= 0x7FFFFFFFull)) {
+          run_round_grouped(ctx, pd, smp, ids, soff, s, kn, B);
+          ids.clear();
+          ns = nc = 0;
+        }
+        if (k == n_profiles) break;
+        ids.push_back(p);
+        ns += pd[p].n_samples;
+        nc += pd[p].n_ctx;
+      }
+    } else {
+      for (const RoundPlan& r : plan) run_round(ctx, pd, smp, r, soff, s, kn, B, true);
+    }
+    B->info.n_rounds = (uint32_t)B->rounds.size();
     B->info.merge_rounds = kn.merge_rounds;
     B->info.scan_wg_per_cu = kn.scan_wg_per_cu;
     B->info.autotuned = o.autotune ? 1 : 0;

@@ -120,3 +120,77 @@ def test_batch_rejects_bad_counts(hpa, hctx):
     with pytest.raises(hpa.HpaError) as ei:
         hpa.attribute_batched(hctx, maps, [len(w.pc) for w in ws], [w.n_ctx for w in ws], pc, cx2, st)
     assert ei.value.code == hpa.E_INVAL
+
+
+def _shared_map_profiles(weighted):
+    """Profiles drawn from three program structures, interleaved in the batch:
+    slices of three sample streams (one whose map has no dense coordinates),
+    one slice with pcs off the dense coordinates, one empty profile."""
+    wa = small_config(300, n_samples=200_000, n_ctx=400, weighted=weighted)
+    wb = small_config(301, n_samples=150_000, n_ctx=250, weighted=weighted)
+    wc = _no_dense_profile(232)
+    if weighted:
+        wc.weight = (1 + np.arange(len(wc.pc)) % 5).astype(np.uint32)
+    cuts = [(wa, 0, 50_000), (wb, 0, 40_000), (wc, 0, 12_000), (wa, 50_000, 120_000), (wb, 40_000, 41_000),
+            (wa, 120_000, 200_000), (wc, 12_000, 30_000), (wb, 41_000, 150_000), (wa, 0, 0), (wb, 0, 5)]
+    out = []
+    for k, (w, a, b) in enumerate(cuts):
+        prof = dict(w=w, pc=w.pc[a:b].copy(), ctx=w.ctx[a:b].copy(), stall=w.stall[a:b].copy(),
+                    weight=None if w.weight is None else w.weight[a:b].copy())
+        if k == 5:  # a pc off the dense coordinates: this round takes the general pipeline
+            prof["pc"][100:140] += np.uint64(1 << 50)
+        out.append(prof)
+    return wa, wb, out
+
+
+@pytest.mark.parametrize("weighted, round_cap", [(False, 0), (True, 0), (False, 100_000)])
+def test_batch_grouped_by_shared_maps(hpa, hctx, weighted, round_cap):
+    print(f"case grouped weighted={weighted} round_cap={round_cap}", flush=True)
+    wa, wb, profs = _shared_map_profiles(weighted)
+    ma, mb = hpa.build_structure_map_workload(hctx, wa), hpa.build_structure_map_workload(hctx, wb)
+    mc = hpa.build_structure_map_workload(hctx, profs[2]["w"])
+    maps = [ma if p["w"] is wa else mb if p["w"] is wb else mc for p in profs]
+    d = lambda a, t: torch.from_numpy(np.ascontiguousarray(a).view(t)).cuda()  # noqa: E731
+    pc = d(np.concatenate([p["pc"] for p in profs]).astype(np.uint64), np.int64).view(torch.uint64)
+    cx = d(np.concatenate([p["ctx"] for p in profs]).astype(np.uint32), np.int32).view(torch.uint32)
+    st = torch.from_numpy(np.concatenate([p["stall"] for p in profs]).astype(np.uint8)).cuda()
+    wt = d(np.concatenate([p["weight"] for p in profs]).astype(np.uint32), np.int32).view(torch.uint32) \
+        if weighted else None
+    b = hpa.attribute_batched(hctx, maps, [len(p["pc"]) for p in profs], [p["w"].n_ctx for p in profs], pc, cx,
+                              st, wt, max_round_samples=round_cap)
+    info = b.info()
+    # one map per round: at least one round per map, more under the cap
+    assert info["n_rounds"] >= (5 if round_cap else 3)
+    for i, p in enumerate(profs):
+        got = b.profile(i).numpy()
+        w, n = p["w"], len(p["pc"])
+        if n:
+            dv = lambda a, t: torch.from_numpy(np.ascontiguousarray(a).view(t)).cuda()  # noqa: E731
+            one = hpa.attribute(hctx, maps[i], dv(p["pc"], np.int64).view(torch.uint64),
+                                dv(p["ctx"], np.int32).view(torch.uint32), torch.from_numpy(p["stall"]).cuda(),
+                                None if p["weight"] is None else dv(p["weight"], np.int32).view(torch.uint32),
+                                w.n_ctx).numpy()
+            for f in ["ctx", "pc", "stall", "count", "scope", "ctx_offsets"]:
+                assert np.array_equal(got[f], one[f]), f"profile {i}: {f}"
+        else:
+            assert len(got["ctx"]) == 0 and not got["ctx_offsets"].any()
+        if i in (1, 2, 5, 9):
+            om = oracle.build_map_workload(w)
+            oa = oracle.attribute(om, p["pc"], p["ctx"], p["stall"], p["weight"], w.n_ctx)
+            assert_attribution_equal(got, oa, f"profile {i} vs oracle")
+
+
+def test_batch_grouped_rejects_bad_ctx(hpa, hctx):
+    wa, wb, profs = _shared_map_profiles(False)
+    ma, mb = hpa.build_structure_map_workload(hctx, wa), hpa.build_structure_map_workload(hctx, wb)
+    mc = hpa.build_structure_map_workload(hctx, profs[2]["w"])
+    maps = [ma if p["w"] is wa else mb if p["w"] is wb else mc for p in profs]
+    cx_np = np.concatenate([p["ctx"] for p in profs]).astype(np.uint32)
+    cx_np[len(profs[0]["ctx"]) + 3] = wb.n_ctx  # a record of profile 1 beyond its profile's count
+    pc = torch.from_numpy(np.concatenate([p["pc"] for p in profs]).astype(np.uint64).view(np.int64)).cuda()
+    st = torch.from_numpy(np.concatenate([p["stall"] for p in profs]).astype(np.uint8)).cuda()
+    cx = torch.from_numpy(cx_np.view(np.int32)).cuda().view(torch.uint32)
+    with pytest.raises(hpa.HpaError) as ei:
+        hpa.attribute_batched(hctx, maps, [len(p["pc"]) for p in profs], [p["w"].n_ctx for p in profs],
+                              pc.view(torch.uint64), cx, st)
+    assert ei.value.code == hpa.E_INVAL
