@@ -294,7 +294,7 @@ typedef struct hpa_attribution hpa_attribution;
 /* count[(ctx, pc, stall)] = sum of weights.  Output keys are unique and sorted
  * ascending by (ctx, pc, stall); scope is the innermost scope of pc (or
  * HPA_UNMAPPED); ctx_offsets (n_ctx + 1) is the CSR index of each context's
- * keys.  When the map's code fits a grid of at most 2^22 instruction
+ * keys.  When the map's code fits a grid of at most 2^26 instruction
  * coordinates in at most 64 address windows (the map builds that grid itself)
  * and every sampled PC lies on it, the attribution runs device-driven and
  * synchronises `stream` once, to learn the number of keys; otherwise it

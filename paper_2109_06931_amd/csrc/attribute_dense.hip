@@ -895,10 +895,10 @@ __device__ __forceinline__ void sort_unit(DSmem& sm, DUnitSmem& du, const DUnitA
   for (uint32_t l = 0; l < nl; ++l)
     for (uint32_t p = du.lstart[l] + tid; p < du.lstart[l + 1]; p += DUB) lctx_of[p] = (uint8_t)l;
   __syncthreads();
-  // gather: item i of thread t is record i * DUB + t of the unit, kept packed
-  // as local context << 26 | D << 4 | stall (D < 2^22).  Unweighted records
-  // were fetched into the exchange plane while the previous unit was written;
-  // weighted ones are read from global memory here (coalesced).
+  // gather: item i of thread t is record i * DUB + t of the unit (D << 4 |
+  // stall).  Unweighted records were fetched into the exchange plane while
+  // the previous unit was written; weighted ones are read from global memory
+  // here (coalesced).
   uint32_t key[IT], val[IT];
   uint32_t dmin = 0xFFFFFFFFu, dmax = 0;
   // (the thread index is hidden from the optimiser here, so that the slot
@@ -914,9 +914,9 @@ __device__ __forceinline__ void sort_unit(DSmem& sm, DUnitSmem& du, const DUnitA
     if (j < n_u) {
       uint32_t r = WEIGHTED ? rec[d.s0 + j] : sm.buf[j];
       if (r == FAR_REC) r = 0;  // the call is redone by the general path
-      key[i] = ((uint32_t)lctx_of[j] << 26) | (r & 0x3FFFFFFu);
+      key[i] = r;
       if constexpr (WEIGHTED) val[i] = rw[d.s0 + j];
-      const uint32_t D = (r >> 4) & 0x3FFFFFu;
+      const uint32_t D = r >> 4;
       dmin = min(dmin, D);
       dmax = max(dmax, D);
     }
@@ -937,11 +937,13 @@ __device__ __forceinline__ void sort_unit(DSmem& sm, DUnitSmem& du, const DUnitA
   // the plan keeps local contexts few enough that keys fit 31 bits
   if (kbits > 31 && tid == 0) atomicOr(&a.info->err, DERR_WIDE);
   const uint32_t empty = 1u << min(kbits, 31);
+  // keys: local context, coordinate offset, stall (the local context from
+  // the LDS table, still intact: the sort has not begun)
 #pragma unroll
   for (int i = 0; i < IT; ++i) {
     const uint32_t j = (uint32_t)i * DUB + tq;
     const uint32_t v = key[i];
-    key[i] = j < n_u ? ((v >> 26) << (pcb + 4)) | ((((v >> 4) & 0x3FFFFFu) - dmin) << 4) | (v & 15u) : empty;
+    key[i] = j < n_u ? ((uint32_t)lctx_of[j] << (pcb + 4)) | (((v >> 4) - dmin) << 4) | (v & 15u) : empty;
   }
   // empty slots sort after every key: kbits + 1 bits, no per-slot test
   if constexpr (WEIGHTED)
@@ -1221,8 +1223,8 @@ __global__ void __launch_bounds__(DUB, 4) k_d_units(DUnitArgs a) {
 bool dense_path_fits(const hpa_structure_map* map, const hpa_samples* smp) {
   if (!map->dense || map->n_win == 0 || map->n_win > DENSE_MAX_WIN) return false;
   if (smp->n >= (1ull << 32) - 1 || smp->n_ctx >= (1u << 31)) return false;
-  // records hold a coordinate in 22 bits
-  return map->n_dense <= (1ull << 22);
+  // records hold a coordinate in 26 bits (a record below FAR_REC)
+  return map->n_dense <= (1ull << 26);
 }
 
 // Returns false (nothing written, no error) when a sample's pc has no dense

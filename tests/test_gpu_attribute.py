@@ -391,3 +391,42 @@ def test_attribute_synchronises_once(hpa, hctx):
     a = hpa.attribute(hctx, m, pc, cx, st, wt, w.n_ctx)
     assert hctx.sync_count() - n0 > 1
     assert_attribution_equal(a.numpy(), oracle.attribute(om, w.pc, w.ctx, w.stall, w.weight, w.n_ctx), "far")
+
+
+def _wide_coordinates(seed, weighted):
+    """400 functions 256 KiB apart (one window) on a 16-byte grid: about
+    6.7M dense coordinates, more than 2^22."""
+    r = np.random.default_rng(seed)
+    n_f, n = 400, 300_000
+    starts = np.uint64(0x5000_0000) + (np.arange(n_f, dtype=np.uint64) << np.uint64(18))
+    w = tiny_random_case(seed, n_samples=10, n_ctx=4)
+    w.scope_start, w.scope_end = starts, starts + np.uint64(272)
+    w.scope_id = np.arange(n_f, dtype=np.uint32)
+    w.scope_kind = np.zeros(n_f, dtype=np.uint32)
+    w.line_start = w.line_end = w.line_file = w.line_line = None
+    w.n_scope_ids = n_f
+    f = np.minimum(r.zipf(1.3, n) - 1, n_f - 1).astype(np.uint64)
+    w.pc = starts[f] + (r.integers(0, 17, n).astype(np.uint64) << np.uint64(4))
+    n_ctx = 300
+    w.ctx_parent = np.full(n_ctx, 0xFFFFFFFF, dtype=np.uint32)
+    w.ctx_entry = np.full(n_ctx, -1, dtype=np.int32)
+    w.ctx = np.repeat(r.integers(0, n_ctx, n // 500), 500).astype(np.uint32)
+    w.stall = r.integers(0, 16, n).astype(np.uint8)
+    w.weight = (1 + r.integers(0, 9, n)).astype(np.uint32) if weighted else None
+    return w
+
+
+@pytest.mark.parametrize("weighted", [False, True])
+def test_attribute_wide_coordinates(hpa, hctx, weighted):
+    """Over 2^22 dense coordinates (records hold 26 bits): the dense pipeline,
+    with fewer local contexts per unit so that keys fit 31 bits."""
+    print(f"case wide coordinates weighted={weighted}", flush=True)
+    w = _wide_coordinates(40 + weighted, weighted)
+    m = hpa.build_structure_map_workload(hctx, w)
+    pc, cx, st, wt = hpa.samples_to_device(w)
+    torch.cuda.synchronize()
+    n0 = hctx.sync_count()
+    a = hpa.attribute(hctx, m, pc, cx, st, wt, w.n_ctx)
+    assert hctx.sync_count() - n0 == 1  # the dense pipeline
+    om = oracle.build_map_workload(w)
+    assert_attribution_equal(a.numpy(), oracle.attribute(om, w.pc, w.ctx, w.stall, w.weight, w.n_ctx), "wide")
