@@ -137,7 +137,7 @@ def _shared_map_profiles(weighted):
     for k, (w, a, b) in enumerate(cuts):
         prof = dict(w=w, pc=w.pc[a:b].copy(), ctx=w.ctx[a:b].copy(), stall=w.stall[a:b].copy(),
                     weight=None if w.weight is None else w.weight[a:b].copy())
-        if k == 5:  # a pc off the dense coordinates: this round takes the general pipeline
+        if k == 5:  # a pc off the dense coordinates: its batch round takes the general pipeline
             prof["pc"][100:140] += np.uint64(1 << 50)
         out.append(prof)
     return wa, wb, out
