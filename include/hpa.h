@@ -68,7 +68,7 @@ typedef enum {
   HPA_E_NOMEM = -5,       /* the allocator returned NULL */
   HPA_E_BUDGET = -6,      /* calling context tree larger than the caller's node budget */
   HPA_E_DEVICE = -7,      /* a HIP runtime call failed */
-  HPA_E_UNSUPPORTED = -8  /* valid input outside what this build handles (message says what) */
+  HPA_E_UNSUPPORTED = -8  /* valid input outside what the library as compiled handles (message says what) */
 } hpa_status;
 
 #define HPA_UNMAPPED 0xFFFFFFFFu           /* no scope / no interval / no parent */
