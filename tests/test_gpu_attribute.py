@@ -430,3 +430,30 @@ def test_attribute_wide_coordinates(hpa, hctx, weighted):
     assert hctx.sync_count() - n0 == 1  # the dense pipeline
     om = oracle.build_map_workload(w)
     assert_attribution_equal(a.numpy(), oracle.attribute(om, w.pc, w.ctx, w.stall, w.weight, w.n_ctx), "wide")
+
+
+@pytest.mark.parametrize("n", [1, 2, 3, 4, 5, 63, 255, 256, 257, 1023, 1025, 4099])
+def test_attribute_ragged_sizes(hpa, hctx, n):
+    """Sample counts around the lane groups (4 samples) and wave steps (256
+    samples) of the dense pipeline's histogram and scatter, from aligned
+    arrays (vector loads) and from arrays one element into a larger buffer
+    (scalar loads)."""
+    print(f"case ragged n={n}", flush=True)
+    w = tiny_random_case(50 + n % 7, n_samples=n, n_ctx=3, weighted=n % 2 == 1)
+    m = hpa.build_structure_map_workload(hctx, w)
+    om = oracle.build_map_workload(w)
+    oa = oracle.attribute(om, w.pc, w.ctx, w.stall, w.weight, w.n_ctx)
+    pc, cx, st, wt = hpa.samples_to_device(w)
+    a = hpa.attribute(hctx, m, pc, cx, st, wt, w.n_ctx)
+    assert_attribution_equal(a.numpy(), oa, f"ragged{n} aligned")
+
+    def shifted(t):
+        buf = torch.empty(t.numel() + 1, dtype=t.dtype, device=t.device)
+        buf[1:] = t
+        return buf[1:]
+
+    p1 = shifted(pc.view(torch.int64)).view(torch.uint64)
+    c1 = shifted(cx.view(torch.int32)).view(torch.uint32)
+    w1 = None if wt is None else shifted(wt.view(torch.int32)).view(torch.uint32)
+    a = hpa.attribute(hctx, m, p1, c1, shifted(st), w1, w.n_ctx)
+    assert_attribution_equal(a.numpy(), oa, f"ragged{n} unaligned")
