@@ -143,9 +143,10 @@ def _shared_map_profiles(weighted):
     return wa, wb, out
 
 
-@pytest.mark.parametrize("weighted, round_cap", [(False, 0), (True, 0), (False, 100_000)])
-def test_batch_grouped_by_shared_maps(hpa, hctx, weighted, round_cap):
-    print(f"case grouped weighted={weighted} round_cap={round_cap}", flush=True)
+@pytest.mark.parametrize("weighted, round_cap, autotune", [(False, 0, False), (True, 0, False),
+                                                           (False, 100_000, False), (True, 100_000, True)])
+def test_batch_grouped_by_shared_maps(hpa, hctx, weighted, round_cap, autotune):
+    print(f"case grouped weighted={weighted} round_cap={round_cap} autotune={autotune}", flush=True)
     wa, wb, profs = _shared_map_profiles(weighted)
     ma, mb = hpa.build_structure_map_workload(hctx, wa), hpa.build_structure_map_workload(hctx, wb)
     mc = hpa.build_structure_map_workload(hctx, profs[2]["w"])
@@ -157,7 +158,7 @@ def test_batch_grouped_by_shared_maps(hpa, hctx, weighted, round_cap):
     wt = d(np.concatenate([p["weight"] for p in profs]).astype(np.uint32), np.int32).view(torch.uint32) \
         if weighted else None
     b = hpa.attribute_batched(hctx, maps, [len(p["pc"]) for p in profs], [p["w"].n_ctx for p in profs], pc, cx,
-                              st, wt, max_round_samples=round_cap)
+                              st, wt, max_round_samples=round_cap, autotune=autotune)
     info = b.info()
     # one map per round: at least one round per map, more under the cap
     assert info["n_rounds"] >= (5 if round_cap else 3)
