@@ -1796,38 +1796,42 @@ k_rebase(const uint64_t* __restrict__ ctx_off, const uint32_t* __restrict__ cbas
   if (blockIdx.x == 0 && threadIdx.x == 0) first_key[P] = ctx_off[cbase[P]];
 }
 
-// A round of profiles that share one map, gathered: record i of the round is
-// record src[p] + (i - doff[p]) of the batch arrays for the profile p that
-// holds it; its global context, and (when the profiles are not adjacent in
-// the batch arrays, pc_out set) its pc, stall and weight, go to contiguous
-// round arrays.
+// A round of profiles that share one map, gathered: the round's records are
+// cut into chunks of at most GATHER_CHUNK records of one profile each (chunk
+// k: profile chunk_prof[k], round records [chunk_start[k], chunk_start[k+1])),
+// and record i of profile p is record src[p] + (i - doff[p]) of the batch
+// arrays.  Its global context, and (when the profiles are not adjacent in the
+// batch arrays, pc_out set) its pc, stall and weight, go to contiguous round
+// arrays.  One workgroup per chunk at a time, so no record searches for its
+// profile.
+constexpr uint32_t GATHER_CHUNK = 1u << 16;
+
 __global__ void __launch_bounds__(256)
 k_gather_round(const uint64_t* __restrict__ pc, const uint32_t* __restrict__ ctx, const uint8_t* __restrict__ stall,
-               const uint32_t* __restrict__ weight, uint64_t n, const uint64_t* __restrict__ doff,
-               const uint64_t* __restrict__ src, const uint32_t* __restrict__ cbase, uint32_t P,
-               uint32_t* __restrict__ g, uint64_t* __restrict__ pc_out, uint8_t* __restrict__ st_out,
-               uint32_t* __restrict__ wt_out, PlanInfo* __restrict__ info) {
-  for (uint64_t i = (uint64_t)blockIdx.x * 256 + threadIdx.x; i < n; i += (uint64_t)gridDim.x * 256) {
-    uint32_t lo = 0, hi = P;  // last profile with doff <= i
-    while (hi - lo > 1) {
-      const uint32_t mid = (lo + hi) >> 1;
-      if (doff[mid] <= i) lo = mid;
-      else hi = mid;
-    }
-    const uint64_t j = src[lo] + (i - doff[lo]);
-    const uint32_t c = ctx[j];
-    if (c >= cbase[lo + 1] - cbase[lo]) {
-      atomicOr(&info->err, (uint32_t)ERR_CTX);
-      g[i] = 0;
-    } else {
-      g[i] = cbase[lo] + c;
-    }
-    if (pc_out) {
-      pc_out[i] = pc[j];
-      st_out[i] = stall[j];
-      if (wt_out) wt_out[i] = weight[j];
+               const uint32_t* __restrict__ weight, const uint64_t* __restrict__ chunk_start,
+               const uint32_t* __restrict__ chunk_prof, uint32_t n_chunks, const uint64_t* __restrict__ doff,
+               const uint64_t* __restrict__ src, const uint32_t* __restrict__ cbase, uint32_t* __restrict__ g,
+               uint64_t* __restrict__ pc_out, uint8_t* __restrict__ st_out, uint32_t* __restrict__ wt_out,
+               PlanInfo* __restrict__ info) {
+  bool bad = false;
+  for (uint32_t k = blockIdx.x; k < n_chunks; k += gridDim.x) {
+    const uint32_t p = chunk_prof[k];
+    const uint64_t i0 = chunk_start[k], i1 = chunk_start[k + 1];
+    const uint64_t shift = src[p] - doff[p];  // batch index = round index + shift
+    const uint32_t base = cbase[p], nc = cbase[p + 1] - base;
+    for (uint64_t i = i0 + threadIdx.x; i < i1; i += 256) {
+      const uint64_t j = i + shift;
+      const uint32_t c = ctx[j];
+      bad |= c >= nc;
+      g[i] = c < nc ? base + c : 0u;
+      if (pc_out) {
+        pc_out[i] = pc[j];
+        st_out[i] = stall[j];
+        if (wt_out) wt_out[i] = weight[j];
+      }
     }
   }
+  if (__any(bad) && (threadIdx.x & (WAVE - 1)) == 0) atomicOr(&info->err, (uint32_t)ERR_CTX);
 }
 
 // Keys of the dense pipeline name global contexts: make them local to their
@@ -1985,8 +1989,19 @@ void run_round_grouped(hpa_ctx* ctx, const hpa_profile_desc* pd, const hpa_sampl
   cbase[P] = (uint32_t)G;
   doff[P] = n;
   const uint64_t s0 = soff_all[ids[0]];
+  // chunks of one profile each for the gather
+  std::vector<uint64_t> chunk_start;
+  std::vector<uint32_t> chunk_prof;
+  for (uint32_t i = 0; i < P; ++i)
+    for (uint64_t a = doff[i]; a < doff[i + 1]; a += GATHER_CHUNK) {
+      chunk_start.push_back(a);
+      chunk_prof.push_back(i);
+    }
+  const uint32_t n_chunks = (uint32_t)chunk_prof.size();
+  chunk_start.push_back(n);
+  if (chunk_prof.empty()) chunk_prof.push_back(0);
   DBuf d_pm = upload(ctx, pm, s), d_cbase = upload(ctx, cbase, s), d_doff = upload(ctx, doff, s),
-       d_src = upload(ctx, src, s);
+       d_src = upload(ctx, src, s), d_cstart = upload(ctx, chunk_start, s), d_cprof_of = upload(ctx, chunk_prof, s);
   DBuf d_cprof(ctx, std::max<uint64_t>(G, 1) * 4, s);
   k_fill_cprof<<<grid_for(G, 256, ctx->n_cu * 8), 256, 0, s>>>(d_cbase.as<uint32_t>(), P, (uint32_t)G,
                                                                d_cprof.as<uint32_t>());
@@ -1999,12 +2014,12 @@ void run_round_grouped(hpa_ctx* ctx, const hpa_profile_desc* pd, const hpa_sampl
     if (weighted) d_wt = DBuf(ctx, std::max<uint64_t>(n, 1) * 4, s);
   }
   HPA_HIP(hipMemsetAsync(d_info.p, 0, sizeof(PlanInfo), s));
-  if (n)
-    k_gather_round<<<grid_for(n, 256, ctx->n_cu * 16), 256, 0, s>>>(
-        smp->pc, smp->ctx, smp->stall, smp->weight, n, d_doff.as<uint64_t>(), d_src.as<uint64_t>(),
-        d_cbase.as<uint32_t>(), P, d_g.as<uint32_t>(), adjacent ? nullptr : d_pc.as<uint64_t>(),
-        adjacent ? nullptr : d_st.as<uint8_t>(), adjacent || !weighted ? nullptr : d_wt.as<uint32_t>(),
-        d_info.as<PlanInfo>());
+  if (n_chunks)
+    k_gather_round<<<std::min<uint32_t>(n_chunks, ctx->n_cu * 8), 256, 0, s>>>(
+        smp->pc, smp->ctx, smp->stall, smp->weight, d_cstart.as<uint64_t>(), d_cprof_of.as<uint32_t>(), n_chunks,
+        d_doff.as<uint64_t>(), d_src.as<uint64_t>(), d_cbase.as<uint32_t>(), d_g.as<uint32_t>(),
+        adjacent ? nullptr : d_pc.as<uint64_t>(), adjacent ? nullptr : d_st.as<uint8_t>(),
+        adjacent || !weighted ? nullptr : d_wt.as<uint32_t>(), d_info.as<PlanInfo>());
   HPA_HIP(hipGetLastError());
   PlanInfo info{};
   HPA_HIP(hipMemcpyAsync(&info, d_info.p, sizeof(info), hipMemcpyDeviceToHost, s));
