@@ -1961,6 +1961,14 @@ bool group_by_map(const hpa_profile_desc* pd, uint32_t n_profiles, std::vector<u
   return true;
 }
 
+// A table inside a shared device buffer.
+struct TabView {
+  const DBuf* b;
+  size_t off;
+  template <class T>
+  T* as() const { return reinterpret_cast<T*>(static_cast<unsigned char*>(b->p) + off); }
+};
+
 // One round of profiles `ids` (one map, batch order within it).
 void run_round_grouped(hpa_ctx* ctx, const hpa_profile_desc* pd, const hpa_samples* smp,
                        const std::vector<uint32_t>& ids, const std::vector<uint64_t>& soff_all, hipStream_t s,
@@ -2000,8 +2008,24 @@ void run_round_grouped(hpa_ctx* ctx, const hpa_profile_desc* pd, const hpa_sampl
   const uint32_t n_chunks = (uint32_t)chunk_prof.size();
   chunk_start.push_back(n);
   if (chunk_prof.empty()) chunk_prof.push_back(0);
-  DBuf d_pm = upload(ctx, pm, s), d_cbase = upload(ctx, cbase, s), d_doff = upload(ctx, doff, s),
-       d_src = upload(ctx, src, s), d_cstart = upload(ctx, chunk_start, s), d_cprof_of = upload(ctx, chunk_prof, s);
+  // the round's tables in one upload (one synchronisation), each at a
+  // 256-byte aligned offset
+  std::vector<unsigned char> tab;
+  auto place = [&](const void* p, size_t bytes) {
+    const size_t off = (tab.size() + 255) & ~(size_t)255;
+    tab.resize(off + bytes);
+    if (bytes) std::memcpy(tab.data() + off, p, bytes);
+    return off;
+  };
+  const size_t o_pm = place(pm.data(), pm.size() * sizeof(ProfMap));
+  const size_t o_cbase = place(cbase.data(), cbase.size() * 4);
+  const size_t o_doff = place(doff.data(), doff.size() * 8);
+  const size_t o_src = place(src.data(), src.size() * 8);
+  const size_t o_cstart = place(chunk_start.data(), chunk_start.size() * 8);
+  const size_t o_cprof = place(chunk_prof.data(), chunk_prof.size() * 4);
+  DBuf d_tab = upload(ctx, tab, s);
+  const TabView d_pm{&d_tab, o_pm}, d_cbase{&d_tab, o_cbase}, d_doff{&d_tab, o_doff}, d_src{&d_tab, o_src},
+      d_cstart{&d_tab, o_cstart}, d_cprof_of{&d_tab, o_cprof};
   DBuf d_cprof(ctx, std::max<uint64_t>(G, 1) * 4, s);
   k_fill_cprof<<<grid_for(G, 256, ctx->n_cu * 8), 256, 0, s>>>(d_cbase.as<uint32_t>(), P, (uint32_t)G,
                                                                d_cprof.as<uint32_t>());
